@@ -1,0 +1,376 @@
+"""Pins the CPU oracle to what the paper and the mathematics fix.
+
+None of these checks re-runs the oracle's own formulas: they compare it with
+values printed in the paper (worked example, Section 2.1 / Section 3), with
+the example's own, differently written coding function, with brute-force
+enumerations of the stated properties (C and D inverse, precursor sets of the
+b-unique form, x stays in I, last-in-first-out, encoder/decoder lockstep), with
+an independent construction of the interleaved stream (Section 4's
+instrumented-decoder multiplexer), and with the entropy bound on the size.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+# --------------------------------------------------------- worked example --
+
+def example_C(s, x):
+    """The example coding function exactly as Section 2.1 prints it."""
+    return 4 * x if s == 0 else 4 * (x // 3) + (x % 3) + 1
+
+
+def example_D(x):
+    """The example decoding function exactly as Section 2.1 prints it."""
+    return (0, x // 4) if x % 4 == 0 else (1, 3 * (x // 4) + (x % 4) - 1)
+
+
+def test_example_C_and_D_equal_paper_formulas(golden_example):
+    f = golden_example["freq"]
+    for x in range(0, 3000):
+        assert oracle.C(f, 2, 0, x) == example_C(0, x)
+        assert oracle.C(f, 2, 1, x) == example_C(1, x)
+        assert oracle.D(f, 2, x) == example_D(x)
+
+
+def test_example_precursor_sets_match_paper(golden_example):
+    f = golden_example["freq"]
+    L = golden_example["L"][0]
+    b = golden_example["radix"][0]
+    for s, key in ((0, "I_a"), (1, "I_b")):
+        # C(s,x) >= x, so no x >= bL can land in I: scanning [0, bL) is complete.
+        pre = [x for x in range(0, b * L) if L <= oracle.C(f, 2, s, x) < b * L]
+        assert pre == golden_example[key]
+
+
+def test_example_decoder_passes_printed_state(golden_example):
+    f = golden_example["freq"]
+    msg = golden_example["message"]
+    L, b = golden_example["L"][0], golden_example["radix"][0]
+    l, r = L.bit_length() - 1, b.bit_length() - 1
+    states, digits, _ = oracle.encode_digits(f, 2, r, l, 1, msg)
+    out, trace = oracle.decode_digits(f, 2, r, l, 1, states, digits, len(msg), trace=True)
+    assert list(out) == msg
+    first_a = msg.index(0)
+    assert int(trace[first_a]) == golden_example["state_after_first_a"][0]
+    assert all(L <= int(x) < b * L for x in trace)
+
+
+def test_example_encoder_decoder_lockstep(golden_example):
+    """Decoder state after symbol i equals the encoder state after it coded
+    symbol i+1 (the encoder runs backwards); the last one is the start L."""
+    f = golden_example["freq"]
+    msg = golden_example["message"]
+    states, digits, etr = oracle.encode_digits(f, 2, 1, 4, 1, msg, trace=True)
+    _, dtr = oracle.decode_digits(f, 2, 1, 4, 1, states, digits, len(msg), trace=True)
+    assert int(states[0]) == int(etr[0])
+    for i in range(len(msg) - 1):
+        assert dtr[i] == etr[i + 1]
+    assert int(dtr[-1]) == 16
+
+
+def test_example_against_scalar_algorithm_with_paper_functions(golden_example):
+    """Algorithm 1 run with the example's printed C and D (not the oracle's
+    general rANS) gives the same stream, final state and decode."""
+    msg = golden_example["message"]
+    L, b = 16, 2
+    x, stream = L, []
+    for s in reversed(msg):
+        while not (L <= example_C(s, x) < b * L):
+            stream.insert(0, x % b)
+            x //= b
+        x = example_C(s, x)
+    states, digits, _ = oracle.encode_digits(golden_example["freq"], 2, 1, 4, 1, msg)
+    assert int(states[0]) == x
+    assert list(digits) == stream
+
+
+# ------------------------------------------------------------ brute force --
+
+def random_models(seed, count=24):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        k = int(rng.integers(2, 5))
+        M = 1 << k
+        n = int(rng.integers(2, min(M, 4) + 1))
+        cuts = np.sort(rng.choice(np.arange(1, M), n - 1, replace=False))
+        f = np.diff(np.concatenate([[0], cuts, [M]])).astype(np.uint32)
+        l = k + int(rng.integers(0, 3))
+        r = int(rng.integers(1, 4))
+        yield f, k, l, r
+
+
+def test_C_D_are_inverse_bruteforce():
+    for f, k, l, r in random_models(1):
+        b, L = 1 << r, 1 << l
+        for x in range(1, 4 * b * L):
+            s, xp = oracle.D(f, k, x)
+            assert f[s] > 0
+            assert oracle.C(f, k, s, xp) == x
+        for s in range(len(f)):
+            for x in range(0, 2 * b * L):
+                assert oracle.D(f, k, oracle.C(f, k, s, x)) == (s, x)
+
+
+def test_precursor_sets_are_b_unique_bruteforce():
+    """I_s = {x : C(s,x) in I} has the form {m, ..., bm-1}, m >= 1."""
+    for f, k, l, r in random_models(2):
+        b, L = 1 << r, 1 << l
+        for s in range(len(f)):
+            pre = [x for x in range(0, b * L) if L <= oracle.C(f, k, s, x) < b * L]
+            m = pre[0]
+            assert m >= 1
+            assert pre == list(range(m, b * m))
+
+
+def test_lifo_property():
+    rng = np.random.default_rng(3)
+    for f, k, l, r in random_models(3, 8):
+        for _ in range(50):
+            a, c = rng.integers(0, len(f), 2)
+            x = int(rng.integers(0, 1000))
+            inner = oracle.C(f, k, int(a), x)
+            assert oracle.D(f, k, oracle.C(f, k, int(c), inner)) == (int(c), inner)
+
+
+def enumerate_messages(n_alpha, max_len):
+    for length in range(0, max_len + 1):
+        yield from itertools.product(range(n_alpha), repeat=length)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_exhaustive_roundtrip_and_injectivity(N):
+    cases = [([1, 3], 2, 4, 1), ([2, 1, 1], 2, 2, 2), ([1, 2, 5], 3, 3, 3), ([3, 5], 3, 4, 2)]
+    for f, k, l, r in cases:
+        b, L = 1 << r, 1 << l
+        seen = {}
+        for msg in enumerate_messages(len(f), 6):
+            states, digits, etr = oracle.encode_digits(f, k, r, l, N, list(msg), trace=True)
+            out, dtr = oracle.decode_digits(f, k, r, l, N, states, digits, len(msg),
+                                            trace=True)
+            assert tuple(int(v) for v in out) == msg
+            assert all(L <= int(x) < b * L for x in etr)
+            assert all(L <= int(x) < b * L for x in dtr)
+            key = (len(msg), tuple(int(v) for v in states), tuple(int(v) for v in digits))
+            assert key not in seen, (msg, seen.get(key))
+            seen[key] = msg
+
+
+def test_lockstep_per_coder():
+    """Coder j's decoder state after symbol i equals its encoder state after
+    symbol i+N (or L when there is none)."""
+    rng = np.random.default_rng(4)
+    f, k, l, r, N = [5, 7, 3, 1], 4, 8, 4, 3
+    msg = rng.integers(0, 4, 200).tolist()
+    st, dg, etr = oracle.encode_digits(f, k, r, l, N, msg, trace=True)
+    _, dtr = oracle.decode_digits(f, k, r, l, N, st, dg, len(msg), trace=True)
+    for i in range(len(msg)):
+        want = int(etr[i + N]) if i + N < len(msg) else 1 << l
+        assert int(dtr[i]) == want
+
+
+# ----------------------------------------------------------- interleaving --
+
+def instrumented_mux(f, k, r, l, N, msg):
+    """Section 4's construction: code each coder's subsequence into its own
+    stream with a single-coder encoder, then run the decoders in the
+    interleaved order, appending every digit read to the shared stream."""
+    b, L = 1 << r, 1 << l
+    lanes = []
+    for j in range(N):
+        sub = msg[j::N]
+        st, dg, _ = oracle.encode_digits(f, k, r, l, 1, sub)
+        lanes.append([int(st[0]), [int(d) for d in dg], 0])
+    mux = []
+    for i, s in enumerate(msg):
+        lane = lanes[i % N]
+        got, x = oracle.D(f, k, lane[0])
+        assert got == s
+        while x < L:
+            d = lane[1][lane[2]]
+            lane[2] += 1
+            mux.append(d)
+            x = b * x + d
+        lane[0] = x
+    return [ln_[0] for ln_ in lanes], mux
+
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_interleaved_stream_equals_instrumented_mux(N):
+    rng = np.random.default_rng(10 + N)
+    for f, k, l, r in [([1, 3], 2, 4, 1), ([9, 1, 4, 2], 4, 6, 3), ([200, 40, 16], 8, 16, 16),
+                       ([100, 50, 106], 8, 23, 8)]:
+        msg = rng.integers(0, len(f), 301).tolist()
+        st, dg, _ = oracle.encode_digits(f, k, r, l, N, msg)
+        final_states, mux = instrumented_mux(f, k, r, l, N, msg)
+        assert [int(v) for v in dg] == mux
+        # after the instrumented decode every coder is back at L
+        assert final_states == [1 << l] * N
+        # the coders' initial decoder states are the single-coder final states
+        for j in range(N):
+            st1, _, _ = oracle.encode_digits(f, k, r, l, 1, msg[j::N])
+            assert int(st[j]) == int(st1[0])
+
+
+def test_wrong_interleave_or_order_fails_end_check():
+    rng = np.random.default_rng(5)
+    f, k, l, r = [30, 20, 14], 6, 16, 16
+    msg = rng.integers(0, 3, 999).tolist()
+    st, dg, _ = oracle.encode_digits(f, k, r, l, 4, msg)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.decode_digits(f, k, r, l, 2, st[:2], dg, len(msg))
+    assert e.value.code == oracle.ECORRUPT
+    with pytest.raises(oracle.OracleError):
+        oracle.decode_digits(f, k, r, l, 4, st[::-1].copy(), dg, len(msg))
+
+
+def test_single_step_rule_and_order_independence_when_b_ge_M():
+    """With b >= M no symbol needs more than one digit, and depth-first and
+    breadth-first streams coincide (Section 5)."""
+    rng = np.random.default_rng(6)
+    for f, k, l, r in [([100, 50, 106], 8, 16, 8), ([1000, 3000, 96], 12, 16, 16)]:
+        for N in (1, 4, 7, 64):
+            msg = rng.integers(0, 3, 777).tolist()
+            s1, d1, _ = oracle.encode_digits(f, k, r, l, N, msg, order="df")
+            s2, d2, _ = oracle.encode_digits(f, k, r, l, N, msg, order="bf")
+            assert (s1 == s2).all() and (d1 == d2).all()
+            assert len(d1) <= len(msg)
+            out = oracle.decode_digits(f, k, r, l, N, s2, d2, len(msg), order="df")
+            assert list(out) == msg
+
+
+def test_depth_first_and_breadth_first_differ_when_b_lt_M():
+    rng = np.random.default_rng(7)
+    f, k, l, r, N = [1, 2, 13], 4, 8, 1, 4
+    differ = 0
+    for _ in range(20):
+        msg = rng.integers(0, 3, 64).tolist()
+        s1, d1, _ = oracle.encode_digits(f, k, r, l, N, msg, order="df")
+        s2, d2, _ = oracle.encode_digits(f, k, r, l, N, msg, order="bf")
+        assert (s1 == s2).all()               # states do not depend on the layout
+        assert sorted(d1) == sorted(d2)        # same digits, different order
+        assert list(oracle.decode_digits(f, k, r, l, N, s2, d2, 64, order="bf")) == msg
+        if list(d1) != list(d2):
+            differ += 1
+    assert differ > 0
+
+
+# ------------------------------------------------------------------ sizes --
+
+def test_size_close_to_cross_entropy():
+    """Coding s grows the state by about M/f_s (Section 2.1), so the payload
+    is close to sum_s c_s log2(M/f_s) bits."""
+    import datagen
+    rng = np.random.Generator(np.random.PCG64(11))
+    for s_exp, k, r, l, N in [(1.1, 12, 16, 16, 4), (0.8, 14, 8, 23, 64), (1.5, 11, 16, 16, 32)]:
+        p = datagen.zipf_probs(256, s_exp)
+        syms = datagen.sample(p, 200_000, rng)
+        f = oracle.quantize(datagen.counts(syms, 256), k)
+        st, dg, _ = oracle.encode_digits(f, k, r, l, N, syms)
+        payload_bits = len(dg) * r
+        c = datagen.counts(syms, 256).astype(np.float64)
+        nz = c > 0
+        hx = float((c[nz] * np.log2((1 << k) / f[nz].astype(np.float64))).sum())
+        assert abs(payload_bits - hx) <= 0.01 * len(syms) + 32 * N + r * N
+
+
+# -------------------------------------------------------------- quantiser --
+
+def test_quantizer_properties():
+    rng = np.random.default_rng(8)
+    for trial in range(300):
+        n = int(rng.integers(1, 300))
+        k = int(rng.integers(max(1, int(np.ceil(np.log2(n)))), 17))
+        c = rng.integers(0, 1000, n).astype(np.uint64)
+        if trial % 3 == 0:
+            c[rng.random(n) < 0.5] = 0
+        if c.sum() == 0:
+            c[0] = 1
+        f = oracle.quantize(c, k)
+        M = 1 << k
+        assert int(f.sum()) == M
+        assert ((f > 0) == (c > 0)).all()
+        exact = c.astype(np.float64) * M / float(c.sum())
+        if not ((exact < 1) & (c > 0)).any():
+            assert (np.abs(f - exact) < 1).all()
+
+
+def test_quantizer_identity_and_errors():
+    f0 = np.array([1, 3, 0, 12], dtype=np.uint64)
+    assert list(oracle.quantize(f0, 4)) == [1, 3, 0, 12]
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.quantize(np.ones(5, dtype=np.uint64), 2)
+    assert e.value.code == oracle.EPREC
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.quantize(np.zeros(5, dtype=np.uint64), 8)
+    assert e.value.code == oracle.EINVAL
+
+
+# -------------------------------------------------------------- container --
+
+def test_container_layout_and_roundtrip():
+    import struct
+    rng = np.random.default_rng(9)
+    syms = rng.integers(0, 7, 10_001).astype(np.uint8)
+    f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), 12)
+    for r, l, N, C in [(16, 16, 4, 0), (16, 16, 64, 1000), (8, 23, 32, 333), (8, 20, 7, 4096)]:
+        buf = oracle.encode(f, syms, 12, r, l, N, C)
+        magic, ver, k_, r_, l_, w_, z, N_, C_, n_, nch, z2 = struct.unpack_from(
+            "<IBBBBBBHIQII", buf.tobytes(), 0)
+        assert (magic, ver, k_, r_, l_, w_, z, N_, n_) == (0x534E4172, 1, 12, r, l, 1, 0, N,
+                                                           len(syms))
+        Ceff = C or len(syms)
+        assert C_ == Ceff and nch == -(-len(syms) // Ceff) and z2 == 0
+        end = 32 + 16 * nch
+        for c in range(nch):
+            off, ln, z3 = struct.unpack_from("<QII", buf.tobytes(), 32 + 16 * c)
+            assert off % 16 == 0 and z3 == 0 and off >= end
+            assert not buf[end:off].any()  # zero padding
+            end = off + ln
+        assert len(buf) == (end + 15) // 16 * 16
+        assert (oracle.decode(f, buf) == syms).all()
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 63, 64, 65])
+def test_container_small_and_ragged(n):
+    f = [3, 1] + [0] * 254
+    syms = (np.arange(n) % 2).astype(np.uint8)
+    for N in (1, 4, 64):
+        buf = oracle.encode(f, syms, 2, 16, 16, N, 0)
+        assert (oracle.decode(f, buf) == syms).all()
+
+
+def test_container_corruption_detected():
+    rng = np.random.default_rng(12)
+    syms = rng.integers(0, 200, 50_000).astype(np.uint8)
+    f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), 12)
+    buf = oracle.encode(f, syms, 12, 16, 16, 64, 8192)
+    hdr = oracle.header(buf)
+    first = int(np.frombuffer(buf[32:40].tobytes(), "<u8")[0])
+    bad = buf.copy()
+    bad[first + 4 * 64 + 100] ^= 0x5A
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.decode(f, bad)
+    assert e.value.code == oracle.ECORRUPT
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(f, buf[:len(buf) - 200])
+    assert hdr["n_chunks"] == 7
+
+
+def test_encode_rejects_absent_symbol():
+    f = [4, 0, 0, 12]
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.encode(f, np.array([0, 1, 3], dtype=np.uint8), 4, 16, 16, 1, 0)
+    assert e.value.code == oracle.ENOSYM
+
+
+def test_uint16_symbols_large_alphabet():
+    rng = np.random.default_rng(13)
+    syms = rng.integers(0, 4096, 20_000).astype(np.uint16)
+    f = oracle.quantize(np.bincount(syms, minlength=4096).astype(np.uint64), 15)
+    for r, l in [(16, 16), (8, 23)]:
+        buf = oracle.encode(f, syms, 15, r, l, 32, 4096)
+        assert (oracle.decode(f, buf, threads=3) == syms).all()
