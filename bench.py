@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of interleaved streaming rANS on one MI355X.
+
+Workload: three 256 MiB uint8 buffers, i.i.d. Zipf(s) over 256 symbols for
+s in {0.8, 1.1, 1.5}; M = 2^14, b = L = 2^16, 64 interleaved coders per chunk
+(one per wave64 lane), 64 KiB chunks.  One step = encode every buffer into a
+container and decode it back (rANS encode + decode GB/s, the library's
+stream-ordered entry points; inputs resident in HBM; static tables built
+once per buffer before timing, as the paper's static order-0 model is fixed
+once per input).
+
+value = uncompressed bytes encoded-and-decoded per second (GB = 1e9 B).
+Also reported: per-kernel times from HIP events recorded on the launch
+stream, the roofline of the dominant kernel, and the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size-log2", type=int, default=28, help="symbols per buffer (log2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(work, threads):
+    """The oracle, as it is, on a bounded sample: the first 64 MiB of each
+    buffer, encoded and decoded with `threads` threads over chunks."""
+    import numpy as np
+
+    import oracle
+    sample = 64 << 20
+    tot_bytes, tot_s = 0, 0.0
+    for w, f in work:
+        s = np.ascontiguousarray(w.syms[:sample])
+        k, r, l, _, N, C = w.params.astuple()
+        t0 = time.perf_counter()
+        c = oracle.encode(f, s, k, r, l, N, C, threads=threads)
+        t1 = time.perf_counter()
+        d = oracle.decode(f, c, threads=threads)
+        t2 = time.perf_counter()
+        assert (d == s).all()
+        tot_bytes += s.nbytes
+        tot_s += t2 - t0
+    return {"value": round(tot_bytes / tot_s / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {sample >> 20} MiB of each of the 3 buffers, encode+decode, "
+                      f"{threads} threads over 64 KiB chunks"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X only: the coder's work is independent per "
+              "chunk and this build runs no multi-GPU path (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1402_3392_amd as lr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n = 1 << args.size_log2
+
+    log(f"generating 3 x {n >> 20} MiB Zipf buffers")
+    work = []
+    for s in datagen.CONFIG2_S:
+        w = datagen.config2(s, n=n)
+        work.append(w)
+    params = [lr.rans_params.make(*w.params.astuple()) for w in work]
+    tables = [lr.rans_tables_build(w.counts, w.params.k) for w in work]
+    freqs = [lr.rans_table_freqs(t) for t in tables]
+
+    d_in = [torch.from_numpy(w.syms).to(dev) for w in work]
+    caps = [lr.rans_encode_bound(n, p) for p in params]
+    d_cont = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    d_dec = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in work]
+    d_len = torch.zeros(len(work), dtype=torch.int64, device=dev)
+    d_st = torch.zeros(2 * len(work), dtype=torch.int32, device=dev)
+
+    def enc(i):
+        lr.rans_encode_async(tables[i], params[i], d_in[i], n, d_cont[i], caps[i],
+                             d_len[i:i + 1], d_st[2 * i:2 * i + 1])
+
+    # the container length and header are fixed for a given input: learn them once
+    for i in range(len(work)):
+        enc(i)
+    torch.cuda.synchronize()
+    assert int(d_st.abs().sum()) == 0, f"encode status {d_st.tolist()}"
+    lens = [int(v) for v in d_len.cpu().tolist()]
+    headers = [bytes(d_cont[i][:32].cpu().numpy().tobytes()) for i in range(len(work))]
+
+    def dec(i):
+        lr.rans_decode_async(tables[i], d_cont[i], lens[i], headers[i], d_dec[i], n,
+                             d_st[2 * i + 1:2 * i + 2])
+
+    def step():
+        d_st.zero_()
+        for i in range(len(work)):
+            enc(i)
+            dec(i)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for i in range(len(work)):
+        assert torch.equal(d_dec[i], d_in[i]), f"round trip mismatch on buffer {i}"
+    assert int(d_st.abs().sum()) == 0
+
+    log(f"timing {args.steps} steps")
+    lr.rans_timing_reset()
+    lr.rans_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lr.rans_timing_enable(False)
+    assert int(d_st.abs().sum()) == 0, f"status {d_st.tolist()}"
+    for i in range(len(work)):
+        assert torch.equal(d_dec[i], d_in[i])
+
+    elapsed = t1 - t0
+    sym_bytes = n * len(work)
+    value = args.steps * sym_bytes / elapsed / 1e9
+    kt = {}
+    for kind, name in [(lr.RANS_KERNEL_DECODE, "decode"), (lr.RANS_KERNEL_ENCODE, "encode"),
+                       (lr.RANS_KERNEL_SCAN, "scan"), (lr.RANS_KERNEL_COMPACT, "compact")]:
+        cnt, ms = lr.rans_timing_read(kind)
+        kt[name] = (cnt, ms)
+    lr.rans_timing_reset()
+
+    # algorithmic bytes per launch: container read (or written) + symbols
+    # written (or read) + the static table (4 bytes per alphabet symbol)
+    alg = [lens[i] + n + 4 * 256 for i in range(len(work))]
+    alg_total = args.steps * sum(alg)
+    per_kernel = {k: {"launches": c, "avg_us": round(1e3 * ms / max(c, 1), 2)}
+                  for k, (c, ms) in kt.items()}
+    dom = "decode" if kt["decode"][1] >= kt["encode"][1] else "encode"
+    dom_gbps = alg_total / (kt[dom][1] / 1e3) / 1e9
+    other = "encode" if dom == "decode" else "decode"
+    roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(dom_gbps, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(dom_gbps / HBM_PEAK_GBPS, 4),
+                "traffic": None,
+                "alg_bytes_per_launch": int(sum(alg) / len(alg))}
+
+    res = {
+        "metric": "rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"3 x {n >> 20} MiB uint8 Zipf(s in 0.8/1.1/1.5) over 256, "
+                               "M=2^14, b=L=2^16, N=64, 64 KiB chunks, encode+decode round trip",
+                   "global_batch": 3, "seq_len": n, "parallelism": "none"},
+        "decode_gbps_kernel": round(sym_bytes * args.steps / (kt["decode"][1] / 1e3) / 1e9, 2),
+        "encode_gbps_kernels": round(sym_bytes * args.steps / (
+            (kt["encode"][1] + kt["scan"][1] + kt["compact"][1]) / 1e3) / 1e9, 2),
+        "compression_ratio": [round(lens[i] / n, 4) for i in range(len(work))],
+        "kernels": per_kernel,
+        "roofline": roofline,
+        f"roofline_{other}": {"achieved": round(alg_total / (kt[other][1] / 1e3) / 1e9, 1),
+                              "frac": round(alg_total / (kt[other][1] / 1e3) / 1e9 /
+                                            HBM_PEAK_GBPS, 4)},
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline with {threads} threads")
+        res["cpu_baseline"] = cpu_baseline(list(zip(work, freqs)), threads)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * librans -- interleaved streaming rANS on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only; "device" pointers are HIP device
+ * allocations (any allocator: hipMalloc, a torch tensor's data_ptr(), ...),
+ * "host" pointers are ordinary process memory.  `stream` is a hipStream_t
+ * passed as void* (NULL = the default stream).
+ *
+ * Method: F. Giesen, "Interleaved entropy coders" (arXiv:1402.3392).
+ *   - coding pair C / D and streaming renormalisation into I = [L, bL):
+ *     Section 2, Algorithm 1;
+ *   - N coders with separate states share one stream with no metadata,
+ *     symbol i belonging to coder (i mod N): Sections 3 and 4;
+ *   - the encoder walks the message backwards and writes the stream
+ *     backwards; its final states travel with the stream: Section 2;
+ *   - refill/flush offsets of the coders that renormalise in a step come
+ *     from a ballot of "this coder does I/O" plus a prefix count: Section 6.
+ * The coder used is rANS: C(s,x) = M*floor(x/f_s) + (x mod f_s) + cum_s,
+ * D(x) = (s, f_s*floor(x/M) + (x mod M) - cum_s) with s the symbol whose
+ * slot range [cum_s, cum_s+f_s) holds x mod M; M = 2^k.  (The paper's worked
+ * example in Section 2.1 is this coder with M = 4, f = (1, 3).)
+ *
+ * Stream format (container).  All fields little-endian.
+ *   header, 32 bytes: u32 magic 0x534E4172 ("rANS"), u8 version 1, u8 k,
+ *     u8 r, u8 l, u8 w, u8 0, u16 N, u32 C, u64 n, u32 n_chunks, u32 0
+ *   directory: n_chunks x { u64 offset, u32 length, u32 0 }
+ *   chunk streams, each at a 16-byte aligned offset, zero padding between;
+ *     the first at align16(32 + 16*n_chunks); the total length is
+ *     align16(end of the last chunk) (32 when n == 0).
+ *   chunk c covers symbols [c*C, min(n, (c+1)*C)); its stream is the N final
+ *     encoder states (u32, coder 0 first) followed by the digits in decoder
+ *     order: u16 words when b = 2^16, bytes when b = 2^8.  A coder that
+ *     renormalises by two digits for one symbol stores the more significant
+ *     digit first; within one step coders appear in ascending order
+ *     (depth-first order, Section 5).  Every coder starts encoding in state L;
+ *     when a chunk's length is not a multiple of N, the last step only
+ *     involves coders 0 .. (len mod N)-1.
+ *
+ * Error behaviour: every entry point returns RANS_OK (0) or a negative
+ * RANS_E* code; nothing aborts the process.  A decode whose coders do not all
+ * end in state L with their chunk stream exactly consumed reports
+ * RANS_ECORRUPT (the decoder retraces the encoder's states in reverse,
+ * Section 3); the symbols written for such a chunk are unspecified.
+ * No entry point reads or writes outside the buffers and lengths it is given,
+ * whatever the content of a container.
+ */
+#ifndef LIBRANS_H
+#define LIBRANS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RANS_OK 0
+#define RANS_EINVAL (-1)   /* parameters out of range or inconsistent        */
+#define RANS_EPREC (-2)    /* more distinct symbols present than M = 2^k      */
+#define RANS_ENOSYM (-3)   /* a symbol with frequency 0 (or >= alphabet)      */
+#define RANS_ENOSPC (-4)   /* output capacity too small                       */
+#define RANS_ECORRUPT (-5) /* malformed container or failed end-of-chunk check */
+#define RANS_EDEVICE (-6)  /* a HIP runtime call failed                       */
+#define RANS_ENOMEM (-7)   /* host or device allocation failed                */
+
+/* Coder parameters.  Constraints checked by rans_params_check:
+ *   8 <= prob_bits (k) <= 15          M = 2^k, the frequencies' denominator
+ *   radix_bits (r) in {8, 16}         b = 2^r, digits are bytes or u16 words
+ *   k <= state_lbits (l), l + r <= 32 L = 2^l; L a multiple of M makes every
+ *                                     precursor set b-unique (Section 2) and
+ *                                     the state fits 32 bits
+ *   sym_bytes (w) in {1, 2}           uint8 or uint16 symbols
+ *   interleave (N) in {1,2,4,...,64}  coders per chunk (one per wave lane)
+ *   reserved == 0
+ *   chunk_syms (C)                    symbols per chunk; 0 = the whole input
+ *                                     (then n must fit 32 bits)            */
+typedef struct rans_params {
+    uint8_t prob_bits;
+    uint8_t radix_bits;
+    uint8_t state_lbits;
+    uint8_t sym_bytes;
+    uint16_t interleave;
+    uint16_t reserved;
+    uint32_t chunk_syms;
+} rans_params;
+
+/* Opaque static order-0 model (Section 7: one static distribution per
+ * input): frequencies, cumulative frequencies, slot->symbol map and the
+ * encoder's per-symbol division constants, resident in device memory.
+ * Owned by the library; the device copy lives on the device that was
+ * current when it was built. */
+typedef struct rans_table rans_table;
+
+/* Host only, touches no GPU.  Quantises counts[alphabet] (host) to
+ * freqs_out[alphabet] (host) summing to 2^prob_bits: integer largest
+ * remainder, f_s = floor(c_s*M/T) with the deficit given to the largest
+ * remainders (ties: lower symbol), present symbols forced to >= 1, an excess
+ * taken from the largest frequencies.  Counts already summing to M map to
+ * themselves.  Errors: RANS_EINVAL (alphabet 0, prob_bits outside 1..16, all
+ * counts 0, a total >= 2^47), RANS_EPREC (more present symbols than M). */
+int rans_quantize(const uint64_t *counts, uint32_t alphabet, uint32_t prob_bits,
+                  uint32_t *freqs_out);
+
+/* Builds a table from host counts[alphabet] (quantised as rans_quantize
+ * does) on the current device.  alphabet <= 65536, prob_bits 8..15.
+ * *out receives a handle to destroy with rans_table_destroy.  Synchronous. */
+int rans_tables_build(const uint64_t *counts, uint32_t alphabet, uint32_t prob_bits,
+                      rans_table **out);
+
+/* Copies the table's quantised frequencies to freqs_out[alphabet] (host). */
+int rans_table_freqs(const rans_table *table, uint32_t *freqs_out);
+
+/* Alphabet size and prob_bits of a table (0 for NULL). */
+uint32_t rans_table_alphabet(const rans_table *table);
+uint32_t rans_table_prob_bits(const rans_table *table);
+
+/* Releases a table (NULL is a no-op). */
+void rans_table_destroy(rans_table *table);
+
+/* Host only.  RANS_OK or RANS_EINVAL for the constraints listed above. */
+int rans_params_check(const rans_params *params);
+
+/* Host only.  An upper bound on the container length rans_encode can
+ * produce for n_syms symbols (each symbol emits at most ceil(k/r) digits).
+ * Returns 0 for invalid parameters. */
+uint64_t rans_encode_bound(uint64_t n_syms, const rans_params *params);
+
+/* Encodes d_syms[n_syms] (device; uint8 or uint16 per params->sym_bytes)
+ * into a container at d_out (device, out_cap bytes).  The table's
+ * prob_bits must equal params->prob_bits.  *out_len (host) receives the
+ * container length.  Blocks until the result is known (stream-ordered
+ * before that).  Errors: RANS_EINVAL, RANS_ENOSYM (a symbol of frequency 0
+ * or >= the alphabet; the output is then unspecified), RANS_ENOSPC (out_cap
+ * below the container length, which is still reported in *out_len),
+ * RANS_EDEVICE, RANS_ENOMEM. */
+int rans_encode(const rans_table *table, const rans_params *params, const void *d_syms,
+                uint64_t n_syms, void *d_out, uint64_t out_cap, uint64_t *out_len,
+                void *stream);
+
+/* Decodes the container d_in[in_len] (device) into d_syms (device,
+ * syms_cap symbols of the container's width).  The table must be the one
+ * the container was encoded with (same prob_bits; the library cannot check
+ * more).  *n_syms (host) receives the symbol count.  The header is read
+ * through a small device-to-host copy; the call blocks until the decode has
+ * finished.  Errors: RANS_ECORRUPT, RANS_ENOSPC (syms_cap < n),
+ * RANS_EINVAL, RANS_EDEVICE. */
+int rans_decode(const rans_table *table, const void *d_in, uint64_t in_len, void *d_syms,
+                uint64_t syms_cap, uint64_t *n_syms, void *stream);
+
+/* Stream-ordered encode: validates on the host, enqueues the kernels on
+ * `stream` and returns without waiting.  *d_status (device int32) must hold
+ * RANS_OK when the stream reaches the call; the kernels lower it to the most
+ * negative failure code (RANS_ENOSYM, RANS_ENOSPC).  *d_out_len (device
+ * u64) receives the container length.  Host-side validation errors are
+ * returned directly.  The library's per-stream workspace is reused in
+ * stream order, so back-to-back calls on one stream are safe. */
+int rans_encode_async(const rans_table *table, const rans_params *params, const void *d_syms,
+                      uint64_t n_syms, void *d_out, uint64_t out_cap, uint64_t *d_out_len,
+                      int32_t *d_status, void *stream);
+
+/* Stream-ordered decode.  h_header (host) is a copy of the container's first
+ * 32 bytes, which the caller already holds (it is validated here, so no
+ * device-to-host copy is needed).  *d_status as for rans_encode_async
+ * (RANS_ECORRUPT from the end-of-chunk check).  Returns without waiting. */
+int rans_decode_async(const rans_table *table, const void *d_in, uint64_t in_len,
+                      const void *h_header, void *d_syms, uint64_t syms_cap, int32_t *d_status,
+                      void *stream);
+
+/* One stream of a batch.  `table` is a host handle; every other pointer is
+ * device memory.  Encode: in = symbols, in_len = their count in BYTES
+ * (a multiple of sym_bytes), out = container buffer of out_cap bytes,
+ * *d_out_len = container length.  Decode: in = container of in_len bytes,
+ * out = symbol buffer of out_cap BYTES, *d_out_len = symbols decoded.
+ * *d_status = RANS_OK or the job's RANS_E* code.  A failing job never
+ * affects another job's output. */
+typedef struct rans_job {
+    const rans_table *table;
+    const void *in;
+    uint64_t in_len;
+    void *out;
+    uint64_t out_cap;
+    uint64_t *d_out_len;
+    int32_t *d_status;
+} rans_job;
+
+/* Batched encode of njobs independent streams with shared params in one
+ * persistent-kernel pass (replayed as a HIP graph).  Asynchronous: results
+ * are in the jobs' d_out_len / d_status once `stream` reaches this point.
+ * Returns RANS_EINVAL for invalid params or job descriptors (checked on the
+ * host), RANS_ENOMEM / RANS_EDEVICE for runtime failures. */
+int rans_encode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *params,
+                      void *stream);
+
+/* Batched decode of njobs containers, all encoded with params' k, r, l, w
+ * and N (checked per job on the device; a mismatch fails that job with
+ * RANS_EINVAL).  Asynchronous, as rans_encode_batch. */
+int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *params,
+                      void *stream);
+
+/* Kernel timing (diagnostics).  While enabled, every kernel launch the
+ * library makes is bracketed by two HIP events recorded on the stream it is
+ * launched on.  rans_timing_read waits for the recorded events and returns
+ * the number of launches and their summed duration (milliseconds) for one
+ * kind; rans_timing_reset forgets all records.  Kinds: */
+#define RANS_KERNEL_DECODE 0       /* plain chunk decoder                    */
+#define RANS_KERNEL_ENCODE 1       /* plain chunk encoder (into workspace)   */
+#define RANS_KERNEL_SCAN 2         /* chunk-length scan + directory          */
+#define RANS_KERNEL_COMPACT 3      /* chunk compaction into the container    */
+#define RANS_KERNEL_BATCH_DECODE 4 /* persistent batched decoder             */
+#define RANS_KERNEL_BATCH_ENCODE 5 /* persistent batched encoder             */
+#define RANS_KERNEL_BATCH_PLAN 6   /* batch planning / scans / compaction    */
+int rans_timing_enable(int on);
+int rans_timing_reset(void);
+int rans_timing_read(int kind, uint64_t *launches, double *total_ms);
+
+/* Static description of an error code. */
+const char *rans_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBRANS_H */

@@ -1,0 +1,288 @@
+"""librans -- interleaved streaming rANS on MI355X: thin Python binding.
+
+Argument marshalling only: every step of encoding and decoding runs in the
+HIP kernels of ``librans.so`` (built from ``csrc/`` by ``_build.py``).  There
+is no CPU fallback: importing this package without the built library raises.
+
+The functions carry the C ABI's names (``include/librans.h``).  Device
+buffers are torch tensors on a ROCm device (only their ``data_ptr()`` is
+used) and streams are torch streams (``cuda_stream`` handle); torch is here
+for device memory and streams, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY_PATH = os.path.join(_HERE, "librans.so")
+
+RANS_OK, RANS_EINVAL, RANS_EPREC, RANS_ENOSYM = 0, -1, -2, -3
+RANS_ENOSPC, RANS_ECORRUPT, RANS_EDEVICE, RANS_ENOMEM = -4, -5, -6, -7
+
+if not os.path.exists(LIBRARY_PATH):
+    raise ImportError(f"{LIBRARY_PATH} is not built; run __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950) first")
+
+_lib = ct.CDLL(LIBRARY_PATH)
+
+
+class rans_params(ct.Structure):
+    """Mirror of the C struct rans_params."""
+    _fields_ = [("prob_bits", ct.c_uint8), ("radix_bits", ct.c_uint8),
+                ("state_lbits", ct.c_uint8), ("sym_bytes", ct.c_uint8),
+                ("interleave", ct.c_uint16), ("reserved", ct.c_uint16),
+                ("chunk_syms", ct.c_uint32)]
+
+    @classmethod
+    def make(cls, k, r, l, w, N, C):
+        return cls(k, r, l, w, N, 0, C)
+
+
+class rans_job(ct.Structure):
+    """Mirror of the C struct rans_job."""
+    _fields_ = [("table", ct.c_void_p), ("in_", ct.c_void_p), ("in_len", ct.c_uint64),
+                ("out", ct.c_void_p), ("out_cap", ct.c_uint64),
+                ("d_out_len", ct.c_void_p), ("d_status", ct.c_void_p)]
+
+
+_u64p = ct.POINTER(ct.c_uint64)
+_u32p = ct.POINTER(ct.c_uint32)
+_P = ct.POINTER(rans_params)
+_sig = {
+    "rans_quantize": (ct.c_int, [_u64p, ct.c_uint32, ct.c_uint32, _u32p]),
+    "rans_tables_build": (ct.c_int, [_u64p, ct.c_uint32, ct.c_uint32, ct.POINTER(ct.c_void_p)]),
+    "rans_table_freqs": (ct.c_int, [ct.c_void_p, _u32p]),
+    "rans_table_alphabet": (ct.c_uint32, [ct.c_void_p]),
+    "rans_table_prob_bits": (ct.c_uint32, [ct.c_void_p]),
+    "rans_table_destroy": (None, [ct.c_void_p]),
+    "rans_params_check": (ct.c_int, [_P]),
+    "rans_encode_bound": (ct.c_uint64, [ct.c_uint64, _P]),
+    "rans_encode": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
+                               ct.c_uint64, _u64p, ct.c_void_p]),
+    "rans_decode": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_void_p,
+                               ct.c_uint64, _u64p, ct.c_void_p]),
+    "rans_encode_async": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
+                                     ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "rans_decode_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_char_p,
+                                     ct.c_void_p, ct.c_uint64, ct.c_void_p, ct.c_void_p]),
+    "rans_encode_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_void_p]),
+    "rans_decode_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_void_p]),
+    "rans_strerror": (ct.c_char_p, [ct.c_int]),
+    "rans_timing_enable": (ct.c_int, [ct.c_int]),
+    "rans_timing_reset": (ct.c_int, []),
+    "rans_timing_read": (ct.c_int, [ct.c_int, _u64p, ct.POINTER(ct.c_double)]),
+}
+for _name, (_res, _args) in _sig.items():
+    if hasattr(_lib, _name):
+        _fn = getattr(_lib, _name)
+        _fn.restype = _res
+        _fn.argtypes = _args
+
+
+class RansError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {rans_strerror(code)} ({code})")
+        self.code = code
+
+
+def _check(rc: int, what: str):
+    if rc != RANS_OK:
+        raise RansError(rc, what)
+
+
+def rans_strerror(code: int) -> str:
+    return _lib.rans_strerror(code).decode()
+
+
+def _ptr(buf) -> int:
+    """Device address of a torch tensor (or an int address)."""
+    if buf is None:
+        return 0
+    if isinstance(buf, int):
+        return buf
+    return int(buf.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _params(p) -> rans_params:
+    if isinstance(p, rans_params):
+        return p
+    if isinstance(p, dict):
+        return rans_params.make(p["k"], p["r"], p["l"], p["w"], p["N"], p["C"])
+    if hasattr(p, "astuple"):
+        return rans_params.make(*p.astuple())
+    return rans_params.make(*p)
+
+
+# ------------------------------------------------------------------ tables --
+
+def rans_quantize(counts, prob_bits: int) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint64))
+    f = np.zeros(len(c), dtype=np.uint32)
+    _check(_lib.rans_quantize(c.ctypes.data_as(_u64p), len(c), prob_bits,
+                              f.ctypes.data_as(_u32p)), "rans_quantize")
+    return f
+
+
+class Table:
+    """Owning handle of a device-resident rans_table."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    @property
+    def alphabet(self) -> int:
+        return int(_lib.rans_table_alphabet(self.handle))
+
+    @property
+    def prob_bits(self) -> int:
+        return int(_lib.rans_table_prob_bits(self.handle))
+
+    def close(self):
+        if self.handle:
+            _lib.rans_table_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rans_tables_build(counts, prob_bits: int) -> Table:
+    c = np.ascontiguousarray(np.asarray(counts, dtype=np.uint64))
+    h = ct.c_void_p()
+    _check(_lib.rans_tables_build(c.ctypes.data_as(_u64p), len(c), prob_bits, ct.byref(h)),
+           "rans_tables_build")
+    return Table(h.value)
+
+
+def rans_table_freqs(table: Table) -> np.ndarray:
+    f = np.zeros(table.alphabet, dtype=np.uint32)
+    _check(_lib.rans_table_freqs(table.handle, f.ctypes.data_as(_u32p)), "rans_table_freqs")
+    return f
+
+
+def rans_params_check(params) -> int:
+    p = _params(params)
+    return int(_lib.rans_params_check(ct.byref(p)))
+
+
+def rans_encode_bound(n_syms: int, params) -> int:
+    p = _params(params)
+    return int(_lib.rans_encode_bound(n_syms, ct.byref(p)))
+
+
+# ------------------------------------------------------- single buffers ----
+
+def rans_encode(table: Table, params, d_syms, n_syms: int, d_out, out_cap: int,
+                stream=None) -> int:
+    """Encodes n_syms symbols at d_syms into d_out; returns the container length."""
+    p = _params(params)
+    olen = ct.c_uint64()
+    rc = _lib.rans_encode(table.handle, ct.byref(p), _ptr(d_syms), n_syms, _ptr(d_out), out_cap,
+                          ct.byref(olen), _stream(stream))
+    _check(rc, "rans_encode")
+    return int(olen.value)
+
+
+def rans_decode(table: Table, d_in, in_len: int, d_syms, syms_cap: int, stream=None) -> int:
+    """Decodes the container d_in[in_len] into d_syms; returns the symbol count."""
+    n = ct.c_uint64()
+    rc = _lib.rans_decode(table.handle, _ptr(d_in), in_len, _ptr(d_syms), syms_cap, ct.byref(n),
+                          _stream(stream))
+    _check(rc, "rans_decode")
+    return int(n.value)
+
+
+def rans_encode_async(table: Table, params, d_syms, n_syms: int, d_out, out_cap: int,
+                      d_out_len, d_status, stream=None):
+    """Stream-ordered encode; *d_status (device int32) must be 0 beforehand."""
+    p = _params(params)
+    _check(_lib.rans_encode_async(table.handle, ct.byref(p), _ptr(d_syms), n_syms, _ptr(d_out),
+                                  out_cap, _ptr(d_out_len), _ptr(d_status), _stream(stream)),
+           "rans_encode_async")
+
+
+def rans_decode_async(table: Table, d_in, in_len: int, header: bytes, d_syms, syms_cap: int,
+                      d_status, stream=None):
+    """Stream-ordered decode given a host copy of the 32-byte header."""
+    hb = bytes(header[:32])
+    _check(_lib.rans_decode_async(table.handle, _ptr(d_in), in_len, hb, _ptr(d_syms), syms_cap,
+                                  _ptr(d_status), _stream(stream)), "rans_decode_async")
+
+
+# ---------------------------------------------------------------- batches --
+
+def make_jobs(specs) -> ct.Array:
+    """specs: iterable of (table, d_in, in_len, d_out, out_cap, d_out_len_addr, d_status_addr)."""
+    specs = list(specs)
+    arr = (rans_job * max(1, len(specs)))()
+    for i, (tab, din, inl, dout, cap, dlen, dst) in enumerate(specs):
+        arr[i] = rans_job(tab.handle, _ptr(din), inl, _ptr(dout), cap, _ptr(dlen), _ptr(dst))
+    return arr
+
+
+def rans_encode_batch(jobs, njobs: int, params, stream=None):
+    p = _params(params)
+    _check(_lib.rans_encode_batch(jobs, njobs, ct.byref(p), _stream(stream)), "rans_encode_batch")
+
+
+def rans_decode_batch(jobs, njobs: int, params, stream=None):
+    p = _params(params)
+    _check(_lib.rans_decode_batch(jobs, njobs, ct.byref(p), _stream(stream)), "rans_decode_batch")
+
+
+# ------------------------------------------------------------------ timing --
+
+RANS_KERNEL_DECODE, RANS_KERNEL_ENCODE, RANS_KERNEL_SCAN, RANS_KERNEL_COMPACT = 0, 1, 2, 3
+RANS_KERNEL_BATCH_DECODE, RANS_KERNEL_BATCH_ENCODE, RANS_KERNEL_BATCH_PLAN = 4, 5, 6
+
+
+def rans_timing_enable(on: bool = True):
+    _check(_lib.rans_timing_enable(1 if on else 0), "rans_timing_enable")
+
+
+def rans_timing_reset():
+    _check(_lib.rans_timing_reset(), "rans_timing_reset")
+
+
+def rans_timing_read(kind: int):
+    """Returns (launches, total milliseconds) of one kernel kind."""
+    n = ct.c_uint64()
+    ms = ct.c_double()
+    _check(_lib.rans_timing_read(kind, ct.byref(n), ct.byref(ms)), "rans_timing_read")
+    return int(n.value), float(ms.value)
+
+
+# --------------------------------------------------- torch conveniences ----
+
+def encode(table: Table, params, syms, stream=None):
+    """syms: device uint8 tensor of n*w bytes.  Returns (container tensor, length)."""
+    import torch
+    p = _params(params)
+    n = syms.numel() * syms.element_size() // p.sym_bytes
+    cap = rans_encode_bound(n, p)
+    out = torch.empty(max(cap, 16), dtype=torch.uint8, device=syms.device)
+    olen = rans_encode(table, p, syms, n, out, cap, stream)
+    return out, olen
+
+
+def decode(table: Table, container, in_len: int, n_syms: int, sym_bytes: int = 1, stream=None):
+    """Returns a device uint8 tensor holding n_syms*sym_bytes decoded bytes."""
+    import torch
+    out = torch.empty(max(n_syms * sym_bytes, 16), dtype=torch.uint8, device=container.device)
+    n = rans_decode(table, container, in_len, out, n_syms, stream)
+    return out[: n * sym_bytes]

@@ -1,0 +1,461 @@
+// librans single-buffer entry points: parameter checks, container header,
+// per-stream device workspace, kernel launches and status read-back.
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "rans_internal.h"
+#include "timing.h"
+#include "workspace.h"
+
+namespace rans {
+
+int max_lds_bytes()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return v;
+}
+
+int check_params(const rans_params* p)
+{
+    if (!p)
+        return RANS_EINVAL;
+    const uint32_t k = p->prob_bits, r = p->radix_bits, l = p->state_lbits, w = p->sym_bytes,
+                   N = p->interleave;
+    if (k < 8 || k > 15 || (r != 8 && r != 16) || l < k || l + r > 32 || (w != 1 && w != 2))
+        return RANS_EINVAL;
+    if (N < 1 || N > 64 || (N & (N - 1)) != 0 || p->reserved != 0)
+        return RANS_EINVAL;
+    return RANS_OK;
+}
+
+uint32_t log2u(uint32_t v)
+{
+    uint32_t r = 0;
+    while ((1u << r) < v)
+        ++r;
+    return r;
+}
+
+// Digits a symbol can emit at most: the state drops below f*b*L/M after at
+// most ceil(k/r) divisions by b.
+uint32_t max_digits(uint32_t k, uint32_t r) { return (k + r - 1) / r; }
+
+uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r)
+{
+    return (uint64_t(C) * max_digits(k, r) * (r / 8) + 15) & ~uint64_t(15);
+}
+
+void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch)
+{
+    std::memset(h, 0, 32);
+    const uint32_t magic = kMagic;
+    std::memcpy(h, &magic, 4);
+    h[4] = 1;
+    h[5] = p.prob_bits;
+    h[6] = p.radix_bits;
+    h[7] = p.state_lbits;
+    h[8] = p.sym_bytes;
+    h[9] = 0;
+    const uint16_t N = p.interleave;
+    std::memcpy(h + 10, &N, 2);
+    std::memcpy(h + 12, &C, 4);
+    std::memcpy(h + 16, &n, 8);
+    std::memcpy(h + 24, &nch, 4);
+}
+
+int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
+{
+    uint32_t magic, C, nch;
+    uint16_t N;
+    uint64_t n;
+    std::memcpy(&magic, h, 4);
+    std::memcpy(&N, h + 10, 2);
+    std::memcpy(&C, h + 12, 4);
+    std::memcpy(&n, h + 16, 8);
+    std::memcpy(&nch, h + 24, 4);
+    if (magic != kMagic || h[4] != 1 || h[9] != 0)
+        return RANS_ECORRUPT;
+    rans_params p{};
+    p.prob_bits = h[5];
+    p.radix_bits = h[6];
+    p.state_lbits = h[7];
+    p.sym_bytes = h[8];
+    p.interleave = N;
+    p.chunk_syms = C;
+    if (check_params(&p) != RANS_OK)
+        return RANS_ECORRUPT;
+    if (n == 0 ? nch != 0 : (C == 0 || nch != (n + C - 1) / C))
+        return RANS_ECORRUPT;
+    if (kHeaderBytes + uint64_t(kDirEntryBytes) * nch > in_len)
+        return RANS_ECORRUPT;
+    out->p = p;
+    out->n = n;
+    out->n_chunks = nch;
+    return RANS_OK;
+}
+
+bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds)
+{
+    const uint64_t maxl = static_cast<uint64_t>(max_lds_bytes());
+    const uint64_t packed = t.dec_bytes + t.sym_bytes, two = t.sym_bytes + t.fc_bytes;
+    // The packed table costs one dependent LDS read per symbol; keep it while
+    // it leaves room for two resident blocks per CU.
+    if (packed <= maxl && packed <= 96 * 1024) {
+        *layout = kPacked;
+        *lds = static_cast<uint32_t>(packed);
+        return true;
+    }
+    if (two <= maxl) {
+        *layout = kTwoLevel;
+        *lds = static_cast<uint32_t>(two);
+        return true;
+    }
+    return false;
+}
+
+void fill_decode_tables(const DevTable& t, Layout layout, DecodeArgs* a)
+{
+    if (layout == kPacked) {
+        a->tab0 = t.dec;
+        a->tab0_bytes = static_cast<uint32_t>(t.dec_bytes);
+        a->tab1 = t.sym;
+        a->tab1_bytes = static_cast<uint32_t>(t.sym_bytes);
+    } else {
+        a->tab0 = t.sym;
+        a->tab0_bytes = static_cast<uint32_t>(t.sym_bytes);
+        a->tab1 = t.fc;
+        a->tab1_bytes = static_cast<uint32_t>(t.fc_bytes);
+    }
+}
+
+}  // namespace rans
+
+using namespace rans;
+
+extern "C" int rans_params_check(const rans_params* params) { return check_params(params); }
+
+extern "C" uint64_t rans_encode_bound(uint64_t n, const rans_params* p)
+{
+    if (check_params(p) != RANS_OK)
+        return 0;
+    uint64_t C = p->chunk_syms ? p->chunk_syms : n;
+    if (n == 0 || C == 0)
+        return kHeaderBytes;
+    if (C > 0xFFFFFFFFull)
+        return 0;
+    const uint64_t nch = (n + C - 1) / C;
+    const uint64_t per = uint64_t(max_digits(p->prob_bits, p->radix_bits)) * (p->radix_bits / 8);
+    const uint64_t full = nch - 1, last = n - full * C;
+    auto a16 = [](uint64_t v) { return (v + 15) & ~uint64_t(15); };
+    return a16(kHeaderBytes + kDirEntryBytes * nch) +
+           full * a16(4ull * p->interleave + per * C) + a16(4ull * p->interleave + per * last);
+}
+
+extern "C" const char* rans_strerror(int code)
+{
+    switch (code) {
+    case RANS_OK: return "ok";
+    case RANS_EINVAL: return "invalid argument or parameters";
+    case RANS_EPREC: return "more distinct symbols than 2^prob_bits";
+    case RANS_ENOSYM: return "symbol with zero frequency or outside the alphabet";
+    case RANS_ENOSPC: return "output buffer too small";
+    case RANS_ECORRUPT: return "corrupt or truncated stream";
+    case RANS_EDEVICE: return "HIP runtime error";
+    case RANS_ENOMEM: return "out of memory";
+    default: return "unknown error";
+    }
+}
+
+// Validates an encode call and fills the launch arguments (host only).
+static int prepare_encode(const rans_table* table, const rans_params* params, const void* d_syms,
+                          uint64_t n, void* d_out, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
+                          uint64_t* ws_need)
+{
+    if (!table || !d_out)
+        return RANS_EINVAL;
+    int rc = check_params(params);
+    if (rc != RANS_OK)
+        return rc;
+    const DevTable& t = *dev_table(table);
+    const rans_params& p = *params;
+    if (t.k != p.prob_bits || (n && !d_syms))
+        return RANS_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_out) & 15) ||
+        (reinterpret_cast<uintptr_t>(d_syms) & (p.sym_bytes - 1)))
+        return RANS_EINVAL;
+    const uint64_t C64 = p.chunk_syms ? p.chunk_syms : n;
+    if (C64 > 0xFFFFFFFFull)
+        return RANS_EINVAL;
+    const uint32_t C = static_cast<uint32_t>(C64);
+    const uint64_t nch64 = n ? (n + C - 1) / C : 0;
+    if (nch64 > 0xFFFFFFFFull)
+        return RANS_EINVAL;
+    const uint32_t nch = static_cast<uint32_t>(nch64);
+    const uint32_t R = p.radix_bits, N = p.interleave;
+    const uint64_t sb = slot_bytes_for(C, p.prob_bits, R);
+    const EncodeLayout el = encode_layout(nch, N, sb);
+    *ws_need = el.total;
+
+    *ea = EncodeArgs{};
+    ea->syms = d_syms;
+    ea->n = n;
+    ea->C = C;
+    ea->n_chunks = nch;
+    ea->N = N;
+    ea->log2N = log2u(N);
+    ea->k = p.prob_bits;
+    ea->l = p.state_lbits;
+    ea->alphabet = t.alphabet;
+    ea->enc = t.enc;
+    ea->enc_bytes = static_cast<uint32_t>(t.enc_bytes);
+    ea->slot_bytes = sb;
+
+    *sa = ScanArgs{};
+    sa->n_chunks = nch;
+    sa->N = N;
+    sa->digit_bytes = R / 8;
+    sa->out = static_cast<uint8_t*>(d_out);
+    make_header(sa->hdr, p, C, n, nch);
+
+    *ca = CompactArgs{};
+    ca->slot_bytes = sb;
+    ca->n_chunks = nch;
+    ca->N = N;
+    ca->digit_bytes = R / 8;
+    ca->out = sa->out;
+    // workspace offsets are stored now and rebased in bind_workspace
+    ea->slots = reinterpret_cast<uint8_t*>(el.slots);
+    ea->states = reinterpret_cast<uint32_t*>(el.states);
+    ea->ndig = reinterpret_cast<uint32_t*>(el.ndig);
+    sa->chunk_off = reinterpret_cast<uint64_t*>(el.chunk_off);
+    sa->total = reinterpret_cast<uint64_t*>(el.flags + 8);
+    return RANS_OK;
+}
+
+static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca)
+{
+    auto rb = [base](auto* p) { return reinterpret_cast<decltype(p)>(base + reinterpret_cast<uintptr_t>(p)); };
+    ea->slots = rb(ea->slots);
+    ea->states = rb(ea->states);
+    ea->ndig = rb(ea->ndig);
+    sa->chunk_off = rb(sa->chunk_off);
+    sa->total = rb(sa->total);
+    sa->ndig = ea->ndig;
+    ca->slots = ea->slots;
+    ca->states = ea->states;
+    ca->ndig = ea->ndig;
+    ca->chunk_off = sa->chunk_off;
+    ca->total = sa->total;
+}
+
+static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
+                                 int R, int W, hipStream_t st)
+{
+    hipError_t e;
+    {
+        TimingScope ts(RANS_KERNEL_ENCODE, st);
+        e = launch_encode(ea, R, W, st);
+    }
+    if (e == hipSuccess) {
+        TimingScope ts(RANS_KERNEL_SCAN, st);
+        e = launch_scan(sa, st);
+    }
+    if (e == hipSuccess) {
+        TimingScope ts(RANS_KERNEL_COMPACT, st);
+        e = launch_compact(ca, st);
+    }
+    return e;
+}
+
+static hipError_t enqueue_decode(const DecodeArgs& da, int R, int W, Layout layout, hipStream_t st)
+{
+    TimingScope ts(RANS_KERNEL_DECODE, st);
+    return launch_decode(da, R, W, layout, st);
+}
+
+extern "C" int rans_encode_async(const rans_table* table, const rans_params* params,
+                                 const void* d_syms, uint64_t n, void* d_out, uint64_t out_cap,
+                                 uint64_t* d_out_len, int32_t* d_status, void* stream)
+{
+    if (!d_status)
+        return RANS_EINVAL;
+    EncodeArgs ea;
+    ScanArgs sa;
+    CompactArgs ca;
+    uint64_t need = 0;
+    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &need);
+    if (rc != RANS_OK)
+        return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace* ws = workspace_for(st);
+    if (!ws)
+        return RANS_ENOMEM;
+    std::lock_guard<std::mutex> lk(ws->mu);
+    rc = ws->reserve(need);
+    if (rc != RANS_OK)
+        return rc;
+    bind_workspace(static_cast<uint8_t*>(ws->dev), &ea, &sa, &ca);
+    ea.status = sa.status = d_status;
+    sa.out_cap = ca.out_cap = out_cap;
+    sa.total_out = d_out_len;
+    return enqueue_encode(ea, sa, ca, params->radix_bits, params->sym_bytes, st) == hipSuccess
+               ? RANS_OK
+               : RANS_EDEVICE;
+}
+
+extern "C" int rans_encode(const rans_table* table, const rans_params* params, const void* d_syms,
+                           uint64_t n, void* d_out, uint64_t out_cap, uint64_t* out_len,
+                           void* stream)
+{
+    if (!out_len)
+        return RANS_EINVAL;
+    *out_len = 0;
+    EncodeArgs ea;
+    ScanArgs sa;
+    CompactArgs ca;
+    uint64_t need = 0;
+    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &need);
+    if (rc != RANS_OK)
+        return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace* ws = workspace_for(st);
+    if (!ws)
+        return RANS_ENOMEM;
+    std::lock_guard<std::mutex> lk(ws->mu);
+    rc = ws->reserve(need);
+    if (rc != RANS_OK)
+        return rc;
+    uint8_t* base = static_cast<uint8_t*>(ws->dev);
+    bind_workspace(base, &ea, &sa, &ca);
+    int32_t* status = reinterpret_cast<int32_t*>(base);  // flags word at offset 0
+    ea.status = sa.status = status;
+    sa.out_cap = ca.out_cap = out_cap;
+    sa.total_out = nullptr;
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(status), 0, 1, st);
+    if (e == hipSuccess)
+        e = enqueue_encode(ea, sa, ca, params->radix_bits, params->sym_bytes, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws->host, base, 16, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return RANS_EDEVICE;
+    int32_t code;
+    uint64_t total;
+    std::memcpy(&code, ws->host, 4);
+    std::memcpy(&total, static_cast<uint8_t*>(ws->host) + 8, 8);
+    *out_len = total;
+    return code;
+}
+
+// Validates a decode call against a host copy of the header.
+static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in_len,
+                          const uint8_t* h_header, void* d_syms, uint64_t syms_cap,
+                          DecodeArgs* da, Header* h, Layout* layout)
+{
+    int rc = parse_header(h_header, in_len, h);
+    if (rc != RANS_OK)
+        return rc;
+    const DevTable& t = *dev_table(table);
+    if (t.k != h->p.prob_bits)
+        return RANS_EINVAL;
+    if (h->p.sym_bytes == 1 && t.sym_w != 1)
+        return RANS_EINVAL;
+    if (h->n > syms_cap)
+        return RANS_ENOSPC;
+    if (h->n && (!d_syms || (reinterpret_cast<uintptr_t>(d_syms) & (h->p.sym_bytes - 1))))
+        return RANS_EINVAL;
+    uint32_t lds;
+    if (!choose_layout(t, layout, &lds))
+        return RANS_EINVAL;
+    *da = DecodeArgs{};
+    da->in = static_cast<const uint8_t*>(d_in);
+    da->in_len = in_len;
+    da->out = d_syms;
+    da->n = h->n;
+    da->C = h->p.chunk_syms;
+    da->n_chunks = h->n_chunks;
+    da->N = h->p.interleave;
+    da->log2N = log2u(da->N);
+    da->k = h->p.prob_bits;
+    da->l = h->p.state_lbits;
+    da->alphabet = t.alphabet;
+    fill_decode_tables(t, *layout, da);
+    return RANS_OK;
+}
+
+extern "C" int rans_decode_async(const rans_table* table, const void* d_in, uint64_t in_len,
+                                 const void* h_header, void* d_syms, uint64_t syms_cap,
+                                 int32_t* d_status, void* stream)
+{
+    if (!table || !d_in || !h_header || !d_status)
+        return RANS_EINVAL;
+    if (in_len < kHeaderBytes)
+        return RANS_ECORRUPT;
+    if (reinterpret_cast<uintptr_t>(d_in) & 15)
+        return RANS_EINVAL;
+    DecodeArgs da;
+    Header h;
+    Layout layout;
+    int rc = prepare_decode(table, d_in, in_len, static_cast<const uint8_t*>(h_header), d_syms,
+                            syms_cap, &da, &h, &layout);
+    if (rc != RANS_OK || h.n == 0)
+        return rc;
+    da.status = d_status;
+    return enqueue_decode(da, h.p.radix_bits, h.p.sym_bytes, layout,
+                          static_cast<hipStream_t>(stream)) == hipSuccess
+               ? RANS_OK
+               : RANS_EDEVICE;
+}
+
+extern "C" int rans_decode(const rans_table* table, const void* d_in, uint64_t in_len, void* d_syms,
+                           uint64_t syms_cap, uint64_t* n_syms, void* stream)
+{
+    if (!table || !d_in || !n_syms)
+        return RANS_EINVAL;
+    *n_syms = 0;
+    if (in_len < kHeaderBytes)
+        return RANS_ECORRUPT;
+    if (reinterpret_cast<uintptr_t>(d_in) & 15)
+        return RANS_EINVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Workspace* ws = workspace_for(st);
+    if (!ws)
+        return RANS_ENOMEM;
+    std::lock_guard<std::mutex> lk(ws->mu);
+    int rc = ws->reserve(256);
+    if (rc != RANS_OK)
+        return rc;
+    if (hipMemcpyAsync(ws->host, d_in, kHeaderBytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return RANS_EDEVICE;
+    uint8_t hdr[kHeaderBytes];
+    std::memcpy(hdr, ws->host, kHeaderBytes);
+    DecodeArgs da;
+    Header h;
+    Layout layout;
+    rc = prepare_decode(table, d_in, in_len, hdr, d_syms, syms_cap, &da, &h, &layout);
+    if (rc == RANS_OK || rc == RANS_ENOSPC)
+        *n_syms = h.n;
+    if (rc != RANS_OK || h.n == 0)
+        return rc;
+    uint8_t* base = static_cast<uint8_t*>(ws->dev);
+    da.status = reinterpret_cast<int32_t*>(base);
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(base), 0, 1, st);
+    if (e == hipSuccess)
+        e = enqueue_decode(da, h.p.radix_bits, h.p.sym_bytes, layout, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws->host, base, 16, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return RANS_EDEVICE;
+    int32_t code;
+    std::memcpy(&code, ws->host, 4);
+    return code;
+}

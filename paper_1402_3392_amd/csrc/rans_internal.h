@@ -1,0 +1,120 @@
+// Internal declarations shared by the librans host code and its HIP kernels.
+// Nothing here is part of the C ABI (include/librans.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/librans.h"
+
+namespace rans {
+
+constexpr uint32_t kMagic = 0x534E4172u;  // "rANS" read little-endian
+constexpr uint32_t kHeaderBytes = 32;
+constexpr uint32_t kDirEntryBytes = 16;
+
+// Kernels report failures by atomicMin of a negative RANS_E* code into an
+// int32 status word the caller zeroed; the most negative code wins.
+
+// Decoder table layouts in LDS.
+//   kPacked: per slot one u32 (f << 16 | (slot - cum_s)) plus the slot's
+//            symbol (w bytes): one dependent LDS read on the state chain.
+//   kTwoLevel: per slot the symbol, per symbol one u32 (f | cum << 16):
+//            two dependent LDS reads, much smaller for large M.
+enum Layout : int { kPacked = 1, kTwoLevel = 2 };
+
+// Device-resident table (see tables.cpp for how each array is built).
+struct DevTable {
+    uint32_t alphabet;  // symbols 0 .. alphabet-1
+    uint32_t k;         // M = 2^k
+    uint32_t sym_w;     // bytes per slot->symbol entry (1 if alphabet <= 256)
+    uint32_t* dec;      // [M]      packed slot entries (kPacked)
+    void* sym;          // [M]      slot -> symbol, sym_w bytes each
+    uint32_t* fc;       // [alpha]  f | cum << 16 (kTwoLevel)
+    uint4* enc;         // [alpha+1] encoder entries; the extra one has f = 0
+    uint64_t dec_bytes, sym_bytes, fc_bytes, enc_bytes;  // padded to 16
+};
+
+// Encoder entry, one per symbol (uint4):
+//   x = GM magic m'      (Granlund & Montgomery, "Division by invariant
+//                         integers using multiplication", PLDI 1994, Fig. 4.1)
+//   y = f | cum << 16
+//   z = sh1 | sh2 << 8   (the two shifts of that method)
+//   w = M - f            (C(s,x) = x + q*(M - f) + cum with q = x / f)
+
+struct DecodeArgs {
+    const uint8_t* in;
+    uint64_t in_len;
+    void* out;
+    uint64_t n;          // symbols in the container
+    uint32_t C;          // symbols per chunk
+    uint32_t n_chunks;
+    uint32_t N;          // coders per chunk (power of two <= 64)
+    uint32_t log2N;
+    uint32_t k, l;
+    uint32_t alphabet;
+    const void* tab0;    // kPacked: dec; kTwoLevel: sym
+    const void* tab1;    // kPacked: sym; kTwoLevel: fc
+    uint32_t tab0_bytes, tab1_bytes;  // multiples of 16
+    int32_t* status;
+};
+
+struct EncodeArgs {
+    const void* syms;
+    uint64_t n;
+    uint32_t C;
+    uint32_t n_chunks;
+    uint32_t N;
+    uint32_t log2N;
+    uint32_t k, l;
+    uint32_t alphabet;
+    const uint4* enc;     // alphabet + 1 entries
+    uint32_t enc_bytes;   // multiple of 16
+    uint8_t* slots;       // n_chunks slots of slot_bytes, digits end at slot end
+    uint64_t slot_bytes;  // multiple of 16
+    uint32_t* states;     // n_chunks * N final states
+    uint32_t* ndig;       // n_chunks digit counts
+    int32_t* status;
+};
+
+struct ScanArgs {
+    const uint32_t* ndig;
+    uint32_t n_chunks;
+    uint32_t N;
+    uint32_t digit_bytes;
+    uint8_t* out;
+    uint64_t out_cap;
+    uint8_t hdr[32];      // header image written by the scan kernel
+    uint64_t* chunk_off;  // n_chunks destination offsets (scratch)
+    uint64_t* total;      // container length (workspace)
+    uint64_t* total_out;  // optional second copy (caller's device word)
+    int32_t* status;
+};
+
+struct CompactArgs {
+    const uint8_t* slots;
+    uint64_t slot_bytes;
+    const uint32_t* states;
+    const uint32_t* ndig;
+    const uint64_t* chunk_off;
+    const uint64_t* total;
+    uint32_t n_chunks;
+    uint32_t N;
+    uint32_t digit_bytes;
+    uint8_t* out;
+    uint64_t out_cap;
+};
+
+// Launchers (kernels.hip).  All asynchronous on `stream`.
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint32_t count, hipStream_t stream);
+hipError_t launch_decode(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
+hipError_t launch_encode(const EncodeArgs& a, int R, int W, hipStream_t stream);
+hipError_t launch_scan(const ScanArgs& a, hipStream_t stream);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t stream);
+
+// Host helpers (tables.cpp / api.cpp).
+int quantize(const uint64_t* counts, uint32_t alphabet, uint32_t k, uint32_t* f);
+const DevTable* dev_table(const rans_table* t);
+int max_lds_bytes();
+
+}  // namespace rans

@@ -1,0 +1,253 @@
+// Static order-0 model: quantisation of counts to M = 2^k and the device
+// tables the kernels stage into LDS.  The paper evaluates a static order-0
+// model determined once per input (Section 7) and names rANS as the coder
+// (Sections 2 and 7); the tables below serve its C and D functions.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "rans_internal.h"
+
+struct rans_table {
+    rans::DevTable dev;
+    std::vector<uint32_t> freq;
+    int device;
+};
+
+namespace rans {
+
+// Integer largest-remainder quantiser (see rans_quantize in librans.h).
+int quantize(const uint64_t* counts, uint32_t alphabet, uint32_t k, uint32_t* f)
+{
+    if (!counts || !f || alphabet == 0 || k < 1 || k > 16)
+        return RANS_EINVAL;
+    const uint64_t M = 1ull << k, lim = 1ull << 47;
+    uint64_t total = 0, present = 0;
+    for (uint32_t s = 0; s < alphabet; ++s) {
+        if (counts[s] >= lim)
+            return RANS_EINVAL;
+        total += counts[s];
+        present += counts[s] != 0;
+    }
+    if (total == 0 || total >= lim)
+        return RANS_EINVAL;
+    if (present > M)
+        return RANS_EPREC;
+
+    std::vector<uint64_t> rem(alphabet);
+    std::vector<uint32_t> grow;  // present, not forced: candidates for +1
+    uint64_t sum = 0;
+    for (uint32_t s = 0; s < alphabet; ++s) {
+        const uint64_t scaled = counts[s] * M;
+        f[s] = static_cast<uint32_t>(scaled / total);
+        rem[s] = scaled % total;
+        if (counts[s] != 0) {
+            if (f[s] == 0)
+                f[s] = 1;  // forced
+            else
+                grow.push_back(s);
+        }
+        sum += f[s];
+    }
+    if (sum < M) {
+        // index-ascending list, stable sort on remainder: ties keep index order
+        std::stable_sort(grow.begin(), grow.end(),
+                         [&](uint32_t a, uint32_t b) { return rem[a] > rem[b]; });
+        const uint64_t need = M - sum;
+        for (uint64_t t = 0; t < need && t < grow.size(); ++t)
+            f[grow[t]] += 1;
+    }
+    while (sum > M) {
+        uint32_t best = alphabet;
+        for (uint32_t s = 0; s < alphabet; ++s)
+            if (f[s] > 1 && (best == alphabet || f[s] > f[best]))
+                best = s;
+        f[best] -= 1;
+        --sum;
+    }
+    return RANS_OK;
+}
+
+// Granlund-Montgomery constants for dividing a 32-bit x by f (1 <= f < 2^31):
+// l = ceil(log2 f), m' = floor(2^32 (2^l - f) / f) + 1, sh1 = min(l,1),
+// sh2 = max(l-1,0); then q = (t + ((x - t) >> sh1)) >> sh2 with
+// t = mulhi(m', x) equals floor(x / f) for every x < 2^32.
+static void gm_constants(uint32_t f, uint32_t* magic, uint32_t* sh1, uint32_t* sh2)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < f)
+        ++l;
+    const uint64_t m = ((1ull << 32) * ((1ull << l) - f)) / f + 1;
+    *magic = static_cast<uint32_t>(m);
+    *sh1 = l < 1 ? l : 1;
+    *sh2 = l > 1 ? l - 1 : 0;
+}
+
+static inline uint32_t gm_divide(uint32_t x, uint32_t magic, uint32_t sh1, uint32_t sh2)
+{
+    const uint32_t t = static_cast<uint32_t>((static_cast<uint64_t>(magic) * x) >> 32);
+    return (t + ((x - t) >> sh1)) >> sh2;
+}
+
+static uint64_t pad16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
+
+const DevTable* dev_table(const rans_table* t) { return t ? &t->dev : nullptr; }
+
+}  // namespace rans
+
+using namespace rans;
+
+extern "C" int rans_quantize(const uint64_t* counts, uint32_t alphabet, uint32_t prob_bits,
+                             uint32_t* freqs_out)
+{
+    return quantize(counts, alphabet, prob_bits, freqs_out);
+}
+
+extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint32_t prob_bits,
+                                 rans_table** out)
+{
+    if (!out)
+        return RANS_EINVAL;
+    *out = nullptr;
+    if (alphabet == 0 || alphabet > 65536 || prob_bits < 8 || prob_bits > 15)
+        return RANS_EINVAL;
+    const uint32_t k = prob_bits, M = 1u << k;
+    std::vector<uint32_t> f(alphabet);
+    int rc = quantize(counts, alphabet, k, f.data());
+    if (rc != RANS_OK)
+        return rc;
+
+    const uint32_t sym_w = alphabet <= 256 ? 1 : 2;
+    std::vector<uint32_t> cum(alphabet + 1, 0);
+    for (uint32_t s = 0; s < alphabet; ++s)
+        cum[s + 1] = cum[s] + f[s];
+
+    DevTable d{};
+    d.alphabet = alphabet;
+    d.k = k;
+    d.sym_w = sym_w;
+    d.dec_bytes = pad16(uint64_t(M) * 4);
+    d.sym_bytes = pad16(uint64_t(M) * sym_w);
+    d.fc_bytes = pad16(uint64_t(alphabet) * 4);
+    d.enc_bytes = pad16(uint64_t(alphabet + 1) * 16);
+
+    std::vector<uint8_t> h_dec(d.dec_bytes, 0), h_sym(d.sym_bytes, 0), h_fc(d.fc_bytes, 0),
+        h_enc(d.enc_bytes, 0);
+    uint32_t* dec = reinterpret_cast<uint32_t*>(h_dec.data());
+    uint32_t* fc = reinterpret_cast<uint32_t*>(h_fc.data());
+    uint32_t* enc = reinterpret_cast<uint32_t*>(h_enc.data());
+    for (uint32_t s = 0; s < alphabet; ++s) {
+        for (uint32_t slot = cum[s]; slot < cum[s + 1]; ++slot) {
+            dec[slot] = (f[s] << 16) | (slot - cum[s]);
+            if (sym_w == 1)
+                h_sym[slot] = static_cast<uint8_t>(s);
+            else {
+                h_sym[2 * slot] = static_cast<uint8_t>(s);
+                h_sym[2 * slot + 1] = static_cast<uint8_t>(s >> 8);
+            }
+        }
+        fc[s] = f[s] | (cum[s] << 16);
+        uint32_t magic = 0, sh1 = 0, sh2 = 0;
+        if (f[s] != 0)
+            gm_constants(f[s], &magic, &sh1, &sh2);
+        enc[4 * s + 0] = magic;
+        enc[4 * s + 1] = f[s] | (cum[s] << 16);
+        enc[4 * s + 2] = sh1 | (sh2 << 8);
+        enc[4 * s + 3] = M - f[s];
+    }
+    // entry `alphabet` stays all-zero: f = 0 marks "not encodable"
+
+    rans_table* t = new (std::nothrow) rans_table();
+    if (!t)
+        return RANS_ENOMEM;
+    t->freq = f;
+    if (hipGetDevice(&t->device) != hipSuccess) {
+        delete t;
+        return RANS_EDEVICE;
+    }
+    void* blob = nullptr;
+    const uint64_t total = d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes;
+    if (hipMalloc(&blob, total) != hipSuccess) {
+        delete t;
+        return RANS_ENOMEM;
+    }
+    uint8_t* p = static_cast<uint8_t*>(blob);
+    d.dec = reinterpret_cast<uint32_t*>(p);
+    d.sym = p + d.dec_bytes;
+    d.fc = reinterpret_cast<uint32_t*>(p + d.dec_bytes + d.sym_bytes);
+    d.enc = reinterpret_cast<uint4*>(p + d.dec_bytes + d.sym_bytes + d.fc_bytes);
+    std::vector<uint8_t> host(total);
+    std::memcpy(host.data(), h_dec.data(), d.dec_bytes);
+    std::memcpy(host.data() + d.dec_bytes, h_sym.data(), d.sym_bytes);
+    std::memcpy(host.data() + d.dec_bytes + d.sym_bytes, h_fc.data(), d.fc_bytes);
+    std::memcpy(host.data() + d.dec_bytes + d.sym_bytes + d.fc_bytes, h_enc.data(),
+                d.enc_bytes);
+    if (hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(blob);
+        delete t;
+        return RANS_EDEVICE;
+    }
+    t->dev = d;
+    *out = t;
+    return RANS_OK;
+}
+
+extern "C" int rans_table_freqs(const rans_table* table, uint32_t* freqs_out)
+{
+    if (!table || !freqs_out)
+        return RANS_EINVAL;
+    std::memcpy(freqs_out, table->freq.data(), table->freq.size() * sizeof(uint32_t));
+    return RANS_OK;
+}
+
+extern "C" uint32_t rans_table_alphabet(const rans_table* table)
+{
+    return table ? table->dev.alphabet : 0;
+}
+
+extern "C" uint32_t rans_table_prob_bits(const rans_table* table)
+{
+    return table ? table->dev.k : 0;
+}
+
+extern "C" void rans_table_destroy(rans_table* table)
+{
+    if (!table)
+        return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(table->device);
+    (void)hipFree(table->dev.dec);  // start of the single allocation
+    (void)hipSetDevice(cur);
+    delete table;
+}
+
+// Host-side check of the division constants (not part of the C ABI header):
+// for every f in [1, fmax] compares the Granlund-Montgomery quotient with
+// x / f at the bounds, at multiples of f and at `samples` pseudo-random x.
+// Returns the number of mismatches.
+extern "C" uint64_t rans_internal_check_division(uint32_t fmax, uint32_t samples)
+{
+    uint64_t bad = 0, seed = 0x9E3779B97F4A7C15ull;
+    for (uint32_t f = 1; f <= fmax; ++f) {
+        uint32_t magic, sh1, sh2;
+        gm_constants(f, &magic, &sh1, &sh2);
+        auto chk = [&](uint32_t x) { bad += gm_divide(x, magic, sh1, sh2) != x / f; };
+        chk(0);
+        chk(0xFFFFFFFFu);
+        chk(0xFFFFFFFFu - f);
+        for (uint64_t m = f; m < (1ull << 32); m += (uint64_t(f) << 12) + f) {
+            chk(static_cast<uint32_t>(m));
+            chk(static_cast<uint32_t>(m - 1));
+        }
+        for (uint32_t i = 0; i < samples; ++i) {
+            seed ^= seed << 13;
+            seed ^= seed >> 7;
+            seed ^= seed << 17;
+            chk(static_cast<uint32_t>(seed));
+        }
+    }
+    return bad;
+}

@@ -1,0 +1,73 @@
+#include "workspace.h"
+
+#include <map>
+#include <utility>
+
+namespace rans {
+
+static std::mutex g_mu;
+static std::map<std::pair<int, hipStream_t>, Workspace*> g_ws;
+
+Workspace* workspace_for(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = g_ws.find(key);
+    if (it != g_ws.end())
+        return it->second;
+    Workspace* w = new Workspace();
+    w->device = dev;
+    w->stream = stream;
+    if (hipHostMalloc(&w->host, 4096, hipHostMallocDefault) != hipSuccess) {
+        delete w;
+        return nullptr;
+    }
+    g_ws[key] = w;
+    return w;
+}
+
+int Workspace::reserve(uint64_t need)
+{
+    if (need <= bytes)
+        return RANS_OK;
+    if (dev) {
+        if (hipStreamSynchronize(stream) != hipSuccess)
+            return RANS_EDEVICE;
+        (void)hipFree(dev);
+        dev = nullptr;
+        bytes = 0;
+    }
+    // grow geometrically so that a sequence of slightly larger calls does
+    // not reallocate every time
+    uint64_t want = need + need / 4;
+    if (hipMalloc(&dev, want) != hipSuccess) {
+        dev = nullptr;
+        if (hipMalloc(&dev, need) != hipSuccess) {
+            dev = nullptr;
+            (void)hipGetLastError();
+            return RANS_ENOMEM;
+        }
+        want = need;
+    }
+    bytes = want;
+    return RANS_OK;
+}
+
+static uint64_t up256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+EncodeLayout encode_layout(uint64_t n_chunks, uint32_t N, uint64_t slot_bytes)
+{
+    EncodeLayout l;
+    l.flags = 0;
+    l.ndig = 256;
+    l.chunk_off = up256(l.ndig + 4 * n_chunks);
+    l.states = up256(l.chunk_off + 8 * n_chunks);
+    l.slots = up256(l.states + 4ull * N * n_chunks);
+    l.total = up256(l.slots + slot_bytes * n_chunks);
+    return l;
+}
+
+}  // namespace rans

@@ -1,0 +1,54 @@
+// Per-(device, stream) device workspace and host-side helpers shared by the
+// single-buffer and batched entry points.
+#pragma once
+
+#include <mutex>
+
+#include "rans_internal.h"
+
+namespace rans {
+
+// Device scratch owned by the library, one per (device, HIP stream), so that
+// calls on different streams never share scratch.  Grows on demand; growth
+// waits for the stream first, since earlier work may still use the old
+// buffer.  `host` is a small pinned buffer for status read-back.
+struct Workspace {
+    std::mutex mu;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void* dev = nullptr;
+    uint64_t bytes = 0;
+    void* host = nullptr;  // 4 KiB pinned
+    int reserve(uint64_t need);
+};
+
+Workspace* workspace_for(hipStream_t stream);
+
+struct Header {
+    rans_params p;
+    uint64_t n;
+    uint32_t n_chunks;
+};
+
+// Byte offsets inside the workspace for one encode call.
+struct EncodeLayout {
+    uint64_t flags;      // 16 B: u32 error bits, pad, u64 container length
+    uint64_t ndig;       // n_chunks u32
+    uint64_t chunk_off;  // n_chunks u64
+    uint64_t states;     // n_chunks * N u32
+    uint64_t slots;      // n_chunks * slot_bytes
+    uint64_t total;
+};
+
+EncodeLayout encode_layout(uint64_t n_chunks, uint32_t N, uint64_t slot_bytes);
+
+int check_params(const rans_params* p);
+uint32_t log2u(uint32_t v);
+uint32_t max_digits(uint32_t k, uint32_t r);
+uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r);
+void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch);
+int parse_header(const uint8_t* h, uint64_t in_len, Header* out);
+bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds);
+void fill_decode_tables(const DevTable& t, Layout layout, DecodeArgs* a);
+
+}  // namespace rans
