@@ -214,6 +214,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->enc = t.enc;
     ea->enc_bytes = static_cast<uint32_t>(t.enc_bytes);
     ea->slot_bytes = sb;
+    ea->slot_stride = sb + 128;
 
     *sa = ScanArgs{};
     sa->n_chunks = nch;
@@ -224,6 +225,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
 
     *ca = CompactArgs{};
     ca->slot_bytes = sb;
+    ca->slot_stride = sb + 128;
     ca->n_chunks = nch;
     ca->N = N;
     ca->digit_bytes = R / 8;
@@ -253,13 +255,21 @@ static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactA
     ca->total = sa->total;
 }
 
+// The N = 64 kernels move symbols in 16-byte pieces: every chunk must start
+// 16-byte aligned in the symbol buffer.
+static bool fast64(uint32_t N, uint32_t C, uint32_t W, const void* syms)
+{
+    return N == 64 && (uint64_t(C) * W) % 16 == 0 && (reinterpret_cast<uintptr_t>(syms) & 15) == 0;
+}
+
 static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
                                  int R, int W, hipStream_t st)
 {
     hipError_t e;
     {
         TimingScope ts(RANS_KERNEL_ENCODE, st);
-        e = launch_encode(ea, R, W, st);
+        e = fast64(ea.N, ea.C, W, ea.syms) ? launch_encode64(ea, R, W, st)
+                                           : launch_encode(ea, R, W, st);
     }
     if (e == hipSuccess) {
         TimingScope ts(RANS_KERNEL_SCAN, st);
@@ -275,7 +285,8 @@ static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const
 static hipError_t enqueue_decode(const DecodeArgs& da, int R, int W, Layout layout, hipStream_t st)
 {
     TimingScope ts(RANS_KERNEL_DECODE, st);
-    return launch_decode(da, R, W, layout, st);
+    return fast64(da.N, da.C, W, da.out) ? launch_decode64(da, R, W, layout, st)
+                                         : launch_decode(da, R, W, layout, st);
 }
 
 extern "C" int rans_encode_async(const rans_table* table, const rans_params* params,

@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
         nsym = static_cast<uint32_t>(a.n - first < a.C ? a.n - first : a.C);
     }
     const uint32_t cap = static_cast<uint32_t>(a.slot_bytes / (R / 8));  // digits per slot
-    uint8_t* slot = a.slots + (ok ? g.chunk : 0) * a.slot_bytes;
+    uint8_t* slot = a.slots + (ok ? g.chunk : 0) * a.slot_stride;
     const InT* in = static_cast<const InT*>(a.syms) + (ok ? g.chunk * a.C : 0);
 
     uint32_t steps = (nsym + N - 1) / N;
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(256) k_compact(const CompactArgs a)
         const uint64_t off = a.chunk_off[c];
         const uint32_t pay = a.ndig[c] * a.digit_bytes;
         const uint32_t words = static_cast<uint32_t>(align16(4ull * a.N + pay) / 4);
-        const uint8_t* slot_end = a.slots + (uint64_t(c) + 1) * a.slot_bytes;
+        const uint8_t* slot_end = a.slots + uint64_t(c) * a.slot_stride + a.slot_bytes;
         const uint8_t* src = slot_end - pay;
         uint32_t* dst = reinterpret_cast<uint32_t*>(a.out + off);
         for (uint32_t q = threadIdx.x; q < words; q += blockDim.x) {

@@ -70,8 +70,10 @@ struct EncodeArgs {
     uint32_t alphabet;
     const uint4* enc;     // alphabet + 1 entries
     uint32_t enc_bytes;   // multiple of 16
-    uint8_t* slots;       // n_chunks slots of slot_bytes, digits end at slot end
-    uint64_t slot_bytes;  // multiple of 16
+    uint8_t* slots;       // n_chunks slots, slot_stride apart
+    uint64_t slot_bytes;  // digit capacity of a slot in bytes (multiple of 16);
+                          // digits end at slot + slot_bytes
+    uint64_t slot_stride; // slot_bytes + 128-byte junk area for idle lanes
     uint32_t* states;     // n_chunks * N final states
     uint32_t* ndig;       // n_chunks digit counts
     int32_t* status;
@@ -94,6 +96,7 @@ struct ScanArgs {
 struct CompactArgs {
     const uint8_t* slots;
     uint64_t slot_bytes;
+    uint64_t slot_stride;
     const uint32_t* states;
     const uint32_t* ndig;
     const uint64_t* chunk_off;
@@ -109,6 +112,11 @@ struct CompactArgs {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint32_t count, hipStream_t stream);
 hipError_t launch_decode(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
 hipError_t launch_encode(const EncodeArgs& a, int R, int W, hipStream_t stream);
+// N = 64 fast paths (decode64.hip / encode64.hip); need (C * w) % 16 == 0 and
+// 16-byte aligned symbol buffers.
+hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
+hipError_t launch_encode64(const EncodeArgs& a, int R, int W, hipStream_t stream);
+uint32_t decode64_lds_per_wave();
 hipError_t launch_scan(const ScanArgs& a, hipStream_t stream);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t stream);
 
