@@ -63,6 +63,11 @@ CASES = [
     (2, "dominant", 15, 8, 23, 32, 4096, 300_000),
     (256, "zipf", 14, 16, 16, 64, 1, 300),
     (256, "zipf", 14, 16, 16, 64, 100, 1_001),
+    # last chunk = 15 full steps + a partial one: the ragged step closes an
+    # output block of the N = 64 decoder
+    (256, "zipf", 12, 16, 16, 64, 1024, 5 * 1024 + 992),
+    (4096, "near_uniform", 15, 16, 16, 64, 2048, 3 * 2048 + 480),
+    (256, "zipf", 12, 8, 23, 64, 1024, 5 * 1024 + 960),
 ]
 
 
