@@ -40,7 +40,26 @@ def parse():
     ap.add_argument("--size-log2", type=int, default=28, help="symbols per buffer (log2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for
+    1 GiB in and 1 GiB out calibrates the counters used for traffic."""
+    import torch
+    src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    gbps = 10 * 2 * src.numel() / (time.perf_counter() - t0) / 1e9
+    print(json.dumps({"copy_probe_bytes": src.numel(), "copy_gbps": round(gbps, 1)}), flush=True)
 
 
 def cpu_baseline(work, threads):
@@ -75,6 +94,10 @@ def main():
         print("bench.py measures one MI355X only: the coder's work is independent per "
               "chunk and this build runs no multi-GPU path (--gpus 1).", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import numpy as np
     import torch
