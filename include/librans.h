@@ -197,6 +197,122 @@ int rans_encode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *p
 int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *params,
                       void *stream);
 
+/* Launch shape of the batched entry points (process-wide; the autotuner
+ * sets it).  waves_per_group: chunks one work item covers, i.e. waves per
+ * persistent block sharing one staged table (1..16); groups_per_cu:
+ * persistent blocks per compute unit (1..8); table_layout: decode table
+ * layout in LDS, 0 = automatic, 1 = per-slot packed entries, 2 = symbol map
+ * plus per-symbol entries; use_graph: replay the batch as a captured HIP
+ * graph (1) or launch its kernels directly (0).  The batched kernels code
+ * 64 interleaved coders per chunk (params->interleave == 64); batched encode
+ * needs chunk_syms != 0 with chunk_syms * sym_bytes a multiple of 16, and
+ * every buffer 16-byte aligned.  Batched calls on a stream that is being
+ * captured launch directly (no nested graph). */
+typedef struct rans_batch_config {
+    uint32_t waves_per_group;
+    uint32_t groups_per_cu;
+    uint32_t table_layout;
+    uint32_t use_graph;
+} rans_batch_config;
+int rans_batch_set_config(const rans_batch_config *cfg);
+int rans_batch_get_config(rans_batch_config *cfg);
+
+/* Autotuner.  Times the batched kernels on a sample (d_syms[n_syms],
+ * device, 16-byte aligned, coded with `table` and base's k, r, l, w) over
+ * chunk sizes C in {4096 .. 65536} (chosen at encode time, written into
+ * the container) and decode launch shapes (waves per work item, blocks per
+ * CU, table layout), with 64 coders per chunk.  A candidate's score is its
+ * encode + decode time, penalised when its container exceeds the 64 KiB-
+ * chunk container by more than 1%.  The best shape becomes the process-wide
+ * rans_batch_config; *out reports it with the measured rates.  Results are
+ * appended to cache_path (text, one line per device / parameter / alphabet
+ * class / size class; NULL disables the cache) and reused on a hit. */
+typedef struct rans_tune_result {
+    uint32_t chunk_syms;
+    uint32_t waves_per_group;
+    uint32_t groups_per_cu;
+    uint32_t table_layout;
+    double encode_gbps;
+    double decode_gbps;
+} rans_tune_result;
+int rans_autotune(const rans_table *table, const void *d_syms, uint64_t n_syms,
+                  const rans_params *base, const char *cache_path, rans_tune_result *out);
+
+/* ---------------------------------------------------------------- serving --
+ * Continuous-batching request server.  Requests (encode or decode of one
+ * device-resident buffer, each with its own table) are admitted first come
+ * first served while the sum of their costs (input + output capacity +
+ * encode scratch of about 2 bytes per symbol) fits hbm_budget; admitted
+ * requests are launched as batched persistent kernels on whichever of the
+ * server's `streams` is idle, up to max_batch per launch, so requests that
+ * arrive while others run are launched alongside them.  Outputs live in a
+ * device arena of hbm_budget bytes allocated once by rans_server_create; the
+ * serving loop itself allocates no device memory.  All requests use
+ * config->params (decode: the containers must carry those parameters;
+ * interleave must be 64).  The calls are thread-safe. */
+#define RANS_OP_ENCODE 0
+#define RANS_OP_DECODE 1
+
+typedef struct rans_server rans_server;
+
+typedef struct rans_server_config {
+    uint64_t hbm_budget; /* bytes, >= 1 MiB */
+    uint32_t streams;    /* 1..16 */
+    uint32_t max_batch;  /* requests per launch, >= 1 */
+    rans_params params;
+} rans_server_config;
+
+/* One finished request.  d_out (device, inside the server's arena) holds
+ * out_len bytes (encode: the container) or symbols (decode) until the
+ * request is released (immediately, unless polled with keep_outputs).
+ * latency_us: arrival to completion seen by the host; queue_us: arrival to
+ * launch. */
+typedef struct rans_completion {
+    uint64_t id;
+    int32_t status;
+    int32_t op;
+    uint64_t in_len;
+    uint64_t out_len;
+    void *d_out;
+    double latency_us;
+    double queue_us;
+} rans_completion;
+
+typedef struct rans_server_stats_t {
+    uint64_t budget, used, peak;
+    uint32_t waiting, ready, busy_streams, reserved;
+} rans_server_stats_t;
+
+/* A request of an arrival schedule for rans_server_replay. */
+typedef struct rans_server_request {
+    int32_t op;
+    uint32_t reserved;
+    const rans_table *table;
+    const void *d_in;
+    uint64_t in_len;     /* bytes */
+    uint64_t out_cap;    /* bytes */
+    double arrival_us;   /* from the start of the replay, non-decreasing */
+} rans_server_request;
+
+int rans_server_create(const rans_server_config *config, rans_server **out);
+void rans_server_destroy(rans_server *server);
+/* Queues a request (RANS_ENOMEM if its cost alone exceeds the budget). */
+int rans_server_submit(rans_server *server, int op, const rans_table *table, const void *d_in,
+                       uint64_t in_len, uint64_t out_cap, uint64_t *id);
+/* Advances the server (collects finished launches, admits, launches) and
+ * returns up to max_out completions. */
+int rans_server_poll(rans_server *server, int keep_outputs, rans_completion *out, uint32_t max_out,
+                     uint32_t *n_out);
+/* Frees a kept output. */
+int rans_server_release(rans_server *server, uint64_t id);
+int rans_server_stats(rans_server *server, rans_server_stats_t *stats);
+/* Submits reqs[i] at its arrival time (microseconds after the call), polls
+ * until all have completed, and stores request i's completion in results[i];
+ * *makespan_us receives the elapsed time.  RANS_ENOMEM if kept outputs make
+ * the remaining requests impossible to admit. */
+int rans_server_replay(rans_server *server, const rans_server_request *reqs, uint32_t n,
+                       int keep_outputs, rans_completion *results, double *makespan_us);
+
 /* Kernel timing (diagnostics).  While enabled, every kernel launch the
  * library makes is bracketed by two HIP events recorded on the stream it is
  * launched on.  rans_timing_read waits for the recorded events and returns

@@ -41,12 +41,49 @@ class rans_params(ct.Structure):
         return cls(k, r, l, w, N, 0, C)
 
 
+class rans_batch_config(ct.Structure):
+    """Mirror of the C struct rans_batch_config."""
+    _fields_ = [("waves_per_group", ct.c_uint32), ("groups_per_cu", ct.c_uint32),
+                ("table_layout", ct.c_uint32), ("use_graph", ct.c_uint32)]
+
+
+class rans_tune_result(ct.Structure):
+    _fields_ = [("chunk_syms", ct.c_uint32), ("waves_per_group", ct.c_uint32),
+                ("groups_per_cu", ct.c_uint32), ("table_layout", ct.c_uint32),
+                ("encode_gbps", ct.c_double), ("decode_gbps", ct.c_double)]
+
+
 class rans_job(ct.Structure):
     """Mirror of the C struct rans_job."""
     _fields_ = [("table", ct.c_void_p), ("in_", ct.c_void_p), ("in_len", ct.c_uint64),
                 ("out", ct.c_void_p), ("out_cap", ct.c_uint64),
                 ("d_out_len", ct.c_void_p), ("d_status", ct.c_void_p)]
 
+
+class rans_server_config(ct.Structure):
+    _fields_ = [("hbm_budget", ct.c_uint64), ("streams", ct.c_uint32), ("max_batch", ct.c_uint32),
+                ("params", rans_params)]
+
+
+class rans_completion(ct.Structure):
+    _fields_ = [("id", ct.c_uint64), ("status", ct.c_int32), ("op", ct.c_int32),
+                ("in_len", ct.c_uint64), ("out_len", ct.c_uint64), ("d_out", ct.c_void_p),
+                ("latency_us", ct.c_double), ("queue_us", ct.c_double)]
+
+
+class rans_server_stats_t(ct.Structure):
+    _fields_ = [("budget", ct.c_uint64), ("used", ct.c_uint64), ("peak", ct.c_uint64),
+                ("waiting", ct.c_uint32), ("ready", ct.c_uint32), ("busy_streams", ct.c_uint32),
+                ("reserved", ct.c_uint32)]
+
+
+class rans_server_request(ct.Structure):
+    _fields_ = [("op", ct.c_int32), ("reserved", ct.c_uint32), ("table", ct.c_void_p),
+                ("d_in", ct.c_void_p), ("in_len", ct.c_uint64), ("out_cap", ct.c_uint64),
+                ("arrival_us", ct.c_double)]
+
+
+RANS_OP_ENCODE, RANS_OP_DECODE = 0, 1
 
 _u64p = ct.POINTER(ct.c_uint64)
 _u32p = ct.POINTER(ct.c_uint32)
@@ -71,6 +108,21 @@ _sig = {
     "rans_encode_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_void_p]),
     "rans_decode_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_void_p]),
     "rans_strerror": (ct.c_char_p, [ct.c_int]),
+    "rans_batch_set_config": (ct.c_int, [ct.POINTER(rans_batch_config)]),
+    "rans_autotune": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, _P, ct.c_char_p,
+                                 ct.POINTER(rans_tune_result)]),
+    "rans_server_create": (ct.c_int, [ct.POINTER(rans_server_config), ct.POINTER(ct.c_void_p)]),
+    "rans_server_destroy": (None, [ct.c_void_p]),
+    "rans_server_submit": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_uint64,
+                                      ct.c_uint64, _u64p]),
+    "rans_server_poll": (ct.c_int, [ct.c_void_p, ct.c_int, ct.POINTER(rans_completion), ct.c_uint32,
+                                    ct.POINTER(ct.c_uint32)]),
+    "rans_server_release": (ct.c_int, [ct.c_void_p, ct.c_uint64]),
+    "rans_server_stats": (ct.c_int, [ct.c_void_p, ct.POINTER(rans_server_stats_t)]),
+    "rans_server_replay": (ct.c_int, [ct.c_void_p, ct.POINTER(rans_server_request), ct.c_uint32,
+                                      ct.c_int, ct.POINTER(rans_completion),
+                                      ct.POINTER(ct.c_double)]),
+    "rans_batch_get_config": (ct.c_int, [ct.POINTER(rans_batch_config)]),
     "rans_timing_enable": (ct.c_int, [ct.c_int]),
     "rans_timing_reset": (ct.c_int, []),
     "rans_timing_read": (ct.c_int, [ct.c_int, _u64p, ct.POINTER(ct.c_double)]),
@@ -243,6 +295,80 @@ def rans_encode_batch(jobs, njobs: int, params, stream=None):
 def rans_decode_batch(jobs, njobs: int, params, stream=None):
     p = _params(params)
     _check(_lib.rans_decode_batch(jobs, njobs, ct.byref(p), _stream(stream)), "rans_decode_batch")
+
+
+def rans_batch_set_config(waves_per_group: int = 16, groups_per_cu: int = 1,
+                          table_layout: int = 0, use_graph: int = 1):
+    cfg = rans_batch_config(waves_per_group, groups_per_cu, table_layout, use_graph)
+    _check(_lib.rans_batch_set_config(ct.byref(cfg)), "rans_batch_set_config")
+
+
+def rans_batch_get_config() -> dict:
+    cfg = rans_batch_config()
+    _check(_lib.rans_batch_get_config(ct.byref(cfg)), "rans_batch_get_config")
+    return {f: int(getattr(cfg, f)) for f, _ in cfg._fields_}
+
+
+def rans_autotune(table: Table, d_syms, n_syms: int, params, cache_path: str | None = None):
+    """Tunes chunk size and batched decode shape on a device sample; returns a dict."""
+    p = _params(params)
+    r = rans_tune_result()
+    cp = cache_path.encode() if cache_path else None
+    _check(_lib.rans_autotune(table.handle, _ptr(d_syms), n_syms, ct.byref(p), cp, ct.byref(r)),
+           "rans_autotune")
+    return {f: getattr(r, f) for f, _ in r._fields_}
+
+
+# ---------------------------------------------------------------- serving --
+
+def rans_server_create(hbm_budget: int, streams: int, max_batch: int, params):
+    cfg = rans_server_config(hbm_budget, streams, max_batch, _params(params))
+    h = ct.c_void_p()
+    _check(_lib.rans_server_create(ct.byref(cfg), ct.byref(h)), "rans_server_create")
+    return h.value
+
+
+def rans_server_destroy(server):
+    _lib.rans_server_destroy(server)
+
+
+def rans_server_submit(server, op: int, table: Table, d_in, in_len: int, out_cap: int) -> int:
+    rid = ct.c_uint64()
+    _check(_lib.rans_server_submit(server, op, table.handle, _ptr(d_in), in_len, out_cap,
+                                   ct.byref(rid)), "rans_server_submit")
+    return int(rid.value)
+
+
+def rans_server_poll(server, keep_outputs: bool = False, max_out: int = 256):
+    arr = (rans_completion * max_out)()
+    n = ct.c_uint32()
+    _check(_lib.rans_server_poll(server, 1 if keep_outputs else 0, arr, max_out, ct.byref(n)),
+           "rans_server_poll")
+    return [arr[i] for i in range(n.value)]
+
+
+def rans_server_release(server, rid: int):
+    _check(_lib.rans_server_release(server, rid), "rans_server_release")
+
+
+def rans_server_stats(server) -> dict:
+    st = rans_server_stats_t()
+    _check(_lib.rans_server_stats(server, ct.byref(st)), "rans_server_stats")
+    return {f: int(getattr(st, f)) for f, _ in st._fields_}
+
+
+def rans_server_replay(server, requests, keep_outputs: bool = False):
+    """requests: list of (op, table, d_in, in_len, out_cap, arrival_us).
+    Returns (list of rans_completion in request order, makespan_us)."""
+    n = len(requests)
+    arr = (rans_server_request * max(n, 1))()
+    for i, (op, tab, din, inl, cap, t) in enumerate(requests):
+        arr[i] = rans_server_request(op, 0, tab.handle, _ptr(din), inl, cap, float(t))
+    res = (rans_completion * max(n, 1))()
+    mk = ct.c_double()
+    _check(_lib.rans_server_replay(server, arr, n, 1 if keep_outputs else 0, res, ct.byref(mk)),
+           "rans_server_replay")
+    return [res[i] for i in range(n)], float(mk.value)
 
 
 # ------------------------------------------------------------------ timing --

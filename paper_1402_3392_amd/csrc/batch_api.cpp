@@ -1,0 +1,288 @@
+// Batched entry points: host validation of the job descriptors, workspace
+// layout, and one HIP graph per launch image (captured on first use, then
+// replayed: one graph launch per batch).  The job descriptors are the only
+// per-call input; they are copied into the workspace ahead of the replay.
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rans_internal.h"
+#include "timing.h"
+#include "workspace.h"
+
+namespace rans {
+namespace {
+
+std::mutex g_cfg_mu;
+rans_batch_config g_cfg = {16, 1, 0, 1};
+
+uint64_t up256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+int num_cus()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+        return 256;
+    return v;
+}
+
+struct Region {
+    uint64_t ctrl, jobs, item_job, chunk_job, slots, states, ndig, chunk_off, total;
+};
+
+Region layout_for(uint32_t njobs, uint64_t max_items, uint64_t max_chunks, uint64_t slot_stride)
+{
+    Region r{};
+    r.ctrl = 0;  // counter + totals
+    r.jobs = 256;
+    r.item_job = up256(r.jobs + sizeof(BatchJob) * uint64_t(njobs));
+    r.chunk_job = up256(r.item_job + 4 * max_items);
+    r.slots = up256(r.chunk_job + 4 * max_chunks);
+    r.states = up256(r.slots + slot_stride * max_chunks);
+    r.ndig = up256(r.states + 256 * max_chunks);
+    r.chunk_off = up256(r.ndig + 4 * max_chunks);
+    r.total = up256(r.chunk_off + 8 * max_chunks);
+    return r;
+}
+
+}  // namespace
+
+int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
+              bool decode, const rans_batch_config* cfg_override)
+{
+    int rc = check_params(params);
+    if (rc != RANS_OK)
+        return rc;
+    if (!jobs && njobs)
+        return RANS_EINVAL;
+    const rans_params& p = *params;
+    const uint32_t w = p.sym_bytes, R = p.radix_bits;
+    // the batched kernels code one chunk per wave: 64 coders per chunk, and
+    // chunks must start 16-byte aligned in the symbol buffers
+    if (p.interleave != 64)
+        return RANS_EINVAL;
+    if (!decode && (p.chunk_syms == 0 || (uint64_t(p.chunk_syms) * w) % 16 != 0))
+        return RANS_EINVAL;
+    if (njobs == 0)
+        return RANS_OK;
+    rans_batch_config cfg;
+    if (cfg_override) {
+        cfg = *cfg_override;
+    } else {
+        std::lock_guard<std::mutex> lk(g_cfg_mu);
+        cfg = g_cfg;
+    }
+    const uint32_t G = cfg.waves_per_group;
+
+    // host checks of every descriptor and the launch shape they imply
+    uint64_t max_items = 0, max_chunks = 0;
+    uint32_t tab_lds = 0, sw = 0;
+    Layout layout = kPacked;
+    std::vector<BatchJob> hj(njobs);
+    for (uint32_t j = 0; j < njobs; ++j) {
+        const rans_job& jb = jobs[j];
+        const DevTable* t = dev_table(jb.table);
+        if (!t || t->k != p.prob_bits || !jb.d_out_len || !jb.d_status)
+            return RANS_EINVAL;
+        if ((jb.in_len && !jb.in) || (jb.out_cap && !jb.out) ||
+            (reinterpret_cast<uintptr_t>(jb.in) & 15) || (reinterpret_cast<uintptr_t>(jb.out) & 15))
+            return RANS_EINVAL;
+        if (w == 1 && t->sym_w != 1)
+            return RANS_EINVAL;
+        if (j == 0)
+            sw = t->sym_w;
+        else if (t->sym_w != sw)
+            return RANS_EINVAL;
+        BatchJob& b = hj[j];
+        std::memset(&b, 0, sizeof(b));
+        b.in = static_cast<const uint8_t*>(jb.in);
+        b.in_len = jb.in_len;
+        b.out = static_cast<uint8_t*>(jb.out);
+        b.out_cap = jb.out_cap;
+        b.d_out_len = jb.d_out_len;
+        b.d_status = jb.d_status;
+        b.alphabet = t->alphabet;
+        b.enc = t->enc;
+        b.enc_bytes = static_cast<uint32_t>(t->enc_bytes);
+        if (decode) {
+            Layout lj;
+            uint32_t lds;
+            if (!choose_layout(*t, &lj, &lds))
+                return RANS_EINVAL;
+            if (cfg.table_layout == 2 || (cfg.table_layout == 0 && j > 0 && lj != layout))
+                lj = kTwoLevel;
+            if (j == 0)
+                layout = lj;
+            else if (lj != layout)
+                layout = kTwoLevel;
+            // chunks cost at least a directory entry and 64 states
+            const uint64_t nch = jb.in_len >= kHeaderBytes ? (jb.in_len - kHeaderBytes) / (16 + 256) : 0;
+            max_items += (nch + G - 1) / G;
+        } else {
+            if (jb.in_len % w)
+                return RANS_EINVAL;
+            const uint64_t n = jb.in_len / w;
+            const uint64_t nch = (n + p.chunk_syms - 1) / p.chunk_syms;
+            if (nch > 0xFFFFFFFFull)
+                return RANS_EINVAL;
+            max_chunks += nch;
+            max_items += (nch + G - 1) / G;
+            tab_lds = tab_lds > b.enc_bytes ? tab_lds : b.enc_bytes;
+        }
+    }
+    if (decode) {
+        if (cfg.table_layout == 2)
+            layout = kTwoLevel;
+        for (uint32_t j = 0; j < njobs; ++j) {
+            const DevTable* t = dev_table(jobs[j].table);
+            BatchJob& b = hj[j];
+            if (layout == kPacked) {
+                b.tab_sym = t->sym;
+                b.sym_bytes = static_cast<uint32_t>(t->sym_bytes);
+                b.tab_ent = t->dec;
+                b.ent_bytes = static_cast<uint32_t>(t->dec_bytes);
+            } else {
+                b.tab_sym = t->sym;
+                b.sym_bytes = static_cast<uint32_t>(t->sym_bytes);
+                b.tab_ent = t->fc;
+                b.ent_bytes = static_cast<uint32_t>(t->fc_bytes);
+            }
+            tab_lds = tab_lds > b.sym_bytes + b.ent_bytes ? tab_lds : b.sym_bytes + b.ent_bytes;
+        }
+    }
+    if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull)
+        return RANS_EINVAL;
+    const uint32_t per_wave = decode ? decode64_lds_per_wave() : 1024;
+    if (uint64_t(tab_lds) + uint64_t(G) * per_wave > uint64_t(max_lds_bytes()))
+        return RANS_EINVAL;
+
+    const uint64_t slot_bytes = decode ? 0 : slot_bytes_for(p.chunk_syms, p.prob_bits, R);
+    const uint64_t slot_stride = decode ? 0 : slot_bytes + 128;
+    const Region rg = layout_for(njobs, max_items ? max_items : 1, max_chunks, slot_stride);
+
+    Workspace* ws = workspace_for(st);
+    if (!ws)
+        return RANS_ENOMEM;
+    std::lock_guard<std::mutex> lk(ws->mu);
+    if ((rc = ws->reserve(rg.total)) != RANS_OK)
+        return rc;
+    const uint64_t jb_bytes = sizeof(BatchJob) * uint64_t(njobs);
+    if ((rc = ws->reserve_pinned(jb_bytes)) != RANS_OK)
+        return rc;
+    uint8_t* base = static_cast<uint8_t*>(ws->dev);
+
+    BatchArgs a{};
+    a.jobs = reinterpret_cast<BatchJob*>(base + rg.jobs);
+    a.njobs = njobs;
+    a.k = p.prob_bits;
+    a.r = R;
+    a.l = p.state_lbits;
+    a.w = w;
+    a.N = p.interleave;
+    a.C = p.chunk_syms;
+    a.G = G;
+    a.counter = reinterpret_cast<uint32_t*>(base + rg.ctrl);
+    a.totals = a.counter + 4;
+    a.item_job = reinterpret_cast<uint32_t*>(base + rg.item_job);
+    a.chunk_job = reinterpret_cast<uint32_t*>(base + rg.chunk_job);
+    a.max_items = static_cast<uint32_t>(max_items ? max_items : 1);
+    a.max_chunks = static_cast<uint32_t>(max_chunks);
+    a.slots = base + rg.slots;
+    a.slot_bytes = slot_bytes;
+    a.slot_stride = slot_stride;
+    a.states = reinterpret_cast<uint32_t*>(base + rg.states);
+    a.ndig = reinterpret_cast<uint32_t*>(base + rg.ndig);
+    a.chunk_off = reinterpret_cast<uint64_t*>(base + rg.chunk_off);
+    a.tab_lds = (tab_lds + 15) & ~15u;
+    const uint32_t grid = static_cast<uint32_t>(num_cus()) * cfg.groups_per_cu;
+
+    // job descriptors -> pinned staging -> workspace, ordered on `st`
+    std::memcpy(ws->pinned, hj.data(), jb_bytes);
+    if (hipMemcpyAsync(a.jobs, ws->pinned, jb_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return RANS_EDEVICE;
+    if (!ws->staged && hipEventCreateWithFlags(&ws->staged, hipEventDisableTiming) != hipSuccess)
+        return RANS_EDEVICE;
+    if (hipEventRecord(ws->staged, st) != hipSuccess)
+        return RANS_EDEVICE;
+    ws->staged_pending = true;
+
+    const int kind = decode ? RANS_KERNEL_BATCH_DECODE : RANS_KERNEL_BATCH_ENCODE;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess)
+        return RANS_EDEVICE;
+    if (!cfg.use_graph || cap != hipStreamCaptureStatusNone) {
+        TimingScope ts(kind, st);
+        return launch_batch(a, decode, R, w, sw, layout, grid, st) == hipSuccess ? RANS_OK
+                                                                                 : RANS_EDEVICE;
+    }
+    // one graph per launch image: the kernel arguments and template choice
+    std::string key(reinterpret_cast<const char*>(&a), sizeof(a));
+    const int shape[5] = {decode ? 1 : 0, static_cast<int>(sw), static_cast<int>(layout),
+                          static_cast<int>(grid), static_cast<int>(R)};
+    key.append(reinterpret_cast<const char*>(shape), sizeof(shape));
+    auto it = ws->graphs.find(key);
+    if (it == ws->graphs.end()) {
+        if (!ws->capture && hipStreamCreateWithFlags(&ws->capture, hipStreamNonBlocking) != hipSuccess)
+            return RANS_EDEVICE;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (hipStreamBeginCapture(ws->capture, hipStreamCaptureModeRelaxed) != hipSuccess)
+            return RANS_EDEVICE;
+        const hipError_t le = launch_batch(a, decode, R, w, sw, layout, grid, ws->capture);
+        const hipError_t ce = hipStreamEndCapture(ws->capture, &graph);
+        if (le != hipSuccess || ce != hipSuccess || !graph) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return RANS_EDEVICE;
+        }
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess)
+            return RANS_EDEVICE;
+        it = ws->graphs.emplace(key, exec).first;
+    }
+    TimingScope ts(kind, st);
+    return hipGraphLaunch(it->second, st) == hipSuccess ? RANS_OK : RANS_EDEVICE;
+}
+
+rans_batch_config batch_config()
+{
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    return g_cfg;
+}
+
+}  // namespace rans
+
+using namespace rans;
+
+extern "C" int rans_encode_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params,
+                                 void* stream)
+{
+    return run_batch(jobs, njobs, params, static_cast<hipStream_t>(stream), false, nullptr);
+}
+
+extern "C" int rans_decode_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params,
+                                 void* stream)
+{
+    return run_batch(jobs, njobs, params, static_cast<hipStream_t>(stream), true, nullptr);
+}
+
+extern "C" int rans_batch_set_config(const rans_batch_config* cfg)
+{
+    if (!cfg || cfg->waves_per_group < 1 || cfg->waves_per_group > 16 || cfg->groups_per_cu < 1 ||
+        cfg->groups_per_cu > 8 || cfg->table_layout > 2)
+        return RANS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    g_cfg = *cfg;
+    return RANS_OK;
+}
+
+extern "C" int rans_batch_get_config(rans_batch_config* cfg)
+{
+    if (!cfg)
+        return RANS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    *cfg = g_cfg;
+    return RANS_OK;
+}

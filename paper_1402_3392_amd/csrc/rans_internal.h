@@ -108,6 +108,45 @@ struct CompactArgs {
     uint64_t out_cap;
 };
 
+// One job of a batch, device-resident (written by the host, then completed
+// by the planning kernel).
+struct BatchJob {
+    const uint8_t* in;     // decode: container; encode: symbols
+    uint64_t in_len;       // bytes
+    uint8_t* out;          // decode: symbols; encode: container
+    uint64_t out_cap;      // bytes
+    uint64_t* d_out_len;
+    int32_t* d_status;
+    const void* tab_sym;   // decode tables of the batch's layout
+    const void* tab_ent;
+    const uint4* enc;      // encoder entries (alphabet + 1)
+    uint32_t sym_bytes, ent_bytes, enc_bytes, alphabet;
+    // plan
+    uint64_t n;            // symbols
+    uint64_t total;        // encode: container length
+    uint32_t C, nch;       // symbols per chunk, chunks (0 when the job failed)
+    uint32_t item_base;    // first work item
+    uint32_t chunk_base;   // first global chunk (encode slots)
+};
+
+struct BatchArgs {
+    BatchJob* jobs;
+    uint32_t njobs;
+    uint32_t k, r, l, w, N, C;  // C: encode chunk size (0 = whole input)
+    uint32_t G;                 // chunks per work item = waves per block
+    uint32_t* counter;          // work-queue head, zeroed before the pass
+    uint32_t* totals;           // [0] work items, [1] chunks
+    uint32_t* item_job;         // work item -> job
+    uint32_t* chunk_job;        // global chunk -> job (encode)
+    uint32_t max_items, max_chunks;
+    uint8_t* slots;             // encode: one slot per global chunk
+    uint64_t slot_bytes, slot_stride;
+    uint32_t* states;           // encode: 64 per global chunk
+    uint32_t* ndig;
+    uint64_t* chunk_off;
+    uint32_t tab_lds;           // LDS bytes reserved for the largest table
+};
+
 // Launchers (kernels.hip).  All asynchronous on `stream`.
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint32_t count, hipStream_t stream);
 hipError_t launch_decode(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
@@ -117,6 +156,10 @@ hipError_t launch_encode(const EncodeArgs& a, int R, int W, hipStream_t stream);
 hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
 hipError_t launch_encode64(const EncodeArgs& a, int R, int W, hipStream_t stream);
 uint32_t decode64_lds_per_wave();
+
+// Batched pass (batch.hip).  `decode` selects the direction.
+hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, Layout layout,
+                        uint32_t grid, hipStream_t stream);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t stream);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t stream);
 

@@ -29,6 +29,35 @@ Workspace* workspace_for(hipStream_t stream)
     return w;
 }
 
+void Workspace::drop_graphs()
+{
+    for (auto& g : graphs)
+        (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+}
+
+int Workspace::reserve_pinned(uint64_t need)
+{
+    if (staged_pending) {
+        if (hipEventSynchronize(staged) != hipSuccess)
+            return RANS_EDEVICE;
+        staged_pending = false;
+    }
+    if (need <= pinned_bytes)
+        return RANS_OK;
+    if (pinned)
+        (void)hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_bytes = 0;
+    const uint64_t want = need + need / 2 + 4096;
+    if (hipHostMalloc(&pinned, want, hipHostMallocDefault) != hipSuccess) {
+        pinned = nullptr;
+        return RANS_ENOMEM;
+    }
+    pinned_bytes = want;
+    return RANS_OK;
+}
+
 int Workspace::reserve(uint64_t need)
 {
     if (need <= bytes)
@@ -36,6 +65,7 @@ int Workspace::reserve(uint64_t need)
     if (dev) {
         if (hipStreamSynchronize(stream) != hipSuccess)
             return RANS_EDEVICE;
+        drop_graphs();  // they hold pointers into the old buffer
         (void)hipFree(dev);
         dev = nullptr;
         bytes = 0;

@@ -2,7 +2,9 @@
 // single-buffer and batched entry points.
 #pragma once
 
+#include <map>
 #include <mutex>
+#include <string>
 
 #include "rans_internal.h"
 
@@ -19,7 +21,17 @@ struct Workspace {
     void* dev = nullptr;
     uint64_t bytes = 0;
     void* host = nullptr;  // 4 KiB pinned
+    // batched calls: pinned staging for job descriptors, the event that says
+    // the last copy out of it has finished, captured graphs by launch image
+    void* pinned = nullptr;
+    uint64_t pinned_bytes = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    hipStream_t capture = nullptr;
+    std::map<std::string, hipGraphExec_t> graphs;
     int reserve(uint64_t need);
+    int reserve_pinned(uint64_t need);
+    void drop_graphs();
 };
 
 Workspace* workspace_for(hipStream_t stream);
@@ -49,6 +61,9 @@ uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r);
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch);
 int parse_header(const uint8_t* h, uint64_t in_len, Header* out);
 bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds);
+int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
+              bool decode, const rans_batch_config* cfg_override);
+rans_batch_config batch_config();
 void fill_decode_tables(const DevTable& t, Layout layout, DecodeArgs* a);
 
 }  // namespace rans

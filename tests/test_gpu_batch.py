@@ -1,0 +1,196 @@
+"""GPU parity of the batched entry points (persistent kernel + HIP graph).
+
+Every job of a batch is checked against the oracle byte for byte (encode)
+and symbol for symbol (decode); a failing job must fail alone; graph replays
+with new data in the same shapes must stay exact.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from rans_util import first_diff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lr():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1402_3392_amd as m
+    m.rans_batch_set_config(16, 1, 0, 1)
+    return m
+
+
+def streams(nstreams, seed, lo=10, hi=17):
+    """Uint8 streams of log-uniform length with Dirichlet(alpha) tables."""
+    return datagen.config4_streams(nstreams=nstreams, lo_log2=lo, hi_log2=hi, seed=seed)
+
+
+class Pool:
+    """Carves 256-byte aligned pieces out of one device allocation."""
+
+    def __init__(self, nbytes):
+        import torch
+        self.buf = torch.zeros(nbytes + 4096, dtype=torch.uint8, device="cuda")
+        self.base = int(self.buf.data_ptr())
+        self.off = 0
+
+    def take(self, nbytes):
+        a = self.base + self.off
+        self.off += (max(nbytes, 1) + 255) // 256 * 256
+        assert self.off <= self.buf.numel()
+        return a
+
+    def put(self, addr, arr):
+        raw = np.ascontiguousarray(arr).view(np.uint8).reshape(-1)
+        import torch
+        o = addr - self.base
+        self.buf[o:o + raw.size].copy_(torch.from_numpy(raw.copy()))
+
+    def get(self, addr, nbytes):
+        o = addr - self.base
+        return self.buf[o:o + nbytes].cpu().numpy()
+
+
+def run_encode_batch(lr, data, k, r, l, C, cap_override=None):
+    import torch
+    params = lr.rans_params.make(k, r, l, 1, 64, C)
+    tables, specs = [], []
+    total = sum(s.size for s, _ in data)
+    pool = Pool(sum(lr.rans_encode_bound(s.size, params) + s.size + 1024 for s, _ in data))
+    lens = torch.zeros(len(data), dtype=torch.int64, device="cuda")
+    st = torch.full((len(data),), 99, dtype=torch.int32, device="cuda")
+    for i, (s, _) in enumerate(data):
+        t = lr.rans_tables_build(datagen.counts(s, 256), k)
+        tables.append(t)
+        din = pool.take(s.size)
+        pool.put(din, s)
+        cap = lr.rans_encode_bound(s.size, params)
+        if cap_override and i in cap_override:
+            cap = cap_override[i]
+        dout = pool.take(cap)
+        specs.append((t, din, s.size, dout, cap, int(lens.data_ptr()) + 8 * i,
+                      int(st.data_ptr()) + 4 * i))
+    jobs = lr.make_jobs(specs)
+    lr.rans_encode_batch(jobs, len(data), params)
+    torch.cuda.synchronize()
+    outs = [pool.get(specs[i][3], int(lens[i])) for i in range(len(data))]
+    assert total > 0
+    return tables, outs, st.cpu().numpy(), lens.cpu().numpy()
+
+
+def run_decode_batch(lr, tables, containers, sizes, k, r, l, corrupt=None):
+    import torch
+    params = lr.rans_params.make(k, r, l, 1, 64, 0)
+    pool = Pool(sum(c.size + n + 1024 for c, n in zip(containers, sizes)))
+    lens = torch.zeros(len(containers), dtype=torch.int64, device="cuda")
+    st = torch.full((len(containers),), 99, dtype=torch.int32, device="cuda")
+    specs = []
+    for i, (c, n) in enumerate(zip(containers, sizes)):
+        din = pool.take(c.size)
+        pool.put(din, c)
+        dout = pool.take(n)
+        specs.append((tables[i], din, c.size, dout, n, int(lens.data_ptr()) + 8 * i,
+                      int(st.data_ptr()) + 4 * i))
+    jobs = lr.make_jobs(specs)
+    lr.rans_decode_batch(jobs, len(containers), params)
+    torch.cuda.synchronize()
+    outs = [pool.get(specs[i][3], sizes[i]) for i in range(len(containers))]
+    return outs, st.cpu().numpy(), lens.cpu().numpy()
+
+
+@pytest.mark.parametrize("k,r,l,C", [(14, 16, 16, 4096), (14, 16, 16, 65536), (12, 8, 23, 8192)])
+def test_batch_encode_decode_match_oracle(lr, k, r, l, C):
+    data = streams(40, seed=4100 + k + r)
+    tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C)
+    assert (st == 0).all(), st
+    refs = []
+    for i, (s, _) in enumerate(data):
+        f = oracle.quantize(datagen.counts(s, 256), k)
+        ref = oracle.encode(f, s, k, r, l, 64, C)
+        refs.append(ref)
+        assert outs[i].size == ref.size and (outs[i] == ref).all(), (i, first_diff(outs[i], ref))
+    dec, st2, n2 = run_decode_batch(lr, tables, refs, [s.size for s, _ in data], k, r, l)
+    assert (st2 == 0).all(), st2
+    for i, (s, _) in enumerate(data):
+        assert n2[i] == s.size
+        assert (dec[i] == s).all(), i
+
+
+def test_batch_failures_are_isolated(lr):
+    k, r, l, C = 14, 16, 16, 4096
+    data = streams(12, seed=4200)
+    # job 3 gets a container capacity of 40 bytes: ENOSPC for it alone
+    tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C, cap_override={3: 40})
+    assert st[3] == lr.RANS_ENOSPC
+    assert (np.delete(st, 3) == 0).all()
+    refs = [oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+            for s, _ in data]
+    for i in range(len(data)):
+        if i != 3:
+            assert (outs[i] == refs[i]).all()
+    # job 5's container is corrupted, job 7's header claims another radix
+    bad = [c.copy() for c in refs]
+    first = int(np.frombuffer(bad[5][32:40].tobytes(), "<u8")[0])
+    bad[5][first + 300] ^= 0x22
+    bad[7][6] = 8
+    dec, st2, _ = run_decode_batch(lr, tables, bad, [s.size for s, _ in data], k, r, l)
+    assert st2[5] == lr.RANS_ECORRUPT
+    assert st2[7] == lr.RANS_EINVAL
+    for i, (s, _) in enumerate(data):
+        if i not in (5, 7):
+            assert st2[i] == 0 and (dec[i] == s).all(), i
+
+
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_batch_replays_stay_exact(lr, use_graph):
+    """Same shapes, new data: the captured graph is replayed; every replay is
+    checked, with host work and synchronisation in between."""
+    lr.rans_batch_set_config(16, 1, 0, use_graph)
+    try:
+        k, r, l, C = 14, 16, 16, 4096
+        for rep in range(3):
+            data = streams(16, seed=4300 + rep, lo=12, hi=15)
+            # equal lengths across replays keep the launch image identical
+            data = [(s[: 1 << 12], p) for s, p in data]
+            tables, outs, st, _ = run_encode_batch(lr, data, k, r, l, C)
+            assert (st == 0).all()
+            for i, (s, _) in enumerate(data):
+                ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+                assert (outs[i] == ref).all(), (rep, i)
+            dec, st2, _ = run_decode_batch(lr, tables, outs, [s.size for s, _ in data], k, r, l)
+            assert (st2 == 0).all()
+            for i, (s, _) in enumerate(data):
+                assert (dec[i] == s).all(), (rep, i)
+    finally:
+        lr.rans_batch_set_config(16, 1, 0, 1)
+
+
+def test_batch_config_validation(lr):
+    with pytest.raises(lr.RansError):
+        lr.rans_batch_set_config(0, 1, 0, 1)
+    with pytest.raises(lr.RansError):
+        lr.rans_batch_set_config(16, 9, 0, 1)
+    lr.rans_batch_set_config(8, 2, 2, 1)
+    assert lr.rans_batch_get_config() == {"waves_per_group": 8, "groups_per_cu": 2,
+                                          "table_layout": 2, "use_graph": 1}
+    lr.rans_batch_set_config(16, 1, 0, 1)
+
+
+@pytest.mark.parametrize("G,gpc,layout", [(4, 2, 0), (8, 2, 2), (16, 1, 1)])
+def test_batch_launch_shapes(lr, G, gpc, layout):
+    lr.rans_batch_set_config(G, gpc, layout, 1)
+    try:
+        k, r, l, C = 14, 16, 16, 8192
+        data = streams(20, seed=4400 + G)
+        tables, outs, st, _ = run_encode_batch(lr, data, k, r, l, C)
+        assert (st == 0).all()
+        dec, st2, _ = run_decode_batch(lr, tables, outs, [s.size for s, _ in data], k, r, l)
+        assert (st2 == 0).all()
+        for i, (s, _) in enumerate(data):
+            ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+            assert (outs[i] == ref).all() and (dec[i] == s).all(), i
+    finally:
+        lr.rans_batch_set_config(16, 1, 0, 1)
