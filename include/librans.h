@@ -201,8 +201,9 @@ int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *p
  * sets it).  waves_per_group: chunks one work item covers, i.e. waves per
  * persistent block sharing one staged table (1..16); groups_per_cu:
  * persistent blocks per compute unit (1..8); table_layout: decode table
- * layout in LDS, 0 = automatic, 1 = per-slot packed entries, 2 = symbol map
- * plus per-symbol entries; use_graph: replay the batch as a captured HIP
+ * layout in LDS, 0 = automatic, 1 = per-slot packed entries plus symbol
+ * map, 2 = symbol map plus per-symbol entries, 3 = one 8-byte entry per slot
+ * holding f, bias and symbol (8-bit alphabets, prob_bits <= 14); use_graph: replay the batch as a captured HIP
  * graph (1) or launch its kernels directly (0).  The batched kernels code
  * 64 interleaved coders per chunk (params->interleave == 64); batched encode
  * needs chunk_syms != 0 with chunk_syms * sym_bytes a multiple of 16, and

@@ -103,8 +103,14 @@ bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds)
 {
     const uint64_t maxl = static_cast<uint64_t>(max_lds_bytes());
     const uint64_t packed = t.dec_bytes + t.sym_bytes, two = t.sym_bytes + t.fc_bytes;
-    // The packed table costs one dependent LDS read per symbol; keep it while
-    // it leaves room for two resident blocks per CU.
+    // One LDS read per symbol when the fused table leaves room for 16 waves'
+    // rings; else the packed table (two independent reads) while it leaves
+    // room for a second block; else the small two-level table.
+    if (t.fused && t.fused_bytes + 16 * 2048 <= maxl) {
+        *layout = kFused;
+        *lds = static_cast<uint32_t>(t.fused_bytes);
+        return true;
+    }
     if (packed <= maxl && packed <= 96 * 1024) {
         *layout = kPacked;
         *lds = static_cast<uint32_t>(packed);
@@ -120,7 +126,12 @@ bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds)
 
 void fill_decode_tables(const DevTable& t, Layout layout, DecodeArgs* a)
 {
-    if (layout == kPacked) {
+    if (layout == kFused) {
+        a->tab0 = t.fused;
+        a->tab0_bytes = static_cast<uint32_t>(t.fused_bytes);
+        a->tab1 = nullptr;
+        a->tab1_bytes = 0;
+    } else if (layout == kPacked) {
         a->tab0 = t.dec;
         a->tab0_bytes = static_cast<uint32_t>(t.dec_bytes);
         a->tab1 = t.sym;

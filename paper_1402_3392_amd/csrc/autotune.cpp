@@ -175,7 +175,7 @@ extern "C" int rans_autotune(const rans_table* table, const void* d_syms, uint64
         // decode shapes for this container
         for (uint32_t G : {16u, 8u, 4u}) {
             for (uint32_t gpc : {1u, 2u}) {
-                for (uint32_t lay : {1u, 2u}) {
+                for (uint32_t lay : {3u, 1u, 2u}) {
                     rans_batch_config cfg{G, gpc, lay, 1};
                     rans_job dj{table, cont.p, clen, dec.p, n_syms * w, d_len, d_status};
                     int de = RANS_OK;

@@ -46,6 +46,8 @@ __global__ void k_batch_plan(BatchArgs a, bool decode)
                 st = RANS_EINVAL;
             } else if (n * a.w > jb.out_cap) {
                 st = RANS_ENOSPC;
+            } else if ((uint64_t(C) * a.w) % 16 != 0) {
+                st = RANS_EINVAL;  // chunks must start 16-byte aligned in the output
             }
         }
         if (st != RANS_OK) {
@@ -317,6 +319,8 @@ hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 template <int R, int W, int SW>
 hipError_t persistent_decode_l(const BatchArgs& a, Layout layout, uint32_t grid, hipStream_t st)
 {
+    if (SW == 1 && layout == kFused)
+        return persistent_decode<R, W, 1, kFused>(a, grid, st);
     return layout == kPacked ? persistent_decode<R, W, SW, kPacked>(a, grid, st)
                              : persistent_decode<R, W, SW, kTwoLevel>(a, grid, st);
 }

@@ -2,6 +2,7 @@
 // layout, and one HIP graph per launch image (captured on first use, then
 // replayed: one graph launch per batch).  The job descriptors are the only
 // per-call input; they are copied into the workspace ahead of the replay.
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -106,16 +107,6 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         b.enc = t->enc;
         b.enc_bytes = static_cast<uint32_t>(t->enc_bytes);
         if (decode) {
-            Layout lj;
-            uint32_t lds;
-            if (!choose_layout(*t, &lj, &lds))
-                return RANS_EINVAL;
-            if (cfg.table_layout == 2 || (cfg.table_layout == 0 && j > 0 && lj != layout))
-                lj = kTwoLevel;
-            if (j == 0)
-                layout = lj;
-            else if (lj != layout)
-                layout = kTwoLevel;
             // chunks cost at least a directory entry and 64 states
             const uint64_t nch = jb.in_len >= kHeaderBytes ? (jb.in_len - kHeaderBytes) / (16 + 256) : 0;
             max_items += (nch + G - 1) / G;
@@ -132,12 +123,41 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         }
     }
     if (decode) {
-        if (cfg.table_layout == 2)
+        // table layout: the configured one, or the best one every table has
+        // (fused > packed > two-level) that fits LDS next to G waves' rings
+        bool all_fused = true;
+        uint64_t max_packed = 0, max_two = 0, max_fused = 0;
+        for (uint32_t j = 0; j < njobs; ++j) {
+            const DevTable* t = dev_table(jobs[j].table);
+            all_fused = all_fused && t->fused;
+            max_packed = std::max<uint64_t>(max_packed, t->sym_bytes + t->dec_bytes);
+            max_two = std::max<uint64_t>(max_two, t->sym_bytes + t->fc_bytes);
+            max_fused = std::max<uint64_t>(max_fused, t->fused_bytes);
+        }
+        const uint64_t room = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave();
+        if (cfg.table_layout == 1)
+            layout = kPacked;
+        else if (cfg.table_layout == 2)
+            layout = kTwoLevel;
+        else if (cfg.table_layout == 3) {
+            if (!all_fused)
+                return RANS_EINVAL;
+            layout = kFused;
+        } else if (all_fused && max_fused <= room)
+            layout = kFused;
+        else if (max_packed <= room && max_packed <= 96 * 1024)
+            layout = kPacked;
+        else
             layout = kTwoLevel;
         for (uint32_t j = 0; j < njobs; ++j) {
             const DevTable* t = dev_table(jobs[j].table);
             BatchJob& b = hj[j];
-            if (layout == kPacked) {
+            if (layout == kFused) {
+                b.tab_sym = nullptr;
+                b.sym_bytes = 0;
+                b.tab_ent = t->fused;
+                b.ent_bytes = static_cast<uint32_t>(t->fused_bytes);
+            } else if (layout == kPacked) {
                 b.tab_sym = t->sym;
                 b.sym_bytes = static_cast<uint32_t>(t->sym_bytes);
                 b.tab_ent = t->dec;
@@ -271,7 +291,7 @@ extern "C" int rans_decode_batch(const rans_job* jobs, uint32_t njobs, const ran
 extern "C" int rans_batch_set_config(const rans_batch_config* cfg)
 {
     if (!cfg || cfg->waves_per_group < 1 || cfg->waves_per_group > 16 || cfg->groups_per_cu < 1 ||
-        cfg->groups_per_cu > 8 || cfg->table_layout > 2)
+        cfg->groups_per_cu > 8 || cfg->table_layout > 3)
         return RANS_EINVAL;
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     g_cfg = *cfg;

@@ -141,7 +141,12 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
 
     auto decode_one = [&](uint32_t& s) {
         const uint32_t slot = x & mask;
-        if (LAYOUT == kPacked) {
+        if (LAYOUT == kFused) {
+            // low 24 bits of e.y are f: what the 24-bit multiply-add reads
+            const uint2 e = reinterpret_cast<const uint2*>(l_ent)[slot];
+            s = e.y >> 24;
+            x = __umul24(e.y, x >> k) + e.x;
+        } else if (LAYOUT == kPacked) {
             const uint32_t e = l_ent[slot];
             s = l_sym[slot];
             x = __umul24(e >> 16, x >> k) + (e & 0xFFFFu);

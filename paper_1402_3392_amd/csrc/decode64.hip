@@ -9,11 +9,12 @@ template <int R, int W, int SW, int LAYOUT>
 __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    // symbol map first (small immediate offsets), then the entries
-    const void* symsrc = LAYOUT == kPacked ? a.tab1 : a.tab0;
-    const void* ent = LAYOUT == kPacked ? a.tab0 : a.tab1;
-    const uint32_t sym_bytes = LAYOUT == kPacked ? a.tab1_bytes : a.tab0_bytes;
-    const uint32_t ent_bytes = LAYOUT == kPacked ? a.tab0_bytes : a.tab1_bytes;
+    // symbol map first (small immediate offsets), then the entries; the
+    // fused layout has no separate symbol map
+    const void* symsrc = LAYOUT == kPacked ? a.tab1 : (LAYOUT == kFused ? nullptr : a.tab0);
+    const void* ent = LAYOUT == kPacked ? a.tab0 : (LAYOUT == kFused ? a.tab0 : a.tab1);
+    const uint32_t sym_bytes = LAYOUT == kPacked ? a.tab1_bytes : (LAYOUT == kFused ? 0 : a.tab0_bytes);
+    const uint32_t ent_bytes = LAYOUT == kPacked ? a.tab0_bytes : (LAYOUT == kFused ? a.tab0_bytes : a.tab1_bytes);
     c64::stage2(lds, symsrc, sym_bytes, ent, ent_bytes);
     __syncthreads();
     // wave-uniform by construction; readfirstlane lets the compiler keep
@@ -45,6 +46,8 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
 template <int R, int W, int SW>
 hipError_t run_l(const DecodeArgs& a, Layout layout, hipStream_t st)
 {
+    if (SW == 1 && layout == kFused)
+        return run<R, W, 1, kFused>(a, st);
     return layout == kPacked ? run<R, W, SW, kPacked>(a, st) : run<R, W, SW, kTwoLevel>(a, st);
 }
 

@@ -131,7 +131,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
         uint32_t s = 0;
         if (act) {
             const uint32_t slot = x & mask;
-            if (LAYOUT == kPacked) {
+            if (LAYOUT == kFused) {
+                const uint2 e = reinterpret_cast<const uint2*>(lds)[slot];
+                s = e.y >> 24;
+                x = __umul24(e.y, x >> k) + e.x;
+            } else if (LAYOUT == kPacked) {
                 const uint32_t e = l_dec[slot];
                 s = l_sym[slot];
                 x = __umul24(e >> 16, x >> k) + (e & 0xFFFFu);
@@ -420,6 +424,8 @@ hipError_t run_decode_n(const DecodeArgs& a, hipStream_t st)
 template <int R, int W, int SW>
 hipError_t run_decode_l(const DecodeArgs& a, Layout layout, hipStream_t st)
 {
+    if (SW == 1 && layout == kFused)
+        return run_decode_n<R, W, 1, kFused>(a, st);
     return layout == kPacked ? run_decode_n<R, W, SW, kPacked>(a, st)
                              : run_decode_n<R, W, SW, kTwoLevel>(a, st);
 }

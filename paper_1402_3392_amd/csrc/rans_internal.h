@@ -21,7 +21,9 @@ constexpr uint32_t kDirEntryBytes = 16;
 //            symbol (w bytes): one dependent LDS read on the state chain.
 //   kTwoLevel: per slot the symbol, per symbol one u32 (f | cum << 16):
 //            two dependent LDS reads, much smaller for large M.
-enum Layout : int { kPacked = 1, kTwoLevel = 2 };
+//   kFused: per slot one u64 {bias, f | sym << 24}: a single LDS read gives
+//            f, bias and the symbol (8-bit alphabets, M <= 2^14: <= 128 KiB).
+enum Layout : int { kPacked = 1, kTwoLevel = 2, kFused = 3 };
 
 // Device-resident table (see tables.cpp for how each array is built).
 struct DevTable {
@@ -32,7 +34,8 @@ struct DevTable {
     void* sym;          // [M]      slot -> symbol, sym_w bytes each
     uint32_t* fc;       // [alpha]  f | cum << 16 (kTwoLevel)
     uint4* enc;         // [alpha+1] encoder entries; the extra one has f = 0
-    uint64_t dec_bytes, sym_bytes, fc_bytes, enc_bytes;  // padded to 16
+    uint2* fused;       // [M]      kFused entries, or null
+    uint64_t dec_bytes, sym_bytes, fc_bytes, enc_bytes, fused_bytes;  // padded to 16
 };
 
 // Encoder entry, one per symbol (uint4):

@@ -132,15 +132,22 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
     d.sym_bytes = pad16(uint64_t(M) * sym_w);
     d.fc_bytes = pad16(uint64_t(alphabet) * 4);
     d.enc_bytes = pad16(uint64_t(alphabet + 1) * 16);
+    const bool fused = alphabet <= 256 && k <= 14;
+    d.fused_bytes = fused ? uint64_t(M) * 8 : 0;
 
     std::vector<uint8_t> h_dec(d.dec_bytes, 0), h_sym(d.sym_bytes, 0), h_fc(d.fc_bytes, 0),
-        h_enc(d.enc_bytes, 0);
+        h_enc(d.enc_bytes, 0), h_fused(d.fused_bytes, 0);
+    uint32_t* fz = reinterpret_cast<uint32_t*>(h_fused.data());
     uint32_t* dec = reinterpret_cast<uint32_t*>(h_dec.data());
     uint32_t* fc = reinterpret_cast<uint32_t*>(h_fc.data());
     uint32_t* enc = reinterpret_cast<uint32_t*>(h_enc.data());
     for (uint32_t s = 0; s < alphabet; ++s) {
         for (uint32_t slot = cum[s]; slot < cum[s + 1]; ++slot) {
             dec[slot] = (f[s] << 16) | (slot - cum[s]);
+            if (fused) {
+                fz[2 * slot] = slot - cum[s];
+                fz[2 * slot + 1] = f[s] | (s << 24);
+            }
             if (sym_w == 1)
                 h_sym[slot] = static_cast<uint8_t>(s);
             else {
@@ -168,7 +175,7 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
         return RANS_EDEVICE;
     }
     void* blob = nullptr;
-    const uint64_t total = d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes;
+    const uint64_t total = d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes + d.fused_bytes;
     if (hipMalloc(&blob, total) != hipSuccess) {
         delete t;
         return RANS_ENOMEM;
@@ -178,12 +185,17 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
     d.sym = p + d.dec_bytes;
     d.fc = reinterpret_cast<uint32_t*>(p + d.dec_bytes + d.sym_bytes);
     d.enc = reinterpret_cast<uint4*>(p + d.dec_bytes + d.sym_bytes + d.fc_bytes);
+    d.fused = fused ? reinterpret_cast<uint2*>(p + d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes)
+                    : nullptr;
     std::vector<uint8_t> host(total);
     std::memcpy(host.data(), h_dec.data(), d.dec_bytes);
     std::memcpy(host.data() + d.dec_bytes, h_sym.data(), d.sym_bytes);
     std::memcpy(host.data() + d.dec_bytes + d.sym_bytes, h_fc.data(), d.fc_bytes);
     std::memcpy(host.data() + d.dec_bytes + d.sym_bytes + d.fc_bytes, h_enc.data(),
                 d.enc_bytes);
+    if (fused)
+        std::memcpy(host.data() + d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes,
+                    h_fused.data(), d.fused_bytes);
     if (hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(blob);
         delete t;
