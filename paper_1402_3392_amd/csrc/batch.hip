@@ -38,8 +38,11 @@ __global__ void k_batch_plan(BatchArgs a, bool decode)
             n = uint64_t(h1.x) | (uint64_t(h1.y) << 32);
             nch = h1.z;
             const bool hdr_ok = magic == kMagic && (b4 & 0xFF) == 1 && ((b8 >> 8) & 0xFF) == 0;
+            // every chunk takes a directory entry and at least 4N bytes of
+            // states: a container that claims more chunks is malformed (and
+            // the host sized the work-item map by this bound)
             if (!hdr_ok || (n == 0 ? nch != 0 : (C == 0 || nch != (n + C - 1) / C)) ||
-                kHeaderBytes + uint64_t(kDirEntryBytes) * nch > jb.in_len) {
+                kHeaderBytes + (uint64_t(kDirEntryBytes) + 4ull * a.N) * nch > jb.in_len) {
                 st = RANS_ECORRUPT;
             } else if (((b4 >> 8) & 0xFF) != a.k || ((b4 >> 16) & 0xFF) != a.r ||
                        (b4 >> 24) != a.l || (b8 & 0xFF) != a.w || (b8 >> 16) != a.N) {
@@ -127,7 +130,8 @@ __device__ __forceinline__ int next_item(const BatchArgs& a, uint32_t* s_slot, u
     if (threadIdx.x == 0) {
         const uint32_t it = atomicAdd(a.counter, 1u);
         s_slot[0] = it;
-        s_slot[1] = it < a.totals[0] ? a.item_job[it] : 0xFFFFFFFFu;
+        const uint32_t j = it < a.totals[0] ? a.item_job[it] : 0xFFFFFFFFu;
+        s_slot[1] = j < a.njobs ? j : 0xFFFFFFFFu;
     }
     __syncthreads();
     *item = s_slot[0];

@@ -134,7 +134,8 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             max_two = std::max<uint64_t>(max_two, t->sym_bytes + t->fc_bytes);
             max_fused = std::max<uint64_t>(max_fused, t->fused_bytes);
         }
-        const uint64_t room = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave();
+        // 256 bytes stay free for the persistent kernel's static LDS
+        const uint64_t room = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave() - 256;
         if (cfg.table_layout == 1)
             layout = kPacked;
         else if (cfg.table_layout == 2)
@@ -174,7 +175,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull)
         return RANS_EINVAL;
     const uint32_t per_wave = decode ? decode64_lds_per_wave() : 1024;
-    if (uint64_t(tab_lds) + uint64_t(G) * per_wave > uint64_t(max_lds_bytes()))
+    if (uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
         return RANS_EINVAL;
 
     const uint64_t slot_bytes = decode ? 0 : slot_bytes_for(p.chunk_syms, p.prob_bits, R);
