@@ -106,7 +106,7 @@ bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds)
     // One LDS read per symbol when the fused table leaves room for 16 waves'
     // rings; else the packed table (two independent reads) while it leaves
     // room for a second block; else the small two-level table.
-    if (t.fused && t.fused_bytes + 16 * 2048 <= maxl) {
+    if (t.fused && t.fused_bytes + 16 * decode64_lds_per_wave(kFused) <= maxl) {
         *layout = kFused;
         *lds = static_cast<uint32_t>(t.fused_bytes);
         return true;
@@ -185,7 +185,7 @@ extern "C" const char* rans_strerror(int code)
 // Validates an encode call and fills the launch arguments (host only).
 static int prepare_encode(const rans_table* table, const rans_params* params, const void* d_syms,
                           uint64_t n, void* d_out, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
-                          uint64_t* ws_need)
+                          PlaceArgs* pa, uint64_t* ws_need)
 {
     if (!table || !d_out)
         return RANS_EINVAL;
@@ -247,10 +247,16 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->ndig = reinterpret_cast<uint32_t*>(el.ndig);
     sa->chunk_off = reinterpret_cast<uint64_t*>(el.chunk_off);
     sa->total = reinterpret_cast<uint64_t*>(el.flags + 8);
+    *pa = PlaceArgs{};
+    pa->ticket = reinterpret_cast<uint32_t*>(el.flags + 16);
+    pa->lookback = reinterpret_cast<uint64_t*>(el.lookback);
+    pa->out = sa->out;
+    std::memcpy(pa->hdr, sa->hdr, 32);
     return RANS_OK;
 }
 
-static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca)
+static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
+                           PlaceArgs* pa)
 {
     auto rb = [base](auto* p) { return reinterpret_cast<decltype(p)>(base + reinterpret_cast<uintptr_t>(p)); };
     ea->slots = rb(ea->slots);
@@ -264,6 +270,9 @@ static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactA
     ca->ndig = ea->ndig;
     ca->chunk_off = sa->chunk_off;
     ca->total = sa->total;
+    pa->ticket = rb(pa->ticket);
+    pa->lookback = rb(pa->lookback);
+    pa->total = sa->total;
 }
 
 // The N = 64 kernels move symbols in 16-byte pieces: every chunk must start
@@ -274,13 +283,23 @@ static bool fast64(uint32_t N, uint32_t C, uint32_t W, const void* syms)
 }
 
 static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
-                                 int R, int W, hipStream_t st)
+                                 const PlaceArgs& pa, int R, int W, hipStream_t st)
 {
     hipError_t e;
+    if (ea.n_chunks > 0 && fast64(ea.N, ea.C, W, ea.syms)) {
+        // one kernel: encode and place by look-back (ticket and look-back
+        // words start at zero)
+        e = launch_fill_u32(pa.ticket, 0, 1, st);
+        if (e == hipSuccess)
+            e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0, 2 * ea.n_chunks, st);
+        if (e != hipSuccess)
+            return e;
+        TimingScope ts(RANS_KERNEL_ENCODE, st);
+        return launch_encode64_place(ea, pa, R, W, st);
+    }
     {
         TimingScope ts(RANS_KERNEL_ENCODE, st);
-        e = fast64(ea.N, ea.C, W, ea.syms) ? launch_encode64(ea, R, W, st)
-                                           : launch_encode(ea, R, W, st);
+        e = launch_encode(ea, R, W, st);
     }
     if (e == hipSuccess) {
         TimingScope ts(RANS_KERNEL_SCAN, st);
@@ -309,8 +328,9 @@ extern "C" int rans_encode_async(const rans_table* table, const rans_params* par
     EncodeArgs ea;
     ScanArgs sa;
     CompactArgs ca;
+    PlaceArgs pa;
     uint64_t need = 0;
-    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &need);
+    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &pa, &need);
     if (rc != RANS_OK)
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -321,11 +341,11 @@ extern "C" int rans_encode_async(const rans_table* table, const rans_params* par
     rc = ws->reserve(need);
     if (rc != RANS_OK)
         return rc;
-    bind_workspace(static_cast<uint8_t*>(ws->dev), &ea, &sa, &ca);
+    bind_workspace(static_cast<uint8_t*>(ws->dev), &ea, &sa, &ca, &pa);
     ea.status = sa.status = d_status;
-    sa.out_cap = ca.out_cap = out_cap;
-    sa.total_out = d_out_len;
-    return enqueue_encode(ea, sa, ca, params->radix_bits, params->sym_bytes, st) == hipSuccess
+    sa.out_cap = ca.out_cap = pa.out_cap = out_cap;
+    sa.total_out = pa.total_out = d_out_len;
+    return enqueue_encode(ea, sa, ca, pa, params->radix_bits, params->sym_bytes, st) == hipSuccess
                ? RANS_OK
                : RANS_EDEVICE;
 }
@@ -340,8 +360,9 @@ extern "C" int rans_encode(const rans_table* table, const rans_params* params, c
     EncodeArgs ea;
     ScanArgs sa;
     CompactArgs ca;
+    PlaceArgs pa;
     uint64_t need = 0;
-    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &need);
+    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &pa, &need);
     if (rc != RANS_OK)
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -353,14 +374,14 @@ extern "C" int rans_encode(const rans_table* table, const rans_params* params, c
     if (rc != RANS_OK)
         return rc;
     uint8_t* base = static_cast<uint8_t*>(ws->dev);
-    bind_workspace(base, &ea, &sa, &ca);
+    bind_workspace(base, &ea, &sa, &ca, &pa);
     int32_t* status = reinterpret_cast<int32_t*>(base);  // flags word at offset 0
     ea.status = sa.status = status;
-    sa.out_cap = ca.out_cap = out_cap;
-    sa.total_out = nullptr;
+    sa.out_cap = ca.out_cap = pa.out_cap = out_cap;
+    sa.total_out = pa.total_out = nullptr;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(status), 0, 1, st);
     if (e == hipSuccess)
-        e = enqueue_encode(ea, sa, ca, params->radix_bits, params->sym_bytes, st);
+        e = enqueue_encode(ea, sa, ca, pa, params->radix_bits, params->sym_bytes, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws->host, base, 16, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)

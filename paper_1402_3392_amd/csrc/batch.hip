@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_slot[2];
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
-    uint8_t* wave_lds = lds + a.tab_lds + wave * c64::kWaveLds;
+    uint8_t* wave_lds = lds + a.tab_lds + wave * c64::wave_lds_bytes(LAYOUT);
     int cur = -1;
     uint32_t item;
     for (;;) {
@@ -311,7 +311,7 @@ hipError_t set_lds(K kernel, uint32_t bytes)
 template <int R, int W, int SW, int LAYOUT>
 hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
-    const uint32_t lds = a.tab_lds + a.G * c64::kWaveLds;
+    const uint32_t lds = a.tab_lds + a.G * c64::wave_lds_bytes(LAYOUT);
     auto kern = k_batch_decode64<R, W, SW, LAYOUT>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)

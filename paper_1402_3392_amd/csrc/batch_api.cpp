@@ -135,7 +135,8 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             max_fused = std::max<uint64_t>(max_fused, t->fused_bytes);
         }
         // 256 bytes stay free for the persistent kernel's static LDS
-        const uint64_t room = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave() - 256;
+        const uint64_t room_fused = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave(kFused) - 256;
+        const uint64_t room = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave(kPacked) - 256;
         if (cfg.table_layout == 1)
             layout = kPacked;
         else if (cfg.table_layout == 2)
@@ -144,7 +145,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             if (!all_fused)
                 return RANS_EINVAL;
             layout = kFused;
-        } else if (all_fused && max_fused <= room)
+        } else if (all_fused && max_fused <= room_fused)
             layout = kFused;
         else if (max_packed <= room && max_packed <= 96 * 1024)
             layout = kPacked;
@@ -174,7 +175,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     }
     if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull)
         return RANS_EINVAL;
-    const uint32_t per_wave = decode ? decode64_lds_per_wave() : 1024;
+    const uint32_t per_wave = decode ? decode64_lds_per_wave(layout) : 1024;
     if (uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
         return RANS_EINVAL;
 

@@ -25,7 +25,8 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
         return;  // no barrier follows
     c64::decode_chunk<R, W, SW, LAYOUT>(a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, lds,
                                         reinterpret_cast<const uint32_t*>(lds + sym_bytes),
-                                        lds + sym_bytes + ent_bytes + wave * c64::kWaveLds, a.status);
+                                        lds + sym_bytes + ent_bytes + wave * c64::wave_lds_bytes(LAYOUT),
+                                        a.status);
 }
 
 template <int R, int W, int SW, int LAYOUT>
@@ -33,7 +34,7 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
-    const uint32_t lds = a.tab0_bytes + a.tab1_bytes + wpb * c64::kWaveLds;
+    const uint32_t lds = a.tab0_bytes + a.tab1_bytes + wpb * c64::wave_lds_bytes(LAYOUT);
     auto kern = k_decode64<R, W, SW, LAYOUT>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -63,7 +64,7 @@ hipError_t run_w(const DecodeArgs& a, int W, Layout layout, hipStream_t st)
 
 }  // namespace
 
-uint32_t decode64_lds_per_wave() { return c64::kWaveLds; }
+uint32_t decode64_lds_per_wave(Layout layout) { return c64::wave_lds_bytes(layout); }
 
 hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream)
 {

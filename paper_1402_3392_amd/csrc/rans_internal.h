@@ -82,6 +82,19 @@ struct EncodeArgs {
     int32_t* status;
 };
 
+// Placement of encoded chunks by decoupled look-back (N = 64 encoder): each
+// chunk publishes its aligned length, sums its predecessors' published
+// values and copies itself to its final offset.
+struct PlaceArgs {
+    uint32_t* ticket;      // chunk tickets in start order (zeroed before)
+    uint64_t* lookback;    // n_chunks words: flag << 62 | value (zeroed before)
+    uint8_t* out;
+    uint64_t out_cap;
+    uint64_t* total;       // container length (workspace)
+    uint64_t* total_out;   // optional caller copy
+    uint8_t hdr[32];
+};
+
 struct ScanArgs {
     const uint32_t* ndig;
     uint32_t n_chunks;
@@ -158,7 +171,10 @@ hipError_t launch_encode(const EncodeArgs& a, int R, int W, hipStream_t stream);
 // 16-byte aligned symbol buffers.
 hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
 hipError_t launch_encode64(const EncodeArgs& a, int R, int W, hipStream_t stream);
-uint32_t decode64_lds_per_wave();
+// N = 64 encode with in-kernel placement (no scan / compaction kernels).
+hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
+                                 hipStream_t stream);
+uint32_t decode64_lds_per_wave(Layout layout);
 
 // Batched pass (batch.hip).  `decode` selects the direction.
 hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, Layout layout,
