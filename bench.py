@@ -42,6 +42,15 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", default="roundtrip",
+                    choices=["roundtrip", "batched", "sweep", "serving"],
+                    help="roundtrip: the headline line (3 x 256 MiB encode+decode); "
+                         "batched: 4096 uneven streams, one persistent launch vs plain calls; "
+                         "sweep: radix/precision/alphabet sweep, batched vs plain decode; "
+                         "serving: Poisson request loop, p50/p99 latency")
+    ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
+    ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
     return ap.parse_args()
 
 
@@ -87,6 +96,319 @@ def cpu_baseline(work, threads):
                       f"{threads} threads over 64 KiB chunks"}
 
 
+class DevPool:
+    """Carves 256-byte aligned pieces out of one device allocation."""
+
+    def __init__(self, nbytes):
+        import torch
+        self.buf = torch.empty(nbytes + 4096, dtype=torch.uint8, device="cuda")
+        self.base = int(self.buf.data_ptr())
+        self.off = 0
+
+    def take(self, nbytes):
+        a = self.base + self.off
+        self.off += (max(nbytes, 1) + 255) // 256 * 256
+        assert self.off <= self.buf.numel(), "pool exhausted"
+        return a
+
+    def view(self, addr, nbytes):
+        o = addr - self.base
+        return self.buf[o:o + nbytes]
+
+
+def timed(fn, reps):
+    """Median wall time (s) of fn() over reps runs on the current stream,
+    measured with events recorded on that stream."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def base_result(metric, value, unit, args, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic", "config": config}
+
+
+def run_batched(args):
+    """Many independent streams of uneven length, each with its own table:
+    one persistent batched launch (a graph replay) against one plain
+    rans_decode_async / rans_encode_async call per stream on the same stream."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1402_3392_amd as lr
+
+    K, R, L, N = 14, 16, 16, 64
+    log(f"generating {args.streams} streams")
+    data = datagen.config4_streams(nstreams=args.streams)
+    sizes = [int(s.size) for s, _ in data]
+    total = sum(sizes)
+    log(f"{total / 2**30:.2f} GiB in {len(data)} streams; building tables")
+    tables = [lr.rans_tables_build(datagen.counts(s, 256), K) for s, _ in data]
+
+    # chunk size and launch shape from the autotuner, on the largest stream
+    big = int(np.argmax(sizes))
+    d_big = torch.from_numpy(data[big][0]).cuda()
+    tune = lr.rans_autotune(tables[big], d_big, sizes[big], lr.rans_params.make(K, R, L, 1, N, 65536))
+    del d_big
+    C = int(tune["chunk_syms"])
+    lr.rans_batch_set_config(int(tune["waves_per_group"]), int(tune["groups_per_cu"]),
+                             int(tune["table_layout"]), 1)
+    params = lr.rans_params.make(K, R, L, 1, N, C)
+    caps = [lr.rans_encode_bound(n, params) for n in sizes]
+    pool = DevPool(sum((n + 255) // 256 * 256 for n in sizes) * 2 + sum(caps) + 256 * len(sizes))
+    d_in = [pool.take(n) for n in sizes]
+    for a, (s, _) in zip(d_in, data):
+        pool.view(a, s.size).copy_(torch.from_numpy(s))
+    d_cont = [pool.take(c) for c in caps]
+    d_dec = [pool.take(n) for n in sizes]
+    lens = torch.zeros(len(data), dtype=torch.int64, device="cuda")
+    st = torch.zeros(len(data), dtype=torch.int32, device="cuda")
+    enc_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], d_cont[i], caps[i],
+                             int(lens.data_ptr()) + 8 * i, int(st.data_ptr()) + 4 * i)
+                            for i in range(len(data)))
+    log("batched encode (containers for decode)")
+    lr.rans_encode_batch(enc_jobs, len(data), params)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0, "batched encode failed"
+    clen = [int(v) for v in lens.cpu().tolist()]
+    headers = [bytes(pool.view(d_cont[i], 32).cpu().numpy().tobytes()) for i in range(len(data))]
+    comp = sum(clen)
+    dec_jobs = lr.make_jobs((tables[i], d_cont[i], clen[i], d_dec[i], sizes[i],
+                             int(lens.data_ptr()) + 8 * i, int(st.data_ptr()) + 4 * i)
+                            for i in range(len(data)))
+    lens_enc = lens.clone()
+
+    def batched_decode():
+        lr.rans_decode_batch(dec_jobs, len(data), params)
+
+    def batched_encode():
+        lr.rans_encode_batch(enc_jobs, len(data), params)
+
+    def plain_decode():
+        for i in range(len(data)):
+            lr.rans_decode_async(tables[i], pool.view(d_cont[i], clen[i]), clen[i], headers[i],
+                                 pool.view(d_dec[i], sizes[i]), sizes[i], st[i:i + 1])
+
+    def plain_encode():
+        for i in range(len(data)):
+            lr.rans_encode_async(tables[i], params, pool.view(d_in[i], sizes[i]), sizes[i],
+                                 pool.view(d_cont[i], caps[i]), caps[i], lens[i:i + 1], st[i:i + 1])
+
+    reps = max(3, args.steps)
+    res = {}
+    for name, fn in [("batched_decode", batched_decode), ("plain_decode", plain_decode),
+                     ("batched_encode", batched_encode), ("plain_encode", plain_encode)]:
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        st.zero_()
+        t = timed(fn, reps)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0, f"{name}: status {st.nonzero()[:4].tolist()}"
+        if name.endswith("decode"):
+            for i in range(0, len(data), max(1, len(data) // 64)):
+                assert torch.equal(pool.view(d_dec[i], sizes[i]), pool.view(d_in[i], sizes[i])), name
+        else:
+            assert torch.equal(lens, lens_enc), name
+        res[name] = t
+        log(f"{name}: {t * 1e3:.2f} ms, {total / t / 1e9:.1f} GB/s")
+    alg = comp + total + 4 * 256 * len(data)
+    out = base_result("rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
+                      round(total / res["batched_decode"] / 1e9, 3), "GB/s", args,
+                      {"workload": f"{len(data)} uint8 streams, lengths 2^U(10,22) B "
+                                   f"({total / 2**30:.2f} GiB), Dirichlet(alpha in 0.05..5) tables, "
+                                   f"M=2^14, b=L=2^16, N=64, C={C} (autotuned), batched decode"})
+    out.update({
+        "batched_decode_gbps": round(total / res["batched_decode"] / 1e9, 2),
+        "plain_decode_gbps": round(total / res["plain_decode"] / 1e9, 2),
+        "decode_speedup": round(res["plain_decode"] / res["batched_decode"], 2),
+        "batched_encode_gbps": round(total / res["batched_encode"] / 1e9, 2),
+        "plain_encode_gbps": round(total / res["plain_encode"] / 1e9, 2),
+        "encode_speedup": round(res["plain_encode"] / res["batched_encode"], 2),
+        "compression_ratio": round(comp / total, 4),
+        "autotune": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tune.items()},
+        "roofline": {"bound": "hbm", "kernel": "k_batch_decode64", "unit": "GB/s",
+                     "achieved": round(alg / res["batched_decode"] / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "frac": round(alg / res["batched_decode"] / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "note": "whole launch incl. planning kernels"},
+    })
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep(args):
+    """Radix / precision / alphabet / entropy sweep: per point, GPU encode
+    (container compared byte for byte with the oracle's), then plain and
+    batched persistent decode of the oracle's container, timed."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    import paper_1402_3392_amd as lr
+
+    pts = datagen.config3_points()
+    sel = [int(x) for x in args.points.split(",") if x] if args.points else range(len(pts))
+    threads = min(16, os.cpu_count() or 1)
+    cache = {}
+    rows = []
+    for idx in sel:
+        p = pts[idx]
+        key = (p["alphabet"], p["dist"])
+        if key not in cache:
+            cache.clear()
+            cache[key] = datagen.config3_data(p["alphabet"], p["dist"])
+        syms = cache[key]
+        w = 1 if p["alphabet"] <= 256 else 2
+        row = {"idx": idx, "alphabet": p["alphabet"], "dist": p["dist"], "k": p["k"], "r": p["r"],
+               "l": p["l"], "N": p["N"]}
+        if not p["feasible"]:
+            row["status"] = "n/a (more symbols present than 2^k)"
+            rows.append(row)
+            log(json.dumps(row))
+            continue
+        counts = datagen.counts(syms, p["alphabet"])
+        f = oracle.quantize(counts, p["k"])
+        table = lr.rans_tables_build(counts, p["k"])
+        params = lr.rans_params.make(p["k"], p["r"], p["l"], w, p["N"], 65536 // w)
+        C = 65536 // w
+        cont = oracle.encode(f, syms, p["k"], p["r"], p["l"], p["N"], C, threads=threads)
+        d_syms = torch.from_numpy(syms.view(np.uint8)).cuda()
+        cap = lr.rans_encode_bound(syms.size, params)
+        d_enc = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        nb = lr.rans_encode(table, params, d_syms, syms.size, d_enc, cap)
+        row["encode_bit_exact"] = bool(nb == cont.size and np.array_equal(d_enc[:nb].cpu().numpy(), cont))
+        d_cont = torch.from_numpy(cont).cuda()
+        d_out = torch.empty(syms.size * w, dtype=torch.uint8, device="cuda")
+        hdr = bytes(cont[:32].tobytes())
+        st = torch.zeros(2, dtype=torch.int32, device="cuda")
+        lens = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+        def plain():
+            lr.rans_decode_async(table, d_cont, cont.size, hdr, d_out, syms.size, st[0:1])
+
+        def enc():
+            lr.rans_encode_async(table, params, d_syms, syms.size, d_enc, cap, lens, st[0:1])
+
+        jobs = lr.make_jobs([(table, d_cont, cont.size, d_out, syms.size * w,
+                              int(lens.data_ptr()), int(st.data_ptr()) + 4)])
+
+        def batched():
+            lr.rans_decode_batch(jobs, 1, params)
+
+        nbytes = syms.size * w
+        for name, fn in [("plain_decode", plain), ("batched_decode", batched), ("encode", enc)]:
+            try:
+                fn()
+                torch.cuda.synchronize()
+            except lr.RansError as e:
+                row[name] = f"n/a ({e})"
+                continue
+            t = timed(fn, max(5, args.steps))
+            row[name + "_gbps"] = round(nbytes / t / 1e9, 2)
+            if name != "encode":
+                row[name + "_ok"] = bool(torch.equal(d_out, d_syms)) and int(st.abs().sum()) == 0
+                d_out.fill_(0)
+            if name == "batched_decode":
+                alg = cont.size + nbytes + 4 * p["alphabet"]
+                row["batched_roofline_frac"] = round(alg / t / 1e9 / HBM_PEAK_GBPS, 4)
+        row["ratio"] = round(cont.size / nbytes, 4)
+        rows.append(row)
+        log(json.dumps(row))
+        table.close()
+    ok = [r for r in rows if "batched_decode_gbps" in r]
+    best = max((r["batched_decode_gbps"] for r in ok), default=0.0)
+    out = base_result("rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
+                      best, "GB/s", args,
+                      {"workload": "64 MiB symbol bytes per point; alphabets 2/16/256/4096, "
+                                   "M=2^11/2^15, p0=0.995 / Zipf(1.1) / near-uniform, "
+                                   "(b,L)=(2^8,2^23)/(2^16,2^16), N=32/64, 64 KiB chunks"})
+    out["points"] = rows
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args):
+    """Request loop: Poisson arrivals of mixed encode/decode requests under an
+    8 GiB HBM budget, rates swept around the saturated throughput; p50/p99
+    latency (arrival to completion) per operation and aggregate GB/s."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1402_3392_amd as lr
+
+    K, R, L, W, N, C = 14, 16, 16, 1, 64, 65536
+    params = lr.rans_params.make(K, R, L, W, N, C)
+    reqs = datagen.config5_requests(nreq=args.requests)
+    log(f"{len(reqs)} requests, {sum(q['size'] for q in reqs) / 2**30:.2f} GiB; staging")
+    staged = []
+    for q in reqs:
+        syms = datagen.request_data(q)
+        table = lr.rans_tables_build(datagen.counts(syms, 256), K)
+        d = torch.from_numpy(syms).cuda()
+        if q["op"] == "encode":
+            staged.append((lr.RANS_OP_ENCODE, table, d, syms.size,
+                           lr.rans_encode_bound(syms.size, params), syms.size))
+        else:
+            cap = lr.rans_encode_bound(syms.size, params)
+            c = torch.empty(cap, dtype=torch.uint8, device="cuda")
+            nb = lr.rans_encode(table, params, d, syms.size, c, cap)
+            staged.append((lr.RANS_OP_DECODE, table, c[:nb].clone(), nb, syms.size, syms.size))
+            del c
+    torch.cuda.synchronize()
+    total = sum(s[5] for s in staged)
+    srv = lr.rans_server_create(8 << 30, 4, 64, params)
+
+    def replay(arrivals):
+        reqlist = [(op, tab, d, inl, cap, float(t))
+                   for (op, tab, d, inl, cap, _), t in zip(staged, arrivals)]
+        res, mk = lr.rans_server_replay(srv, reqlist)
+        bad = [r.status for r in res if r.status != 0]
+        assert not bad, f"serving failures: {bad[:4]}"
+        return res, mk
+
+    log("saturated replay")
+    replay(np.zeros(len(staged)))  # warm: graphs, arena
+    _, mk = replay(np.zeros(len(staged)))
+    sat_rate = len(staged) / mk  # requests per microsecond
+    rows = []
+    for frac in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+        rng = np.random.Generator(np.random.PCG64(5001 + int(frac * 100)))
+        arr = np.cumsum(rng.exponential(1.0 / (frac * sat_rate), len(staged)))
+        arr -= arr[0]
+        res, mk = replay(arr)
+        lat = {op: np.array([r.latency_us for r in res if r.op == op]) for op in (0, 1)}
+        row = {"rate_frac": frac, "req_per_s": round(frac * sat_rate * 1e6, 1),
+               "gbps": round(total / (mk * 1e-6) / 1e9, 2)}
+        for op, name in ((1, "decode"), (0, "encode")):
+            if lat[op].size:
+                row[f"{name}_p50_ms"] = round(float(np.percentile(lat[op], 50)) / 1e3, 3)
+                row[f"{name}_p99_ms"] = round(float(np.percentile(lat[op], 99)) / 1e3, 3)
+        rows.append(row)
+        log(json.dumps(row))
+    stats = lr.rans_server_stats(srv)
+    lr.rans_server_destroy(srv)
+    at1 = [r for r in rows if r["rate_frac"] == 1.0][0]
+    out = base_result("rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
+                      at1["decode_p99_ms"], "ms", args,
+                      {"workload": f"{len(staged)} requests, sizes 2^U(12,26) B, encode/decode 50/50, "
+                                   "Zipf(s~U(0.7,1.5)) tables, M=2^14, b=L=2^16, N=64, 64 KiB chunks, "
+                                   "8 GiB HBM budget, Poisson arrivals"}, higher=False)
+    out.update({"saturated_gbps": round(total / (len(staged) / sat_rate * 1e-6) / 1e9, 2),
+                "rates": rows, "server": stats})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -97,6 +419,9 @@ def main():
 
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload != "roundtrip":
+        {"batched": run_batched, "sweep": run_sweep, "serving": run_serving}[args.workload](args)
         return
 
     import numpy as np

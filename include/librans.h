@@ -205,7 +205,8 @@ int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *p
  * map, 2 = symbol map plus per-symbol entries, 3 = one 8-byte entry per slot
  * holding f, bias and symbol (8-bit alphabets, prob_bits <= 14); use_graph: replay the batch as a captured HIP
  * graph (1) or launch its kernels directly (0).  The batched kernels code
- * 64 interleaved coders per chunk (params->interleave == 64); batched encode
+ * 32 or 64 interleaved coders per chunk (params->interleave 32 or 64; one
+ * wave per chunk, so with 32 half of each wave idles); batched encode
  * needs chunk_syms != 0 with chunk_syms * sym_bytes a multiple of 16, and
  * every buffer 16-byte aligned.  Batched calls on a stream that is being
  * captured launch directly (no nested graph). */
@@ -250,7 +251,7 @@ int rans_autotune(const rans_table *table, const void *d_syms, uint64_t n_syms,
  * device arena of hbm_budget bytes allocated once by rans_server_create; the
  * serving loop itself allocates no device memory.  All requests use
  * config->params (decode: the containers must carry those parameters;
- * interleave must be 64).  The calls are thread-safe. */
+ * interleave 32 or 64).  The calls are thread-safe. */
 #define RANS_OP_ENCODE 0
 #define RANS_OP_DECODE 1
 

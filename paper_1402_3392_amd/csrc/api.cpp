@@ -279,7 +279,8 @@ static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactA
 // 16-byte aligned in the symbol buffer.
 static bool fast64(uint32_t N, uint32_t C, uint32_t W, const void* syms)
 {
-    return N == 64 && (uint64_t(C) * W) % 16 == 0 && (reinterpret_cast<uintptr_t>(syms) & 15) == 0;
+    return (N == 32 || N == 64) && (uint64_t(C) * W) % 16 == 0 &&
+           (reinterpret_cast<uintptr_t>(syms) & 15) == 0;
 }
 
 static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
@@ -291,7 +292,8 @@ static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const
         // words start at zero)
         e = launch_fill_u32(pa.ticket, 0, 1, st);
         if (e == hipSuccess)
-            e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0, 2 * ea.n_chunks, st);
+            e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0,
+                                2 * (ea.n_chunks + (ea.n_chunks + 63) / 64), st);
         if (e != hipSuccess)
             return e;
         TimingScope ts(RANS_KERNEL_ENCODE, st);

@@ -4,7 +4,7 @@
 // scan turns chunk counts into work items of G chunks, and a persistent grid
 // pulls work items from an atomic counter.  A block restages its LDS table
 // whenever the next work item belongs to another job; each of its G waves
-// codes one chunk with the same N = 64 chunk coder as the single-buffer
+// codes one chunk with the same N = 32 or 64 chunk coder as the single-buffer
 // kernels.  Encode jobs then get their container laid out per job (scan of
 // chunk lengths, header, directory) and compacted.  No kernel waits on
 // another block: every block leaves when the counter passes the last item.
@@ -138,13 +138,16 @@ __device__ __forceinline__ int next_item(const BatchArgs& a, uint32_t* s_slot, u
     return static_cast<int>(s_slot[1]);
 }
 
-template <int R, int W, int SW, int LAYOUT>
+template <int R, int W, int SW, int LAYOUT, int NL>
 __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_slot[2];
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
-    uint8_t* wave_lds = lds + a.tab_lds + wave * c64::wave_lds_bytes(LAYOUT);
+    // the waves' rings and output blocks first (low LDS addresses for the
+    // direct-to-LDS loads), the job's tables after them
+    uint8_t* wave_lds = lds + wave * c64::wave_lds_bytes(LAYOUT);
+    uint8_t* tab = lds + a.G * c64::wave_lds_bytes(LAYOUT);
     int cur = -1;
     uint32_t item;
     for (;;) {
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
             break;
         const BatchJob& jb = a.jobs[j];
         if (j != cur) {
-            c64::stage2(lds, jb.tab_sym, jb.sym_bytes, jb.tab_ent, jb.ent_bytes);
+            c64::stage2(tab, jb.tab_sym, jb.sym_bytes, jb.tab_ent, jb.ent_bytes);
             __syncthreads();
             cur = j;
         }
@@ -161,15 +164,15 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
         if (c < nch) {
             const uint32_t sym_bytes = c64::uni(jb.sym_bytes);
-            c64::decode_chunk<R, W, SW, LAYOUT>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
-                                                a.k, a.l, lds,
-                                                reinterpret_cast<const uint32_t*>(lds + sym_bytes),
+            c64::decode_chunk<R, W, SW, LAYOUT, NL>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
+                                                a.k, a.l, tab,
+                                                reinterpret_cast<const uint32_t*>(tab + sym_bytes),
                                                 wave_lds, jb.d_status);
         }
     }
 }
 
-template <int R, int W>
+template <int R, int W, int NL>
 __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
         if (c < nch) {
             const uint64_t g = c64::uni(jb.chunk_base) + uint64_t(c);
-            c64::encode_chunk<R, W>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
+            c64::encode_chunk<R, W, NL>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
                                     reinterpret_cast<const uint4*>(lds), a.slots + g * a.slot_stride,
                                     a.slot_bytes, sbuf, a.states + g * 64, a.ndig + g, jb.d_status);
         }
@@ -308,11 +311,11 @@ hipError_t set_lds(K kernel, uint32_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
-template <int R, int W, int SW, int LAYOUT>
+template <int R, int W, int SW, int LAYOUT, int NL>
 hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
     const uint32_t lds = a.tab_lds + a.G * c64::wave_lds_bytes(LAYOUT);
-    auto kern = k_batch_decode64<R, W, SW, LAYOUT>;
+    auto kern = k_batch_decode64<R, W, SW, LAYOUT, NL>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)
         return e;
@@ -320,13 +323,20 @@ hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int R, int W, int SW, int LAYOUT>
+hipError_t persistent_decode_n(const BatchArgs& a, uint32_t grid, hipStream_t st)
+{
+    return a.N == 32 ? persistent_decode<R, W, SW, LAYOUT, 32>(a, grid, st)
+                     : persistent_decode<R, W, SW, LAYOUT, 64>(a, grid, st);
+}
+
 template <int R, int W, int SW>
 hipError_t persistent_decode_l(const BatchArgs& a, Layout layout, uint32_t grid, hipStream_t st)
 {
     if (SW == 1 && layout == kFused)
-        return persistent_decode<R, W, 1, kFused>(a, grid, st);
-    return layout == kPacked ? persistent_decode<R, W, SW, kPacked>(a, grid, st)
-                             : persistent_decode<R, W, SW, kTwoLevel>(a, grid, st);
+        return persistent_decode_n<R, W, 1, kFused>(a, grid, st);
+    return layout == kPacked ? persistent_decode_n<R, W, SW, kPacked>(a, grid, st)
+                             : persistent_decode_n<R, W, SW, kTwoLevel>(a, grid, st);
 }
 
 template <int R>
@@ -340,11 +350,11 @@ hipError_t persistent_decode_w(const BatchArgs& a, int W, int SW, Layout layout,
     return persistent_decode_l<R, 2, 2>(a, layout, grid, st);
 }
 
-template <int R, int W>
+template <int R, int W, int NL>
 hipError_t persistent_encode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
     const uint32_t lds = a.tab_lds + a.G * 1024;
-    auto kern = k_batch_encode64<R, W>;
+    auto kern = k_batch_encode64<R, W, NL>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)
         return e;
@@ -373,10 +383,16 @@ hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, L
                     : persistent_decode_w<8>(a, W, SW, layout, grid, st);
         return e;
     }
-    if (R == 16)
-        e = W == 1 ? persistent_encode<16, 1>(a, grid, st) : persistent_encode<16, 2>(a, grid, st);
-    else
-        e = W == 1 ? persistent_encode<8, 1>(a, grid, st) : persistent_encode<8, 2>(a, grid, st);
+    if (a.N == 32) {
+        if (R == 16)
+            e = W == 1 ? persistent_encode<16, 1, 32>(a, grid, st) : persistent_encode<16, 2, 32>(a, grid, st);
+        else
+            e = W == 1 ? persistent_encode<8, 1, 32>(a, grid, st) : persistent_encode<8, 2, 32>(a, grid, st);
+    } else if (R == 16) {
+        e = W == 1 ? persistent_encode<16, 1, 64>(a, grid, st) : persistent_encode<16, 2, 64>(a, grid, st);
+    } else {
+        e = W == 1 ? persistent_encode<8, 1, 64>(a, grid, st) : persistent_encode<8, 2, 64>(a, grid, st);
+    }
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_batch_cscan, dim3(a.njobs), dim3(256), 0, st, a);

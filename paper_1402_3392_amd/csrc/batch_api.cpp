@@ -59,9 +59,9 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         return RANS_EINVAL;
     const rans_params& p = *params;
     const uint32_t w = p.sym_bytes, R = p.radix_bits;
-    // the batched kernels code one chunk per wave: 64 coders per chunk, and
+    // the batched kernels code one chunk per wave: 32 or 64 coders per chunk, and
     // chunks must start 16-byte aligned in the symbol buffers
-    if (p.interleave != 64)
+    if (p.interleave != 64 && p.interleave != 32)
         return RANS_EINVAL;
     if (!decode && (p.chunk_syms == 0 || (uint64_t(p.chunk_syms) * w) % 16 != 0))
         return RANS_EINVAL;

@@ -3,12 +3,12 @@
 //
 // Decode (rANS D, then Algorithm 1's refill; offsets from a ballot of the
 // refilling lanes plus mbcnt, Section 6):
-//  * the chunk's digit stream is read from a per-wave LDS ring of four
-//    256-byte windows; windows are fetched from HBM four windows ahead of
-//    the one being read, with loads whose completion the code awaits
-//    explicitly (s_waitcnt vmcnt) just before a window enters the ring, so a
-//    refill never waits on HBM latency;
-//  * decoded symbols go to a per-wave 1 KiB LDS block and leave as one
+//  * the chunk's digit stream reaches a per-wave LDS ring of eight 256-byte
+//    windows by direct global-to-LDS loads, issued up to seven windows
+//    ahead; no register ever holds a load in flight, and the code awaits
+//    completion explicitly (s_waitcnt vmcnt) when the read position enters a
+//    new window, so a refill rarely waits on HBM latency;
+//  * decoded symbols go to a per-wave LDS block and leave as one 8- or
 //    16-byte store per lane.
 // Encode (Algorithm 1's Encode with rANS's C, walking backwards):
 //  * symbols arrive in 1 KiB blocks, one 16-byte load per lane issued a block
@@ -23,16 +23,21 @@
 
 #include "rans_internal.h"
 
+// The direct-to-LDS load takes its LDS address in M0, which inline assembly
+// has to name as clobbered; clang warns that M0 is reserved.  These kernels
+// make no other use of M0.
+#pragma clang diagnostic ignored "-Winline-asm"
+
 namespace rans {
 namespace c64 {
 
-constexpr uint32_t kWin = 512;       // stream window bytes
-constexpr uint32_t kRing = 2 * kWin + 128;  // two windows + mirror of slot 0's head
+constexpr uint32_t kWin = 256;               // stream window: one 4-byte load per lane
+constexpr uint32_t kSlots = 8;               // ring slots
+constexpr uint32_t kRing = (kSlots + 1) * kWin;  // slots + a copy of slot 0 after the last
 
 // Output block per wave: 1 KiB, or 512 bytes next to the large fused table.
 constexpr uint32_t obuf_bytes(int layout) { return layout == kFused ? 512 : 1024; }
 constexpr uint32_t wave_lds_bytes(int layout) { return obuf_bytes(layout) + kRing; }
-
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m, uint32_t acc)
@@ -48,24 +53,32 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v)
     return (uint64_t(uni(uint32_t(v >> 32))) << 32) | uni(uint32_t(v));
 }
 
-// Issues a 4-byte global load whose completion the caller awaits with
-// wait_vm<>() before using the result.
-__device__ __forceinline__ uint32_t async_load(const uint8_t* p)
+// LDS byte address of a pointer into this block's shared memory.
+__device__ __forceinline__ uint32_t lds_addr(const void* p)
 {
-    uint32_t v;
-    asm volatile("global_load_dword %0, %1, off" : "=v"(v) : "v"(p) : "memory");
-    return v;
+    typedef __attribute__((address_space(3))) const uint8_t* lds_ptr;
+    return uni(static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_ptr)p)));
 }
 
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-// 8-byte variant of async_load.
-__device__ __forceinline__ u32x2 async_load2(const uint8_t* p)
+// Direct global-to-LDS copy of 256 bytes: lane i moves the 4 bytes at
+// base + voff (its own offset) to LDS address dst + 4 i.  base and dst are
+// wave-uniform.  No register receives the data; the caller awaits completion
+// with wait_vm<>() before reading the LDS bytes.  M0 carries dst and must be
+// set one instruction ahead of the load.
+__device__ __forceinline__ void dma256(const uint8_t* base, uint32_t voff, uint32_t dst)
 {
-    u32x2 v;
-    asm volatile("global_load_dwordx2 %0, %1, off" : "=v"(v) : "v"(p) : "memory");
-    return v;
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1"
+                 :
+                 : "v"(voff), "s"(base), "s"(dst)
+                 : "memory", "m0");
 }
+
+// Lanes of a wave hand data to each other through LDS (a lane reads bytes
+// another lane wrote).  The hardware runs a wave's LDS operations in order,
+// but the compiler reasons per lane and may move a read above a write it
+// proves cannot touch the same lane's bytes; this compiler barrier keeps
+// every LDS access on its side.
+__device__ __forceinline__ void lane_fence() { asm volatile("" ::: "memory"); }
 
 // Per lane: b where the lane's bit of mask m is set, a elsewhere (one
 // v_cndmask on the ballot mask, no exec-mask branch).
@@ -77,7 +90,7 @@ __device__ __forceinline__ uint32_t select_mask(uint64_t m, uint32_t a, uint32_t
 }
 
 // All but the `n` most recent vector-memory operations of this wave have
-// completed (they complete in issue order).
+// completed (loads and stores complete in issue order).
 template <int n>
 __device__ __forceinline__ void wait_vm()
 {
@@ -97,11 +110,13 @@ __device__ __forceinline__ void stage2(uint8_t* lds, const void* a, uint32_t aby
 }
 
 // Decodes chunk `chunk` of the container `in` (n_chunks chunks of C symbols,
-// n in total) into out_base (the container's symbol 0).  l_sym / l_ent are
-// the LDS tables (symbol map first, then the packed per-slot entries or the
-// per-symbol f|cum entries), wave_lds this wave's 2 KiB.  Every argument
-// must be wave-uniform.
-template <int R, int W, int SW, int LAYOUT>
+// n in total, NL = 32 or 64 interleaved coders: lanes NL.. of the wave stay
+// idle) into out_base (the container's symbol 0).  l_sym / l_ent are
+// the LDS tables (symbol map first, then the packed per-slot entries, the
+// per-symbol f|cum entries or the fused entries), wave_lds this wave's
+// wave_lds_bytes(LAYOUT) bytes.  Every argument must be wave-uniform.  When
+// it returns, every load it issued has completed, so wave_lds can be reused.
+template <int R, int W, int SW, int LAYOUT, int NL>
 __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                              uint64_t chunk, uint32_t C, uint64_t n, void* out_base,
                                              uint32_t k_, uint32_t l, const void* l_sym_v,
@@ -113,8 +128,8 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     const SymT* l_sym = static_cast<const SymT*>(l_sym_v);
     const uint32_t lane = threadIdx.x & 63;
     constexpr uint32_t OB = obuf_bytes(LAYOUT);
-    uint8_t* obuf = wave_lds;        // output block
-    uint8_t* ring = wave_lds + OB;   // two 512-byte windows + 128-byte mirror
+    uint8_t* obuf = wave_lds;              // output block (first: the initial states)
+    const uint8_t* ring = wave_lds + OB;   // kSlots windows + copy of slot 0
     const uint8_t* de = in + kHeaderBytes + kDirEntryBytes * chunk;
     // directory values are the same for the whole wave: keep them scalar
     const uint64_t off = uni64(*reinterpret_cast<const uint64_t*>(de));
@@ -122,56 +137,67 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     const uint64_t first = chunk * C;
     const uint32_t nsym = uni(static_cast<uint32_t>(n - first < C ? n - first : C));
     const uint64_t data0 = (kHeaderBytes + uint64_t(kDirEntryBytes) * n_chunks + 15) & ~15ull;
-    if ((off & 15) || off < data0 || off > in_len || len > in_len - off || len < 256 ||
-        ((len - 256) % (R / 8)) != 0) {
+    if ((off & 15) || off < data0 || off > in_len || len > in_len - off || len < 4 * NL ||
+        ((len - 4 * NL) % (R / 8)) != 0) {
         if (lane == 0)
             atomicMin(status, RANS_ECORRUPT);
         return;
     }
-    const uint32_t ndig = (len - 256) / (R / 8);
+    const bool live = NL == 64 || lane < NL;
+    const uint32_t plen = len - 4 * NL;  // digit bytes after the NL states
     const uint32_t L = 1u << l, k = k_, mask = (1u << k) - 1;
 
-    // Window w = payload bytes [w*512, w*512+512); lane fetches 8 of them.
-    // Addresses past the container are clamped to its last whole 8 bytes, so
-    // every load is issued (the wait counts rely on that) and stays inside.
-    const uint64_t room = (in_len - 8) & ~7ull;  // in_len >= 32 here
-    const uint64_t pay_off = off + 256 + 8 * lane;
-    auto waddr = [&](uint32_t w) -> const uint8_t* {
-        const uint64_t o = pay_off + uint64_t(w) * kWin;
-        return in + (o <= room ? o : room);
+    // Window w = digit bytes [256 w, 256 w + 256) sits in ring slot w % 8;
+    // windows 0, 8, 16, ... go to one more slot after the last as well, so a
+    // read that starts in slot 7 runs on into the next window unwrapped.
+    // Lane addresses past the container (whole 4-byte words) are pulled back
+    // to its last word; such bytes are never used.
+    const uint64_t room = (in_len - 4) & ~3ull;  // in_len >= 176 here
+    const uint32_t lds_ob = lds_addr(obuf), lds_ring = lds_ob + OB, lane4 = 4 * lane;
+    auto fetch = [&](uint64_t src, uint32_t dst) {  // 256 container bytes from src
+        uint32_t vo = lane4;
+        if (src + kWin > room + 4) {
+            if (src > room)
+                src = room;
+            vo = min(lane4, static_cast<uint32_t>(room - src));
+        }
+        dma256(in + src, vo, dst);
     };
-    // window w lives in ring slot w & 1; slot 0's first 128 bytes are mirrored
-    // after slot 1, so a step's reads (< 128 bytes past any position) need no
-    // wrap-around
-    auto put_window = [&](uint32_t w, const u32x2& v) {
-        *reinterpret_cast<u32x2*>(ring + (w & 1) * kWin + 8 * lane) = v;
-        if ((w & 1) == 0 && lane < 16)
-            *reinterpret_cast<u32x2*>(ring + 2 * kWin + 8 * lane) = v;
+    const uint64_t pay = off + 4 * NL;
+    const uint32_t nwin = (plen + kWin - 1) / kWin;
+    auto issue = [&](uint32_t w) {
+        fetch(pay + uint64_t(w) * kWin, lds_ring + (w % kSlots) * kWin);
+        if (w % kSlots == 0)
+            fetch(pay + uint64_t(w) * kWin, lds_ring + kSlots * kWin);
     };
-    uint32_t x = async_load(in + off + 4 * lane);  // coder `lane`'s initial state
-    u32x2 p0 = async_load2(waddr(0));
-    u32x2 p1 = async_load2(waddr(1));
-    u32x2 p2 = async_load2(waddr(2));
-    u32x2 p3 = async_load2(waddr(3));
-    wait_vm<2>();
-    put_window(0, p0);
-    put_window(1, p1);
-    p0 = async_load2(waddr(4));
-    p1 = async_load2(waddr(5));
-    // ring holds windows kw, kw+1; p[(kw+2)%4 ..] hold kw+2 .. kw+5 in flight
+    fetch(off, lds_ob);  // coder i's initial state: bytes 4 i .. 4 i + 3 (i < NL)
+#pragma unroll
+    for (uint32_t w = 0; w < kSlots; ++w)
+        if (w < nwin)
+            issue(w);
+    // windows 0..2 are in once at most five later loads are pending
+    if (nwin >= kSlots)
+        wait_vm<5>();
+    else
+        wait_vm<0>();
+    uint32_t x = reinterpret_cast<const uint32_t*>(obuf)[lane];
+    lane_fence();  // the output block is reused for symbols
+    if (!live)
+        x = L;  // idle lanes stay at L and never refill
 
-    constexpr uint32_t WD = kWin / (R / 8);    // digits per window
-    constexpr uint32_t SPB = OB / (64 * W);    // steps per output block
+    constexpr uint32_t SPB = OB / (NL * W);    // steps per output block
     constexpr uint32_t PIECE = OB / 64;         // bytes each lane moves per block
+    constexpr uint32_t RMASK = kSlots * kWin - 1;
     using Piece = typename std::conditional<PIECE == 16, uint4, uint2>::type;
-    const uint32_t full = nsym / 64;           // steps with all lanes active
-    const uint32_t steps = (nsym + 63) / 64;
+    const uint32_t full = nsym / NL;           // steps with every coder active
+    const uint32_t steps = (nsym + NL - 1) / NL;
     OutT* out = static_cast<OutT*>(out_base) + first;
     OutT* ob = reinterpret_cast<OutT*>(obuf) + lane;
 
-    uint32_t pos = 0, kw = 0, wend = WD, t = 0;
+    uint32_t bpos = 0, kw = 0, wend = kWin, t = 0;  // bpos: next digit byte
 
     auto decode_one = [&](uint32_t& s) {
+        const uint32_t x0 = x;
         const uint32_t slot = x & mask;
         if (LAYOUT == kFused) {
             // low 24 bits of e.y are f: what the 24-bit multiply-add reads
@@ -187,6 +213,8 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             const uint32_t fc = l_ent[s];
             x = __umul24(fc & 0xFFFFu, x >> k) + slot - (fc >> 16);
         }
+        if (!live)
+            x = x0;
     };
     // Refill: every lane reads the ring at its would-be offset (the prefix
     // count of refilling lanes below it) and a select on the ballot keeps
@@ -197,106 +225,100 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         const uint64_t m1 = ballot(n1);
         if (R == 16) {
             if (m1) {
-                const uint32_t at = 2 * (pos & (2 * WD - 1));
-                const uint32_t v = *reinterpret_cast<const uint16_t*>(ring + at + 2 * mbcnt(m1, 0));
+                const uint32_t v =
+                    *reinterpret_cast<const uint16_t*>(ring + (bpos & RMASK) + 2 * mbcnt(m1, 0));
                 x = select_mask(m1, x, (x << 16) | v);
-                pos += __popcll(m1);
+                bpos += 2 * __popcll(m1);
             }
         } else {
             const bool n2 = act && x < (L >> 8);
             const uint64_t m2 = ballot(n2);
             if (m1) {
-                const uint8_t* r = ring + (pos & (2 * WD - 1)) + mbcnt(m2, mbcnt(m1, 0));
+                const uint8_t* r = ring + (bpos & RMASK) + mbcnt(m2, mbcnt(m1, 0));
                 const uint32_t x1 = (x << 8) | r[0];
                 const uint32_t x2 = (x1 << 8) | r[1];
                 x = select_mask(m1, x, select_mask(m2, x1, x2));
-                pos += __popcll(m1) + __popcll(m2);
+                bpos += __popcll(m1) + __popcll(m2);
             }
         }
     };
     auto flush = [&](uint32_t tb) {  // output block starting at step tb
+        lane_fence();
         const Piece v = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
-        *reinterpret_cast<Piece*>(reinterpret_cast<uint8_t*>(out + uint64_t(tb) * 64) + PIECE * lane) = v;
+        lane_fence();
+        *reinterpret_cast<Piece*>(reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL) + PIECE * lane) = v;
     };
     auto step1 = [&](OutT* dst) {
         uint32_t s;
         decode_one(s);
-        refill(true);
-        *dst = static_cast<OutT>(s);
+        refill(live);
+        if (live)
+            *dst = static_cast<OutT>(s);
     };
     // four full steps; t is a multiple of 4 here, so the output offsets are
     // immediates and a block ends exactly at a multiple of four
     auto step4 = [&]() {
-        OutT* o4 = ob + (t & (SPB - 1)) * 64;
+        OutT* o4 = ob + (t & (SPB - 1)) * NL;
         step1(o4);
-        step1(o4 + 64);
-        step1(o4 + 128);
-        step1(o4 + 192);
+        step1(o4 + NL);
+        step1(o4 + 2 * NL);
+        step1(o4 + 3 * NL);
         t += 4;
         if ((t & (SPB - 1)) == 0)
             flush(t - SPB);
     };
     auto step_single = [&]() {
-        step1(ob + (t & (SPB - 1)) * 64);
+        step1(ob + (t & (SPB - 1)) * NL);
         ++t;
         if ((t & (SPB - 1)) == 0)
             flush(t - SPB);
     };
-    // last, partial step: only lanes below nsym % 64 take part
+    // last, partial step: only lanes below nsym % NL take part
     auto partial_step = [&]() {
-        const bool act = lane < nsym - t * 64;
+        const bool act = lane < nsym - t * NL;
         uint32_t s = 0;
         if (act)
             decode_one(s);
         refill(act);
-        ob[(t & (SPB - 1)) * 64] = static_cast<OutT>(s);
+        if (live)
+            ob[(t & (SPB - 1)) * NL] = static_cast<OutT>(s);
         ++t;
     };
+    // A step reads at most 2 NL <= 128 digit bytes, so four steps that start below
+    // wend = 256 (kw + 1) stay inside windows kw .. kw + 2.  Moving kw on
+    // issues window kw + 7 into the slot of the window just finished, then
+    // waits until at most five later loads are pending: window kw + 2 is in.
+    auto advance = [&]() {
+        while (bpos >= wend) {
+            ++kw;
+            wend += kWin;
+            if (kw + kSlots - 1 < nwin) {
+                issue(kw + kSlots - 1);
+                wait_vm<5>();
+            } else {
+                wait_vm<0>();
+            }
+        }
+    };
 
-    // Four steps read fewer than WD digits, so with pos < wend (= (kw+1)*WD)
-    // they stay inside the resident windows kw, kw+1: the window test runs
-    // once per four steps.  When fewer than four full steps remain, one shift
-    // (if pos has entered window kw+1) keeps the rest inside the ring too.
-    bool done = false;
-#define RANS_SHIFT(PREG)                                                   \
-    do {                                                                   \
-        wait_vm<3>();                                                      \
-        put_window(kw + 2, PREG);                                          \
-        PREG = async_load2(waddr(kw + 6));                                 \
-        ++kw;                                                              \
-        wend += WD;                                                        \
-    } while (0)
-#define RANS_PHASE(PREG)                                                   \
-    if (!done) {                                                           \
-        while (t + 4 <= full && pos < wend)                                \
-            step4();                                                       \
-        if (t + 4 <= full) {                                               \
-            RANS_SHIFT(PREG);                                              \
-        } else {                                                           \
-            if (pos >= wend)                                               \
-                RANS_SHIFT(PREG);                                          \
-            while (t < full)                                               \
-                step_single();                                             \
-            if (t < steps)                                                 \
-                partial_step();                                            \
-            done = true;                                                   \
-        }                                                                  \
+    while (t + 4 <= full) {
+        advance();
+        step4();
     }
-    while (!done) {
-        RANS_PHASE(p2)
-        RANS_PHASE(p3)
-        RANS_PHASE(p0)
-        RANS_PHASE(p1)
-    }
-#undef RANS_PHASE
-#undef RANS_SHIFT
+    advance();  // fewer than four steps remain
+    while (t < full)
+        step_single();
+    if (t < steps)
+        partial_step();
+
     // Blocks that ended inside the full steps were flushed; the rest,
     // [tb, steps), holds the ragged end: whole lane pieces, then the one
     // lane that straddles the end byte by byte.
     const uint32_t tb = (full / SPB) * SPB;
+    lane_fence();
     if (tb < steps) {
-        const uint32_t nbytes = (nsym - tb * 64) * W;  // valid bytes of this block
-        uint8_t* dst = reinterpret_cast<uint8_t*>(out + uint64_t(tb) * 64);
+        const uint32_t nbytes = (nsym - tb * NL) * W;  // valid bytes of this block
+        uint8_t* dst = reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL);
         if (PIECE * lane + PIECE <= nbytes) {
             *reinterpret_cast<Piece*>(dst + PIECE * lane) = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
         } else if (PIECE * lane < nbytes) {
@@ -304,8 +326,8 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
                 dst[b] = obuf[b];
         }
     }
-    wait_vm<0>();
-    const bool bad = x != L || pos != ndig;
+    wait_vm<0>();  // windows fetched ahead land before wave_lds is reused
+    const bool bad = x != L || bpos != plen;
     if (ballot(bad) && lane == 0)
         atomicMin(status, RANS_ECORRUPT);
 }
@@ -348,7 +370,7 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, bool& nosy
     }
 }
 
-template <int R, int W>
+template <int R, int W, int NL>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
                                              const uint4* l_enc, uint8_t* slot, uint64_t slot_bytes,
@@ -357,37 +379,40 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
                                              uint32_t* nd_out = nullptr)
 {
     using InT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
-    constexpr uint32_t SPB = 16 / W;  // steps per 1 KiB symbol block
+    constexpr uint32_t SPB = 1024 / (W * NL);  // steps per 1 KiB symbol block
     const uint32_t lane = threadIdx.x & 63;
+    const bool live = NL == 64 || lane < NL;
     const uint64_t first = chunk * C;
     const uint32_t nsym = uni(static_cast<uint32_t>(n - first < C ? n - first : C));
     const InT* in = static_cast<const InT*>(syms_base) + first;
     const uint32_t junk = static_cast<uint32_t>(slot_bytes);  // byte offset of the junk area
     const uint32_t sh = l + R - k;
-    const uint32_t steps = (nsym + 63) / 64;
-    const uint32_t nblk = nsym / (64 * SPB);  // whole blocks
+    const uint32_t steps = (nsym + NL - 1) / NL;
+    const uint32_t nblk = nsym / (NL * SPB);  // whole blocks
     uint32_t x = 1u << l;
     uint32_t wpos = uni(static_cast<uint32_t>(slot_bytes / (R / 8)));
     bool nosym = false;
 
     // steps above the whole blocks (the partial tail), one at a time
     for (uint32_t t = steps; t-- > nblk * SPB;) {
-        const uint64_t i = uint64_t(t) * 64 + lane;
-        const bool act = i < nsym;
+        const uint64_t i = uint64_t(t) * NL + lane;
+        const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
         enc_step<R>(x, wpos, nosym, s, act, l_enc, alphabet, sh, slot, junk, lane);
     }
 
     if (nblk > 0) {
-        // block b = symbols [b*64*SPB, (b+1)*64*SPB); lane loads 16 bytes
+        // block b = symbols [b*NL*SPB, (b+1)*NL*SPB); lane loads 16 bytes
         const uint4* blk = reinterpret_cast<const uint4*>(in) + lane;
         auto load_blk = [&](int64_t b) { return blk[(b < 0 ? 0 : b) * 64]; };
         auto run_blk = [&](uint4 v) {
+            lane_fence();
             *reinterpret_cast<uint4*>(sbuf + 16 * lane) = v;
+            lane_fence();
             const InT* sb = reinterpret_cast<const InT*>(sbuf) + lane;
 #pragma unroll
             for (int q = SPB - 1; q >= 0; --q)
-                enc_step<R>(x, wpos, nosym, sb[q * 64], true, l_enc, alphabet, sh, slot, junk, lane);
+                enc_step<R>(x, wpos, nosym, sb[q * NL], live, l_enc, alphabet, sh, slot, junk, lane);
         };
         int64_t b = int64_t(nblk) - 1;
         uint4 A = load_blk(b);
@@ -405,7 +430,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             --b;
         }
     }
-    if (states_out)
+    if (states_out && live)
         states_out[lane] = x;
     if (ndig_out && lane == 0)
         *ndig_out = static_cast<uint32_t>(slot_bytes / (R / 8)) - wpos;
@@ -432,56 +457,70 @@ __device__ __forceinline__ uint4 funnel16(const uint4& lo, const uint4& hi, uint
                       __builtin_amdgcn_alignbyte(a3, a2, b), __builtin_amdgcn_alignbyte(a4, a3, b));
 }
 
-constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kValMask = (1ull << 62) - 1;
+constexpr uint64_t kFlag = 1ull << 62, kValMask = kFlag - 1;
 
-// Places encoded chunk `chunk` (64 final states in x, nd digits ending at
-// slot + slot_bytes) into the container by decoupled look-back over the
-// published lengths of its predecessors, which all started earlier (chunk
-// indices are taken from a ticket in start order), so the walk ends.  The
-// walk is bounded; a timeout reports RANS_EINVAL and writes nothing.
-template <int R>
+// Sum over the wave of one 64-bit value per lane.
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v)
+{
+    for (int d = 32; d >= 1; d >>= 1)
+        v += static_cast<uint64_t>(__shfl_xor(static_cast<long long>(v), d));
+    return v;
+}
+
+// Lane-parallel wait for a published word (flag bit set); bounded spin.
+// The words carry self-contained values (lengths) and order nothing else, so
+// they are relaxed device-scope atomics: coherent across the chip's L2
+// slices without the whole-L2 write-back / invalidate that acquire and
+// release would add to every publish and every spin iteration.
+__device__ __forceinline__ uint64_t await_word(const uint64_t* w, bool& timeout)
+{
+    uint32_t spins = 0;
+    for (;;) {
+        const uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v & kFlag)
+            return v & kValMask;
+        if (++spins > (1u << 22)) {
+            timeout = true;
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Places encoded chunk `chunk` (NL final states in x, nd digits ending at
+// slot + slot_bytes) into the container.  Its offset is the sum of the
+// padded lengths of all lower chunks, found in two lane-parallel levels:
+// every chunk publishes its length; the lengths of the lower chunks of its
+// own group of 64 are read one per lane and summed; the last chunk of each
+// group publishes the group's total; the totals of the lower groups are
+// read 64 at a time and summed.  A chunk only waits on lower chunks, which
+// started earlier (chunk indices come from a ticket in start order), so the
+// waits end; they are bounded anyway, and a timeout reports RANS_EINVAL and
+// writes nothing.  p.lookback holds nch chunk words, then the group words,
+// all zero before the kernel.
+template <int R, int NL>
 __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32_t x, uint32_t nd,
                                             const uint8_t* slot, uint64_t slot_bytes,
                                             const PlaceArgs& p, int32_t* status)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t pay = nd * (R / 8);
-    const uint32_t len = 256 + pay;
+    const uint32_t len = 4 * NL + pay;
     const uint64_t al = (uint64_t(len) + 15) & ~15ull;
-    uint64_t excl = 0;
-    uint32_t timeout = 0;
-    if (lane == 0) {
-        if (chunk == 0) {
-            __hip_atomic_store(&p.lookback[0], kFlagInc | al, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&p.lookback[chunk], kFlagAgg | al, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t j = chunk - 1;
-            uint32_t spins = 0;
-            for (;;) {
-                const uint64_t v =
-                    __hip_atomic_load(&p.lookback[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if ((v >> 62) == 2) {
-                    excl += v & kValMask;
-                    break;
-                }
-                if ((v >> 62) == 1) {
-                    excl += v & kValMask;
-                    --j;  // chunk 0 publishes an inclusive value, so j stays >= 0
-                    continue;
-                }
-                if (++spins > (1u << 22)) {
-                    timeout = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-            __hip_atomic_store(&p.lookback[chunk], kFlagInc | (excl + al), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-    excl = uni64(excl);  // lane 0 is the first active lane
-    timeout = uni(timeout);
+    uint64_t* agg = p.lookback;
+    uint64_t* grp = p.lookback + nch;
+    if (lane == 0)
+        __hip_atomic_store(&agg[chunk], kFlag | al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool timeout = false;
+    const uint32_t g = chunk >> 6, g0 = chunk & ~63u;
+    const uint64_t local = wave_sum(g0 + lane < chunk ? await_word(&agg[g0 + lane], timeout) : 0);
+    if ((chunk & 63) == 63 && lane == 0)
+        __hip_atomic_store(&grp[g], kFlag | (local + al), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t before = 0;
+    for (uint32_t b = 0; b < g; b += 64)
+        before += wave_sum(b + lane < g ? await_word(&grp[b + lane], timeout) : 0);
+    const uint64_t excl = uni64(before + local);
+    timeout = ballot(timeout) != 0;
     const uint64_t base = (kHeaderBytes + uint64_t(kDirEntryBytes) * nch + 15) & ~15ull;
     const uint64_t off = base + excl;
     const bool fits = !timeout && off + al <= p.out_cap;
@@ -493,13 +532,14 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
             de[2] = len;
             de[3] = 0;
         }
-        reinterpret_cast<uint32_t*>(dst)[lane] = x;
+        if (NL == 64 || lane < NL)
+            reinterpret_cast<uint32_t*>(dst)[lane] = x;
         const uint8_t* src = slot + slot_bytes - pay;
         const uint32_t mis = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(src) & 15);
         // reads reach at most 31 bytes past the slot: inside its junk area
         const uint4* S = reinterpret_cast<const uint4*>(src - mis);
-        uint4* D = reinterpret_cast<uint4*>(dst + 256);
-        const uint32_t pieces = static_cast<uint32_t>((al - 256) / 16);
+        uint4* D = reinterpret_cast<uint4*>(dst + 4 * NL);
+        const uint32_t pieces = static_cast<uint32_t>((al - 4 * NL) / 16);
         for (uint32_t q = lane; q < pieces; q += 64) {
             uint4 v = funnel16(S[q], S[q + 1], mis);
             const uint32_t have = pay - 16 * q;  // > 0 for every piece

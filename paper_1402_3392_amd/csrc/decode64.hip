@@ -1,11 +1,12 @@
-// Single-buffer N = 64 decode kernel: one wave per chunk, tables staged in
-// LDS once per block; the chunk coder itself is c64::decode_chunk.
+// Single-buffer decode kernel for N = 32 or 64 interleaved coders: one wave
+// per chunk, tables staged in LDS once per block; the chunk coder itself is
+// c64::decode_chunk.
 #include "coder64.h"
 
 namespace rans {
 namespace {
 
-template <int R, int W, int SW, int LAYOUT>
+template <int R, int W, int SW, int LAYOUT, int NL>
 __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -15,7 +16,10 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
     const void* ent = LAYOUT == kPacked ? a.tab0 : (LAYOUT == kFused ? a.tab0 : a.tab1);
     const uint32_t sym_bytes = LAYOUT == kPacked ? a.tab1_bytes : (LAYOUT == kFused ? 0 : a.tab0_bytes);
     const uint32_t ent_bytes = LAYOUT == kPacked ? a.tab0_bytes : (LAYOUT == kFused ? a.tab0_bytes : a.tab1_bytes);
-    c64::stage2(lds, symsrc, sym_bytes, ent, ent_bytes);
+    // the waves' rings and output blocks first (low LDS addresses for the
+    // direct-to-LDS loads), the tables after them
+    uint8_t* tab = lds + c64::uni(blockDim.x >> 6) * c64::wave_lds_bytes(LAYOUT);
+    c64::stage2(tab, symsrc, sym_bytes, ent, ent_bytes);
     __syncthreads();
     // wave-uniform by construction; readfirstlane lets the compiler keep
     // everything derived from it in SGPRs
@@ -23,19 +27,18 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
     const uint64_t chunk = uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (chunk >= a.n_chunks)
         return;  // no barrier follows
-    c64::decode_chunk<R, W, SW, LAYOUT>(a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, lds,
-                                        reinterpret_cast<const uint32_t*>(lds + sym_bytes),
-                                        lds + sym_bytes + ent_bytes + wave * c64::wave_lds_bytes(LAYOUT),
-                                        a.status);
+    c64::decode_chunk<R, W, SW, LAYOUT, NL>(a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, tab,
+                                        reinterpret_cast<const uint32_t*>(tab + sym_bytes),
+                                        lds + wave * c64::wave_lds_bytes(LAYOUT), a.status);
 }
 
-template <int R, int W, int SW, int LAYOUT>
+template <int R, int W, int SW, int LAYOUT, int NL>
 hipError_t run(const DecodeArgs& a, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
     const uint32_t lds = a.tab0_bytes + a.tab1_bytes + wpb * c64::wave_lds_bytes(LAYOUT);
-    auto kern = k_decode64<R, W, SW, LAYOUT>;
+    auto kern = k_decode64<R, W, SW, LAYOUT, NL>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -44,12 +47,18 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int R, int W, int SW, int LAYOUT>
+hipError_t run_n(const DecodeArgs& a, hipStream_t st)
+{
+    return a.N == 32 ? run<R, W, SW, LAYOUT, 32>(a, st) : run<R, W, SW, LAYOUT, 64>(a, st);
+}
+
 template <int R, int W, int SW>
 hipError_t run_l(const DecodeArgs& a, Layout layout, hipStream_t st)
 {
     if (SW == 1 && layout == kFused)
-        return run<R, W, 1, kFused>(a, st);
-    return layout == kPacked ? run<R, W, SW, kPacked>(a, st) : run<R, W, SW, kTwoLevel>(a, st);
+        return run_n<R, W, 1, kFused>(a, st);
+    return layout == kPacked ? run_n<R, W, SW, kPacked>(a, st) : run_n<R, W, SW, kTwoLevel>(a, st);
 }
 
 template <int R>

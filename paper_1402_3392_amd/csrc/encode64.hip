@@ -1,29 +1,15 @@
-// Single-buffer N = 64 encode kernel: one wave per chunk, encoder entries
-// staged in LDS once per block; the chunk coder is c64::encode_chunk.
+// Single-buffer encode kernel for N = 32 or 64 interleaved coders: one wave
+// per chunk, encoder entries staged in LDS once per block; the chunk coder is
+// c64::encode_chunk and the chunk is placed into the container in the same
+// kernel by c64::place_chunk.
 #include "coder64.h"
 
 namespace rans {
 namespace {
 
-template <int R, int W>
-__global__ void __launch_bounds__(1024) k_encode64(const EncodeArgs a)
-{
-    extern __shared__ __align__(16) uint8_t lds[];
-    c64::stage2(lds, a.enc, a.enc_bytes, nullptr, 0);
-    __syncthreads();
-    const uint32_t wave = c64::uni(threadIdx.x >> 6);
-    const uint64_t chunk = uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
-    if (chunk >= a.n_chunks)
-        return;
-    c64::encode_chunk<R, W>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
-                            reinterpret_cast<const uint4*>(lds), a.slots + chunk * a.slot_stride,
-                            a.slot_bytes, lds + a.enc_bytes + wave * 1024, a.states + chunk * 64,
-                            a.ndig + chunk, a.status);
-}
-
-// Encode with placement: chunk indices come from a ticket in start order so
-// that every look-back only waits on chunks that are already running.
-template <int R, int W>
+// Chunk indices come from a ticket in start order so that every look-back
+// only waits on chunks that are already running.
+template <int R, int W, int NL>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -38,19 +24,19 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
         return;
     uint8_t* slot = a.slots + uint64_t(chunk) * a.slot_stride;
     uint32_t x = 0, nd = 0;
-    c64::encode_chunk<R, W>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
-                            reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
-                            lds + a.enc_bytes + wave * 1024, nullptr, nullptr, a.status, &x, &nd);
-    c64::place_chunk<R>(chunk, a.n_chunks, x, c64::uni(nd), slot, a.slot_bytes, p, a.status);
+    c64::encode_chunk<R, W, NL>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
+                                reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
+                                lds + a.enc_bytes + wave * 1024, nullptr, nullptr, a.status, &x, &nd);
+    c64::place_chunk<R, NL>(chunk, a.n_chunks, x, c64::uni(nd), slot, a.slot_bytes, p, a.status);
 }
 
-template <int R, int W>
+template <int R, int W, int NL>
 hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
     const uint32_t lds = a.enc_bytes + wpb * 1024;
-    auto kern = k_encode64_place<R, W>;
+    auto kern = k_encode64_place<R, W, NL>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -59,19 +45,12 @@ hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int R, int W>
-hipError_t run(const EncodeArgs& a, hipStream_t st)
+template <int NL>
+hipError_t run_n(const EncodeArgs& a, const PlaceArgs& p, int R, int W, hipStream_t st)
 {
-    const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
-    const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
-    const uint32_t lds = a.enc_bytes + wpb * 1024;
-    auto kern = k_encode64<R, W>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a);
-    return hipGetLastError();
+    if (R == 16)
+        return W == 1 ? run_place<16, 1, NL>(a, p, st) : run_place<16, 2, NL>(a, p, st);
+    return W == 1 ? run_place<8, 1, NL>(a, p, st) : run_place<8, 2, NL>(a, p, st);
 }
 
 }  // namespace
@@ -81,18 +60,7 @@ hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R,
 {
     if (a.n_chunks == 0)
         return hipSuccess;
-    if (R == 16)
-        return W == 1 ? run_place<16, 1>(a, p, stream) : run_place<16, 2>(a, p, stream);
-    return W == 1 ? run_place<8, 1>(a, p, stream) : run_place<8, 2>(a, p, stream);
-}
-
-hipError_t launch_encode64(const EncodeArgs& a, int R, int W, hipStream_t stream)
-{
-    if (a.n_chunks == 0)
-        return hipSuccess;
-    if (R == 16)
-        return W == 1 ? run<16, 1>(a, stream) : run<16, 2>(a, stream);
-    return W == 1 ? run<8, 1>(a, stream) : run<8, 2>(a, stream);
+    return a.N == 32 ? run_n<32>(a, p, R, W, stream) : run_n<64>(a, p, R, W, stream);
 }
 
 }  // namespace rans

@@ -82,12 +82,13 @@ struct EncodeArgs {
     int32_t* status;
 };
 
-// Placement of encoded chunks by decoupled look-back (N = 64 encoder): each
-// chunk publishes its aligned length, sums its predecessors' published
-// values and copies itself to its final offset.
+// Placement of encoded chunks inside the encode kernel (N = 32, 64): each
+// chunk publishes its aligned length, sums the published lengths of the
+// chunks below it (two lane-parallel levels: its group of 64, then the group
+// totals) and copies itself to its final offset.
 struct PlaceArgs {
     uint32_t* ticket;      // chunk tickets in start order (zeroed before)
-    uint64_t* lookback;    // n_chunks words: flag << 62 | value (zeroed before)
+    uint64_t* lookback;    // n_chunks + ceil(n_chunks / 64) words: flag << 62 | value (zeroed before)
     uint8_t* out;
     uint64_t out_cap;
     uint64_t* total;       // container length (workspace)
@@ -167,11 +168,10 @@ struct BatchArgs {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint32_t count, hipStream_t stream);
 hipError_t launch_decode(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
 hipError_t launch_encode(const EncodeArgs& a, int R, int W, hipStream_t stream);
-// N = 64 fast paths (decode64.hip / encode64.hip); need (C * w) % 16 == 0 and
-// 16-byte aligned symbol buffers.
+// One-wave-per-chunk fast paths for N = 32 or 64 (decode64.hip /
+// encode64.hip); need (C * w) % 16 == 0 and 16-byte aligned symbol buffers.
 hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t stream);
-hipError_t launch_encode64(const EncodeArgs& a, int R, int W, hipStream_t stream);
-// N = 64 encode with in-kernel placement (no scan / compaction kernels).
+// Encode with in-kernel placement (no scan / compaction kernels).
 hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
                                  hipStream_t stream);
 uint32_t decode64_lds_per_wave(Layout layout);

@@ -49,7 +49,7 @@ struct EncodeLayout {
     uint64_t chunk_off;  // n_chunks u64
     uint64_t states;     // n_chunks * N u32
     uint64_t slots;      // n_chunks * slot_stride
-    uint64_t lookback;   // n_chunks u64 (placement by look-back)
+    uint64_t lookback;   // n_chunks + ceil(n_chunks / 64) u64 (in-kernel placement)
     uint64_t total;
 };
 

@@ -54,9 +54,9 @@ class Pool:
         return self.buf[o:o + nbytes].cpu().numpy()
 
 
-def run_encode_batch(lr, data, k, r, l, C, cap_override=None):
+def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64):
     import torch
-    params = lr.rans_params.make(k, r, l, 1, 64, C)
+    params = lr.rans_params.make(k, r, l, 1, N, C)
     tables, specs = [], []
     total = sum(s.size for s, _ in data)
     pool = Pool(sum(lr.rans_encode_bound(s.size, params) + s.size + 1024 for s, _ in data))
@@ -81,9 +81,9 @@ def run_encode_batch(lr, data, k, r, l, C, cap_override=None):
     return tables, outs, st.cpu().numpy(), lens.cpu().numpy()
 
 
-def run_decode_batch(lr, tables, containers, sizes, k, r, l, corrupt=None):
+def run_decode_batch(lr, tables, containers, sizes, k, r, l, corrupt=None, N=64):
     import torch
-    params = lr.rans_params.make(k, r, l, 1, 64, 0)
+    params = lr.rans_params.make(k, r, l, 1, N, 0)
     pool = Pool(sum(c.size + n + 1024 for c, n in zip(containers, sizes)))
     lens = torch.zeros(len(containers), dtype=torch.int64, device="cuda")
     st = torch.full((len(containers),), 99, dtype=torch.int32, device="cuda")
@@ -101,18 +101,20 @@ def run_decode_batch(lr, tables, containers, sizes, k, r, l, corrupt=None):
     return outs, st.cpu().numpy(), lens.cpu().numpy()
 
 
-@pytest.mark.parametrize("k,r,l,C", [(14, 16, 16, 4096), (14, 16, 16, 65536), (12, 8, 23, 8192)])
-def test_batch_encode_decode_match_oracle(lr, k, r, l, C):
-    data = streams(40, seed=4100 + k + r)
-    tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C)
+@pytest.mark.parametrize("k,r,l,C,N", [(14, 16, 16, 4096, 64), (14, 16, 16, 65536, 64),
+                                       (12, 8, 23, 8192, 64), (14, 16, 16, 4096, 32),
+                                       (12, 8, 23, 2048, 32)])
+def test_batch_encode_decode_match_oracle(lr, k, r, l, C, N):
+    data = streams(40, seed=4100 + k + r + N)
+    tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C, N=N)
     assert (st == 0).all(), st
     refs = []
     for i, (s, _) in enumerate(data):
         f = oracle.quantize(datagen.counts(s, 256), k)
-        ref = oracle.encode(f, s, k, r, l, 64, C)
+        ref = oracle.encode(f, s, k, r, l, N, C)
         refs.append(ref)
         assert outs[i].size == ref.size and (outs[i] == ref).all(), (i, first_diff(outs[i], ref))
-    dec, st2, n2 = run_decode_batch(lr, tables, refs, [s.size for s, _ in data], k, r, l)
+    dec, st2, n2 = run_decode_batch(lr, tables, refs, [s.size for s, _ in data], k, r, l, N=N)
     assert (st2 == 0).all(), st2
     for i, (s, _) in enumerate(data):
         assert n2[i] == s.size

@@ -68,6 +68,13 @@ CASES = [
     (256, "zipf", 12, 16, 16, 64, 1024, 5 * 1024 + 992),
     (4096, "near_uniform", 15, 16, 16, 64, 2048, 3 * 2048 + 480),
     (256, "zipf", 12, 8, 23, 64, 1024, 5 * 1024 + 960),
+    # N = 32 on the one-wave-per-chunk kernels (lanes 32..63 idle): the last
+    # chunk is 31 full steps + a partial one (w = 1: 32 steps per block,
+    # w = 2: 16), and a high-entropy case that refills on most steps
+    (256, "zipf", 14, 16, 16, 32, 2048, 3 * 2048 + 31 * 32 + 17),
+    (4096, "near_uniform", 15, 16, 16, 32, 2048, 2 * 2048 + 15 * 32 + 5),
+    (256, "uniform", 8, 16, 16, 32, 4096, 50_000),
+    (16, "zipf", 11, 8, 23, 32, 1024, 7 * 1024 + 999),
 ]
 
 
