@@ -3,11 +3,11 @@
 //
 // Decode (rANS D, then Algorithm 1's refill; offsets from a ballot of the
 // refilling lanes plus mbcnt, Section 6):
-//  * the chunk's digit stream reaches a per-wave LDS ring of eight 256-byte
-//    windows by direct global-to-LDS loads, issued up to seven windows
-//    ahead; no register ever holds a load in flight, and the code awaits
-//    completion explicitly (s_waitcnt vmcnt) when the read position enters a
-//    new window, so a refill rarely waits on HBM latency;
+//  * the chunk's digit stream reaches a per-wave LDS ring of 256-byte
+//    windows (4 or 8 slots) by direct global-to-LDS loads issued ahead of
+//    the read position; no register ever holds a load in flight, and the
+//    code awaits completion explicitly (s_waitcnt vmcnt) when the read
+//    position enters a new window, so a refill rarely waits on HBM latency;
 //  * decoded symbols go to a per-wave LDS block and leave as one 8- or
 //    16-byte store per lane.
 // Encode (Algorithm 1's Encode with rANS's C, walking backwards):
@@ -31,13 +31,20 @@
 namespace rans {
 namespace c64 {
 
-constexpr uint32_t kWin = 256;               // stream window: one 4-byte load per lane
-constexpr uint32_t kSlots = 8;               // ring slots
-constexpr uint32_t kRing = (kSlots + 1) * kWin;  // slots + a copy of slot 0 after the last
+constexpr uint32_t kWin = 256;  // stream window: one 4-byte load per lane
 
-// Output block per wave: 1 KiB, or 512 bytes next to the large fused table.
+// Per-wave LDS geometry by table layout.  The fused table (M * 8 bytes)
+// leaves about 2 KiB per wave for 16 waves: 4 ring slots tested every 2
+// steps and a 512-byte output block.  The smaller tables take 8 slots tested
+// every 4 steps and a 1 KiB output block.  One more slot after the ring
+// holds a copy of slot 0.
+constexpr uint32_t ring_slots(int layout) { return layout == kFused ? 4 : 8; }
+constexpr uint32_t test_steps(int layout) { return layout == kFused ? 2 : 4; }
 constexpr uint32_t obuf_bytes(int layout) { return layout == kFused ? 512 : 1024; }
-constexpr uint32_t wave_lds_bytes(int layout) { return obuf_bytes(layout) + kRing; }
+constexpr uint32_t wave_lds_bytes(int layout)
+{
+    return obuf_bytes(layout) + (ring_slots(layout) + 1) * kWin;
+}
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m, uint32_t acc)
@@ -129,7 +136,13 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     const uint32_t lane = threadIdx.x & 63;
     constexpr uint32_t OB = obuf_bytes(LAYOUT);
     uint8_t* obuf = wave_lds;              // output block (first: the initial states)
-    const uint8_t* ring = wave_lds + OB;   // kSlots windows + copy of slot 0
+    constexpr uint32_t S = ring_slots(LAYOUT), TB = test_steps(LAYOUT);
+    // a block of TB steps reads at most 128 TB bytes starting below the end
+    // of window kw, so windows kw .. kw + RES - 1 must have landed; the
+    // loads of the other S - RES slots may still be in flight
+    constexpr uint32_t RES = 1 + TB / 2;
+    constexpr int AHEAD = static_cast<int>(S - RES);
+    const uint8_t* ring = wave_lds + OB;   // S windows + copy of slot 0
     const uint8_t* de = in + kHeaderBytes + kDirEntryBytes * chunk;
     // directory values are the same for the whole wave: keep them scalar
     const uint64_t off = uni64(*reinterpret_cast<const uint64_t*>(de));
@@ -147,9 +160,9 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     const uint32_t plen = len - 4 * NL;  // digit bytes after the NL states
     const uint32_t L = 1u << l, k = k_, mask = (1u << k) - 1;
 
-    // Window w = digit bytes [256 w, 256 w + 256) sits in ring slot w % 8;
-    // windows 0, 8, 16, ... go to one more slot after the last as well, so a
-    // read that starts in slot 7 runs on into the next window unwrapped.
+    // Window w = digit bytes [256 w, 256 w + 256) sits in ring slot w % S;
+    // windows 0, S, 2S, ... go to one more slot after the last as well, so a
+    // read that starts in slot S - 1 runs on into the next window unwrapped.
     // Lane addresses past the container (whole 4-byte words) are pulled back
     // to its last word; such bytes are never used.
     const uint64_t room = (in_len - 4) & ~3ull;  // in_len >= 176 here
@@ -165,21 +178,51 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     };
     const uint64_t pay = off + 4 * NL;
     const uint32_t nwin = (plen + kWin - 1) / kWin;
+    // windows below wfast lie wholly inside the container: no clamping
+    const uint32_t wfast =
+        uni(room + 4 >= pay + kWin ? static_cast<uint32_t>((room + 4 - pay - kWin) / kWin) + 1 : 0u);
+    // Vector-memory operations (these loads and the output stores) complete
+    // in issue order.  The wait after a window load leaves in flight the
+    // operations issued after the load of window kw + RES - 1: the AHEAD
+    // window loads after it plus the stores and slot-0 copies among them,
+    // counted per window interval in hist[] (oldest first) and cur (since the
+    // newest window load).
+    uint32_t hist[AHEAD > 0 ? AHEAD : 1] = {};
+    uint32_t cur = 0;
+    auto fetch_win = [&](uint32_t w, uint32_t dst) {
+        const uint64_t src = pay + uint64_t(w) * kWin;
+        if (w < wfast)
+            dma256(in + src, lane4, dst);
+        else
+            fetch(src, dst);
+    };
     auto issue = [&](uint32_t w) {
-        fetch(pay + uint64_t(w) * kWin, lds_ring + (w % kSlots) * kWin);
-        if (w % kSlots == 0)
-            fetch(pay + uint64_t(w) * kWin, lds_ring + kSlots * kWin);
+        if (w % S == 0) {  // the copy goes first, so it lands no later than the window
+            fetch_win(w, lds_ring + S * kWin);
+            ++cur;
+        }
+        fetch_win(w, lds_ring + (w % S) * kWin);
+#pragma unroll
+        for (int i = 0; i + 1 < AHEAD; ++i)
+            hist[i] = hist[i + 1];
+        hist[AHEAD - 1] = cur;
+        cur = 0;
     };
     fetch(off, lds_ob);  // coder i's initial state: bytes 4 i .. 4 i + 3 (i < NL)
 #pragma unroll
-    for (uint32_t w = 0; w < kSlots; ++w)
+    for (uint32_t w = 0; w < S; ++w)
         if (w < nwin)
             issue(w);
-    // windows 0..2 are in once at most five later loads are pending
-    if (nwin >= kSlots)
-        wait_vm<5>();
+    // windows 0 .. RES - 1 (and window 0's copy, issued before window 0)
+    // are in once at most S - RES later loads are pending
+    if (nwin >= S)
+        wait_vm<AHEAD>();
     else
         wait_vm<0>();
+#pragma unroll
+    for (int i = 0; i < AHEAD; ++i)
+        hist[i] = 0;
+    cur = 0;
     uint32_t x = reinterpret_cast<const uint32_t*>(obuf)[lane];
     lane_fence();  // the output block is reused for symbols
     if (!live)
@@ -187,14 +230,18 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
 
     constexpr uint32_t SPB = OB / (NL * W);    // steps per output block
     constexpr uint32_t PIECE = OB / 64;         // bytes each lane moves per block
-    constexpr uint32_t RMASK = kSlots * kWin - 1;
+    constexpr uint32_t DB = R / 8;                 // bytes per digit
+    constexpr uint32_t DMASK = S * kWin / DB - 1;  // ring size in digits, minus 1
+    constexpr uint32_t WD = kWin / DB;             // digits per window
     using Piece = typename std::conditional<PIECE == 16, uint4, uint2>::type;
     const uint32_t full = nsym / NL;           // steps with every coder active
     const uint32_t steps = (nsym + NL - 1) / NL;
     OutT* out = static_cast<OutT*>(out_base) + first;
     OutT* ob = reinterpret_cast<OutT*>(obuf) + lane;
 
-    uint32_t bpos = 0, kw = 0, wend = kWin, t = 0;  // bpos: next digit byte
+    // pos: next digit; wend: digits up to the end of window kw
+    uint32_t pos = 0, kw = 0, wend = WD, t = 0;
+    const uint32_t ndig = plen / DB;
 
     auto decode_one = [&](uint32_t& s) {
         const uint32_t x0 = x;
@@ -216,29 +263,29 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         if (!live)
             x = x0;
     };
-    // Refill: every lane reads the ring at its would-be offset (the prefix
-    // count of refilling lanes below it) and a select on the ballot keeps
-    // the word in the lanes that need it.  The step is skipped as a whole
-    // when no lane refills.
+    // Refill: every lane reads the ring at its would-be digit (the ring
+    // position, a scalar, plus the prefix count of refilling lanes below it)
+    // and a select on the ballot keeps the digit in the lanes that need it.
+    // The step is skipped as a whole when no lane refills.
     auto refill = [&](bool act) {
         const bool n1 = act && x < L;
         const uint64_t m1 = ballot(n1);
         if (R == 16) {
             if (m1) {
-                const uint32_t v =
-                    *reinterpret_cast<const uint16_t*>(ring + (bpos & RMASK) + 2 * mbcnt(m1, 0));
+                const uint16_t* rp = reinterpret_cast<const uint16_t*>(ring) + (pos & DMASK);
+                const uint32_t v = rp[mbcnt(m1, 0)];
                 x = select_mask(m1, x, (x << 16) | v);
-                bpos += 2 * __popcll(m1);
+                pos += __popcll(m1);
             }
         } else {
             const bool n2 = act && x < (L >> 8);
             const uint64_t m2 = ballot(n2);
             if (m1) {
-                const uint8_t* r = ring + (bpos & RMASK) + mbcnt(m2, mbcnt(m1, 0));
+                const uint8_t* r = ring + (pos & DMASK) + mbcnt(m2, mbcnt(m1, 0));
                 const uint32_t x1 = (x << 8) | r[0];
                 const uint32_t x2 = (x1 << 8) | r[1];
                 x = select_mask(m1, x, select_mask(m2, x1, x2));
-                bpos += __popcll(m1) + __popcll(m2);
+                pos += __popcll(m1) + __popcll(m2);
             }
         }
     };
@@ -247,6 +294,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         const Piece v = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
         lane_fence();
         *reinterpret_cast<Piece*>(reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL) + PIECE * lane) = v;
+        ++cur;  // one store instruction (more would only make waits longer)
     };
     auto step1 = [&](OutT* dst) {
         uint32_t s;
@@ -255,15 +303,14 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         if (live)
             *dst = static_cast<OutT>(s);
     };
-    // four full steps; t is a multiple of 4 here, so the output offsets are
-    // immediates and a block ends exactly at a multiple of four
-    auto step4 = [&]() {
-        OutT* o4 = ob + (t & (SPB - 1)) * NL;
-        step1(o4);
-        step1(o4 + NL);
-        step1(o4 + 2 * NL);
-        step1(o4 + 3 * NL);
-        t += 4;
+    // TB full steps; t is a multiple of TB here (and TB divides SPB), so the
+    // output offsets are immediates and an output block ends on a test block
+    auto stepblk = [&]() {
+        OutT* o = ob + (t & (SPB - 1)) * NL;
+#pragma unroll
+        for (uint32_t i = 0; i < TB; ++i)
+            step1(o + i * NL);
+        t += TB;
         if ((t & (SPB - 1)) == 0)
             flush(t - SPB);
     };
@@ -284,28 +331,53 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             ob[(t & (SPB - 1)) * NL] = static_cast<OutT>(s);
         ++t;
     };
-    // A step reads at most 2 NL <= 128 digit bytes, so four steps that start below
-    // wend = 256 (kw + 1) stay inside windows kw .. kw + 2.  Moving kw on
-    // issues window kw + 7 into the slot of the window just finished, then
-    // waits until at most five later loads are pending: window kw + 2 is in.
+    // A step reads at most 2 NL <= 128 digit bytes, so TB steps that start
+    // below wend = 256 (kw + 1) stay inside windows kw .. kw + RES - 1.
+    // Moving kw on issues window kw + S - 1 into the slot of the window just
+    // finished, then waits until at most S - RES later loads are pending:
+    // window kw + RES - 1 is in.
     auto advance = [&]() {
-        while (bpos >= wend) {
+        while (pos >= wend) {
             ++kw;
-            wend += kWin;
-            if (kw + kSlots - 1 < nwin) {
-                issue(kw + kSlots - 1);
-                wait_vm<5>();
+            wend += WD;
+            if (kw + S - 1 < nwin) {
+                issue(kw + S - 1);
+                uint32_t pend = cur;
+#pragma unroll
+                for (int i = 0; i < AHEAD; ++i)
+                    pend += hist[i];
+                // more than two extra operations: waiting as if two only waits longer
+                if (pend == 0)
+                    wait_vm<AHEAD>();
+                else if (pend == 1)
+                    wait_vm<AHEAD + 1>();
+                else
+                    wait_vm<AHEAD + 2>();
             } else {
                 wait_vm<0>();
             }
         }
     };
+    static_assert(SPB % TB == 0 && 128 * TB <= (RES - 1) * kWin && RES < S, "ring geometry");
 
-    while (t + 4 <= full) {
-        advance();
-        step4();
+    // whole output blocks: every offset is an immediate, one flush per block
+    constexpr uint32_t NB = SPB / TB;
+    while (t + SPB <= full) {
+#pragma unroll
+        for (uint32_t b = 0; b < NB; ++b) {
+            advance();
+#pragma unroll
+            for (uint32_t i = 0; i < TB; ++i)
+                step1(ob + (b * TB + i) * NL);
+        }
+        t += SPB;
+        flush(t - SPB);
     }
-    advance();  // fewer than four steps remain
+    while (t + TB <= full) {  // fewer than SPB full steps remain
+        advance();
+        stepblk();
+    }
+    advance();  // fewer than TB full steps remain
     while (t < full)
         step_single();
     if (t < steps)
@@ -327,7 +399,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         }
     }
     wait_vm<0>();  // windows fetched ahead land before wave_lds is reused
-    const bool bad = x != L || bpos != plen;
+    const bool bad = x != L || pos != ndig;
     if (ballot(bad) && lane == 0)
         atomicMin(status, RANS_ECORRUPT);
 }

@@ -1,9 +1,13 @@
 """Host model of the fast decoder's stream schedule (CPU).
 
-The N = 32/64 decode kernel copies a chunk's digit stream into an 8-slot LDS
-ring of 256-byte windows with direct-to-LDS loads issued up to seven windows
-ahead, and waits with `s_waitcnt vmcnt(5)` (or 0 near the end) whenever its
-read position enters a new window.  This model replays that schedule lane by
+The N = 32/64 decode kernel copies a chunk's digit stream into an S-slot LDS
+ring of 256-byte windows (S = 8 tested every 4 steps, or S = 4 tested every
+2 steps next to the large fused table) with direct-to-LDS loads issued up to
+S - 1 windows ahead, and waits whenever its read position enters a new
+window, leaving in flight exactly the operations issued after the newest
+window a test block may read (S - 1 - TB/2 window loads plus the output
+stores and slot-0 copies among them, counted as the kernel counts them; 0
+near the end).  This model replays that schedule lane by
 lane on the oracle's containers, with loads that land only when a wait
 guarantees them (until then their ring bytes hold random garbage), output
 stores counted as memory operations, and the same refill addressing.  It
@@ -16,10 +20,12 @@ import pytest
 import datagen
 import oracle
 
-KWIN, KSLOTS = 256, 8
+KWIN = 256
 
 
-def model_decode_chunk(cont, nch, chunk, C, n, k, l, R, f, NL, rng, OB=1024):
+def model_decode_chunk(cont, nch, chunk, C, n, k, l, R, f, NL, rng, S=8, TB=4, OB=1024):
+    RES = 1 + TB // 2
+    AHEAD = S - RES
     in_len = cont.size
     M = 1 << k
     cum = np.concatenate([[0], np.cumsum(f)])
@@ -31,7 +37,7 @@ def model_decode_chunk(cont, nch, chunk, C, n, k, l, R, f, NL, rng, OB=1024):
     nsym = min(n - first, C)
     plen = ln - 4 * NL
     room = (in_len - 4) & ~3
-    lds = rng.integers(0, 256, OB + (KSLOTS + 1) * KWIN, dtype=np.uint8)
+    lds = rng.integers(0, 256, OB + (S + 1) * KWIN, dtype=np.uint8)
     pending = []  # oldest first; None = an output store
 
     def fetch(src, dst):
@@ -50,15 +56,21 @@ def model_decode_chunk(cont, nch, chunk, C, n, k, l, R, f, NL, rng, OB=1024):
 
     pay, nwin = off + 4 * NL, (plen + KWIN - 1) // KWIN
 
+    cnt = {"hist": [0] * AHEAD, "cur": 0}
+
     def issue(w):
-        fetch(pay + w * KWIN, OB + (w % KSLOTS) * KWIN)
-        if w % KSLOTS == 0:
-            fetch(pay + w * KWIN, OB + KSLOTS * KWIN)
+        if w % S == 0:  # the copy of slot 0 first, as the kernel does
+            fetch(pay + w * KWIN, OB + S * KWIN)
+            cnt["cur"] += 1
+        fetch(pay + w * KWIN, OB + (w % S) * KWIN)
+        cnt["hist"] = cnt["hist"][1:] + [cnt["cur"]]
+        cnt["cur"] = 0
 
     fetch(off, 0)
-    for w in range(min(KSLOTS, nwin)):
+    for w in range(min(S, nwin)):
         issue(w)
-    wait(5 if nwin >= KSLOTS else 0)
+    wait(AHEAD if nwin >= S else 0)
+    cnt["hist"], cnt["cur"] = [0] * AHEAD, 0
     L = 1 << l
     live = np.arange(64) < NL
     x = np.frombuffer(lds[:256].tobytes(), "<u4").astype(np.int64).copy()
@@ -73,7 +85,7 @@ def model_decode_chunk(cont, nch, chunk, C, n, k, l, R, f, NL, rng, OB=1024):
         slot = x & (M - 1)
         sym = slot2sym[slot]
         x = np.where(act, f[sym] * (x >> k) + slot - cum[sym], x)
-        base = OB + (st["bpos"] & (KSLOTS * KWIN - 1))
+        base = OB + (st["bpos"] & (S * KWIN - 1))
         if R == 16:
             n1 = act & (x < L)
             if n1.any():
@@ -96,20 +108,21 @@ def model_decode_chunk(cont, nch, chunk, C, n, k, l, R, f, NL, rng, OB=1024):
         st["t"] = t + 1
         if st["t"] % SPB == 0:
             pending.append(None)
+            cnt["cur"] += 1
 
     def advance():
         while st["bpos"] >= st["wend"]:
             st["kw"] += 1
             st["wend"] += KWIN
-            if st["kw"] + KSLOTS - 1 < nwin:
-                issue(st["kw"] + KSLOTS - 1)
-                wait(5)
+            if st["kw"] + S - 1 < nwin:
+                issue(st["kw"] + S - 1)
+                wait(min(AHEAD + cnt["cur"] + sum(cnt["hist"]), AHEAD + 6))
             else:
                 wait(0)
 
-    while st["t"] + 4 <= full:
+    while st["t"] + TB <= full:
         advance()
-        for _ in range(4):
+        for _ in range(TB):
             step(live)
     advance()
     while st["t"] < full:
@@ -133,10 +146,12 @@ CASES = [  # k, r, l, N, C, n, zipf s (small s: high entropy, many windows per s
 ]
 
 
+@pytest.mark.parametrize("geometry", [(8, 4, 1024), (4, 2, 512)], ids=["S8", "S4"])
 @pytest.mark.parametrize("case", CASES, ids=[f"k{c[0]}-r{c[1]}-N{c[3]}-C{c[4]}-n{c[5]}-s{c[6]}"
                                              for c in CASES])
-def test_ring_schedule_decodes_oracle_containers(case):
+def test_ring_schedule_decodes_oracle_containers(case, geometry):
     k, r, l, N, C, n, s = case
+    S, TB, OB = geometry
     rng = np.random.default_rng(n + k)
     syms = rng.choice(256, size=n, p=datagen.zipf_probs(256, s)).astype(np.uint8)
     f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), k)
@@ -144,6 +159,6 @@ def test_ring_schedule_decodes_oracle_containers(case):
     f = np.asarray(f, np.int64)
     nch = (n + C - 1) // C
     for c in range(nch):
-        out, ok = model_decode_chunk(cont, nch, c, C, n, k, l, r, f, N, rng)
+        out, ok = model_decode_chunk(cont, nch, c, C, n, k, l, r, f, N, rng, S=S, TB=TB, OB=OB)
         assert ok, (c, "end check")
         assert (out == syms[c * C:c * C + C]).all(), c
