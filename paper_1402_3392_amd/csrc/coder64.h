@@ -21,6 +21,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rans_internal.h"
 
 // The direct-to-LDS load takes its LDS address in M0, which inline assembly
@@ -266,12 +268,14 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     // Refill: every lane reads the ring at its would-be digit (the ring
     // position, a scalar, plus the prefix count of refilling lanes below it)
     // and a select on the ballot keeps the digit in the lanes that need it.
-    // The step is skipped as a whole when no lane refills.
-    auto refill = [&](bool act) {
+    // In sparse chunks the step is skipped as a whole when no lane refills;
+    // in dense ones (dense = std::true_type) it runs unconditionally, which
+    // takes a branch off every step's dependency chain.
+    auto refill = [&](bool act, auto dense) {
         const bool n1 = act && x < L;
         const uint64_t m1 = ballot(n1);
         if (R == 16) {
-            if (m1) {
+            if (dense || m1) {
                 const uint16_t* rp = reinterpret_cast<const uint16_t*>(ring) + (pos & DMASK);
                 const uint32_t v = rp[mbcnt(m1, 0)];
                 x = select_mask(m1, x, (x << 16) | v);
@@ -280,7 +284,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         } else {
             const bool n2 = act && x < (L >> 8);
             const uint64_t m2 = ballot(n2);
-            if (m1) {
+            if (dense || m1) {
                 const uint8_t* r = ring + (pos & DMASK) + mbcnt(m2, mbcnt(m1, 0));
                 const uint32_t x1 = (x << 8) | r[0];
                 const uint32_t x2 = (x1 << 8) | r[1];
@@ -296,10 +300,10 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         *reinterpret_cast<Piece*>(reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL) + PIECE * lane) = v;
         ++cur;  // one store instruction (more would only make waits longer)
     };
-    auto step1 = [&](OutT* dst) {
+    auto step1 = [&](OutT* dst, auto dense) {
         uint32_t s;
         decode_one(s);
-        refill(live);
+        refill(live, dense);
         if (live)
             *dst = static_cast<OutT>(s);
     };
@@ -309,13 +313,13 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         OutT* o = ob + (t & (SPB - 1)) * NL;
 #pragma unroll
         for (uint32_t i = 0; i < TB; ++i)
-            step1(o + i * NL);
+            step1(o + i * NL, std::false_type{});
         t += TB;
         if ((t & (SPB - 1)) == 0)
             flush(t - SPB);
     };
     auto step_single = [&]() {
-        step1(ob + (t & (SPB - 1)) * NL);
+        step1(ob + (t & (SPB - 1)) * NL, std::false_type{});
         ++t;
         if ((t & (SPB - 1)) == 0)
             flush(t - SPB);
@@ -326,7 +330,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         uint32_t s = 0;
         if (act)
             decode_one(s);
-        refill(act);
+        refill(act, std::false_type{});
         if (live)
             ob[(t & (SPB - 1)) * NL] = static_cast<OutT>(s);
         ++t;
@@ -362,17 +366,25 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
 
     // whole output blocks: every offset is an immediate, one flush per block
     constexpr uint32_t NB = SPB / TB;
-    while (t + SPB <= full) {
+    auto blocks = [&](auto dense) {
+        while (t + SPB <= full) {
 #pragma unroll
-        for (uint32_t b = 0; b < NB; ++b) {
-            advance();
+            for (uint32_t b = 0; b < NB; ++b) {
+                advance();
 #pragma unroll
-            for (uint32_t i = 0; i < TB; ++i)
-                step1(ob + (b * TB + i) * NL);
+                for (uint32_t i = 0; i < TB; ++i)
+                    step1(ob + (b * TB + i) * NL, dense);
+            }
+            t += SPB;
+            flush(t - SPB);
         }
-        t += SPB;
-        flush(t - SPB);
-    }
+    };
+    // dense: at least one refill per 16 coder steps (two digits per refill
+    // at most with byte digits), so a step without any refill is rare
+    if (uint64_t(ndig) * 16 >= uint64_t(nsym) * (R == 8 ? 2 : 1))
+        blocks(std::true_type{});
+    else
+        blocks(std::false_type{});
     while (t + TB <= full) {  // fewer than SPB full steps remain
         advance();
         stepblk();
