@@ -45,9 +45,11 @@ uint32_t log2u(uint32_t v)
 // most ceil(k/r) divisions by b.
 uint32_t max_digits(uint32_t k, uint32_t r) { return (k + r - 1) / r; }
 
+// Digit slot of one chunk: room for its largest stream, rounded to 256 bytes
+// (the encoder writes whole 256-byte windows, aligned to the slot).
 uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r)
 {
-    return (uint64_t(C) * max_digits(k, r) * (r / 8) + 15) & ~uint64_t(15);
+    return (uint64_t(C) * max_digits(k, r) * (r / 8) + 255) & ~uint64_t(255);
 }
 
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch)

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ uint32_t s_slot[2];
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
-    uint8_t* sbuf = lds + a.tab_lds + wave * 1024;
+    uint8_t* sbuf = lds + a.tab_lds + wave * c64::kEncWaveLds;
     int cur = -1;
     uint32_t item;
     for (;;) {
@@ -353,7 +353,7 @@ hipError_t persistent_decode_w(const BatchArgs& a, int W, int SW, Layout layout,
 template <int R, int W, int NL>
 hipError_t persistent_encode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
-    const uint32_t lds = a.tab_lds + a.G * 1024;
+    const uint32_t lds = a.tab_lds + a.G * c64::kEncWaveLds;
     auto kern = k_batch_encode64<R, W, NL>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)

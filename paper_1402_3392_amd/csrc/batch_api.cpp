@@ -175,7 +175,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     }
     if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull)
         return RANS_EINVAL;
-    const uint32_t per_wave = decode ? decode64_lds_per_wave(layout) : 1024;
+    const uint32_t per_wave = decode ? decode64_lds_per_wave(layout) : kEncWaveLdsBytes;
     if (uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
         return RANS_EINVAL;
 

@@ -13,10 +13,9 @@
 // Encode (Algorithm 1's Encode with rANS's C, walking backwards):
 //  * symbols arrive in 1 KiB blocks, one 16-byte load per lane issued a block
 //    ahead and transposed through LDS;
-//  * every step issues exactly one digit store per lane (two for byte
-//    digits); lanes with nothing to emit store into a junk area past the
-//    slot.  A fixed number of memory operations per block lets the
-//    compiler's wait for the next block leave recent stores in flight.
+//  * digits go to a per-wave LDS ring at positions from a ballot prefix and
+//    reach HBM a 256-byte window at a time, one coalesced 4-byte store per
+//    lane, instead of a scattered 2-byte store per lane and step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -416,35 +415,41 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         atomicMin(status, RANS_ECORRUPT);
 }
 
-// Encodes chunk `chunk` of syms_base (n symbols, C per chunk) into the digit
-// slot `slot` (digits end at slot + slot_bytes; 128 junk bytes follow),
-// writes the 64 final states to states_out and the digit count to *ndig_out.
-// l_enc: LDS encoder entries (alphabet + 1), wave_lds: this wave's 1 KiB.
+// Per-wave LDS of the encoder: a 1 KiB symbol block, then a 1 KiB digit ring.
+constexpr uint32_t kEncWaveLds = kEncWaveLdsBytes;
+static_assert(kEncWaveLds == 2048, "encoder LDS layout");
+
+// One encoder step (Algorithm 1's Encode with rANS's C) for every lane:
+// emits the digits the renormalisation drops into the wave's LDS digit ring
+// (at their slot positions modulo the ring; positions from a ballot prefix,
+// the stream growing downwards), then applies C.  fmin tracks the smallest
+// f seen (0: a symbol the table cannot encode).
 template <int R>
-__device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, bool& nosym, uint32_t s, bool act,
+__device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& fmin, uint32_t s, bool act,
                                          const uint4* l_enc, uint32_t alphabet, uint32_t sh,
-                                         uint8_t* slot, uint32_t junk, uint32_t lane)
+                                         uint8_t* dring)
 {
+    constexpr uint32_t RD = 1024 / (R / 8);  // ring size in digits
     const uint4 e = l_enc[min(s, alphabet)];
     const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16;
-    nosym |= act && f == 0;
+    if (act)
+        fmin = min(fmin, f);
     const bool e1 = act && (x >> sh) >= f;
     if (R == 16) {
         const uint64_t m = ballot(e1);
         wpos -= __popcll(m);
-        const uint32_t idx = mbcnt(m, wpos);
-        const uint32_t o = e1 ? 2 * idx : junk + 2 * lane;
-        *reinterpret_cast<uint16_t*>(slot + o) = static_cast<uint16_t>(x);
+        if (e1)
+            reinterpret_cast<uint16_t*>(dring)[mbcnt(m, wpos) & (RD - 1)] = static_cast<uint16_t>(x);
         x = e1 ? x >> 16 : x;
     } else {
         const bool e2 = act && (x >> (sh + 8)) >= f;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
         wpos -= __popcll(m1) + __popcll(m2);
         const uint32_t idx = mbcnt(m2, mbcnt(m1, wpos));
-        const uint32_t o1 = e1 ? idx : junk + lane;
-        const uint32_t o2 = e2 ? idx + 1 : junk + 64 + lane;
-        slot[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
-        slot[o2] = static_cast<uint8_t>(x);
+        if (e1)
+            dring[idx & (RD - 1)] = static_cast<uint8_t>(e2 ? x >> 8 : x);
+        if (e2)
+            dring[(idx + 1) & (RD - 1)] = static_cast<uint8_t>(x);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     if (act) {
@@ -454,35 +459,62 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, bool& nosy
     }
 }
 
+// Encodes chunk `chunk` of syms_base (n symbols, C per chunk, NL = 32 or 64
+// interleaved coders) into the digit slot `slot` (digits end at slot +
+// slot_bytes, a multiple of 256; 128 more bytes follow), writes the NL final
+// states to states_out and the digit count to *ndig_out (or to the
+// caller's x_out / nd_out).  l_enc: LDS encoder entries (alphabet + 1);
+// wave_lds: this wave's kEncWaveLds bytes.  Digits reach the slot from the
+// LDS ring a 256-byte window at a time, one 4-byte store per lane, as soon
+// as the stream has grown past the window.
 template <int R, int W, int NL>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
                                              const uint4* l_enc, uint8_t* slot, uint64_t slot_bytes,
-                                             uint8_t* sbuf, uint32_t* states_out, uint32_t* ndig_out,
+                                             uint8_t* wave_lds, uint32_t* states_out, uint32_t* ndig_out,
                                              int32_t* status, uint32_t* x_out = nullptr,
                                              uint32_t* nd_out = nullptr)
 {
     using InT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
     constexpr uint32_t SPB = 1024 / (W * NL);  // steps per 1 KiB symbol block
+    constexpr uint32_t DB = R / 8, WD = 256 / DB;  // bytes per digit, digits per window
     const uint32_t lane = threadIdx.x & 63;
     const bool live = NL == 64 || lane < NL;
+    uint8_t* sbuf = wave_lds;
+    uint8_t* dring = wave_lds + 1024;
     const uint64_t first = chunk * C;
     const uint32_t nsym = uni(static_cast<uint32_t>(n - first < C ? n - first : C));
     const InT* in = static_cast<const InT*>(syms_base) + first;
-    const uint32_t junk = static_cast<uint32_t>(slot_bytes);  // byte offset of the junk area
     const uint32_t sh = l + R - k;
     const uint32_t steps = (nsym + NL - 1) / NL;
     const uint32_t nblk = nsym / (NL * SPB);  // whole blocks
+    const uint32_t top = uni(static_cast<uint32_t>(slot_bytes / DB));
     uint32_t x = 1u << l;
-    uint32_t wpos = uni(static_cast<uint32_t>(slot_bytes / (R / 8)));
-    bool nosym = false;
+    uint32_t wpos = top;       // lowest digit written so far
+    uint32_t wlo = top - WD;   // first digit of the window being filled
+    uint32_t fmin = 0xFFFFu;
+
+    auto store_window = [&](uint32_t lo) {  // ring window holding digits [lo, lo + WD)
+        lane_fence();
+        const uint32_t v = reinterpret_cast<const uint32_t*>(dring + ((lo * DB) & 1023u))[lane];
+        lane_fence();
+        reinterpret_cast<uint32_t*>(slot + uint64_t(lo) * DB)[lane] = v;
+    };
+    // a step emits at most 64 * 2 bytes < 256, so it completes one window at most
+    auto after_step = [&]() {
+        if (wpos < wlo) {
+            store_window(wlo);
+            wlo -= WD;
+        }
+    };
 
     // steps above the whole blocks (the partial tail), one at a time
     for (uint32_t t = steps; t-- > nblk * SPB;) {
         const uint64_t i = uint64_t(t) * NL + lane;
         const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
-        enc_step<R>(x, wpos, nosym, s, act, l_enc, alphabet, sh, slot, junk, lane);
+        enc_step<R>(x, wpos, fmin, s, act, l_enc, alphabet, sh, dring);
+        after_step();
     }
 
     if (nblk > 0) {
@@ -495,8 +527,10 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             lane_fence();
             const InT* sb = reinterpret_cast<const InT*>(sbuf) + lane;
 #pragma unroll
-            for (int q = SPB - 1; q >= 0; --q)
-                enc_step<R>(x, wpos, nosym, sb[q * NL], live, l_enc, alphabet, sh, slot, junk, lane);
+            for (int q = SPB - 1; q >= 0; --q) {
+                enc_step<R>(x, wpos, fmin, sb[q * NL], live, l_enc, alphabet, sh, dring);
+                after_step();
+            }
         };
         int64_t b = int64_t(nblk) - 1;
         uint4 A = load_blk(b);
@@ -514,15 +548,17 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             --b;
         }
     }
+    if (wpos < wlo + WD)  // the window holding the stream's first digits
+        store_window(wlo);
     if (states_out && live)
         states_out[lane] = x;
     if (ndig_out && lane == 0)
-        *ndig_out = static_cast<uint32_t>(slot_bytes / (R / 8)) - wpos;
+        *ndig_out = top - wpos;
     if (x_out)
         *x_out = x;
     if (nd_out)
-        *nd_out = static_cast<uint32_t>(slot_bytes / (R / 8)) - wpos;
-    if (ballot(nosym) && lane == 0)
+        *nd_out = top - wpos;
+    if (ballot(fmin == 0) && lane == 0)
         atomicMin(status, RANS_ENOSYM);
 }
 
@@ -620,7 +656,7 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
             reinterpret_cast<uint32_t*>(dst)[lane] = x;
         const uint8_t* src = slot + slot_bytes - pay;
         const uint32_t mis = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(src) & 15);
-        // reads reach at most 31 bytes past the slot: inside its junk area
+        // reads reach at most 31 bytes past the slot: inside the 128 bytes after it
         const uint4* S = reinterpret_cast<const uint4*>(src - mis);
         uint4* D = reinterpret_cast<uint4*>(dst + 4 * NL);
         const uint32_t pieces = static_cast<uint32_t>((al - 4 * NL) / 16);

@@ -26,7 +26,8 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
     uint32_t x = 0, nd = 0;
     c64::encode_chunk<R, W, NL>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
                                 reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
-                                lds + a.enc_bytes + wave * 1024, nullptr, nullptr, a.status, &x, &nd);
+                                lds + a.enc_bytes + wave * c64::kEncWaveLds, nullptr, nullptr, a.status,
+                                &x, &nd);
     c64::place_chunk<R, NL>(chunk, a.n_chunks, x, c64::uni(nd), slot, a.slot_bytes, p, a.status);
 }
 
@@ -35,7 +36,7 @@ hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
-    const uint32_t lds = a.enc_bytes + wpb * 1024;
+    const uint32_t lds = a.enc_bytes + wpb * c64::kEncWaveLds;
     auto kern = k_encode64_place<R, W, NL>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);

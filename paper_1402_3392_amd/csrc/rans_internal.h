@@ -175,6 +175,9 @@ hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hip
 hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
                                  hipStream_t stream);
 uint32_t decode64_lds_per_wave(Layout layout);
+// LDS per wave of the one-wave-per-chunk encoder: 1 KiB symbol block + 1 KiB
+// digit ring.
+constexpr uint32_t kEncWaveLdsBytes = 2048;
 
 // Batched pass (batch.hip).  `decode` selects the direction.
 hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, Layout layout,
