@@ -32,6 +32,36 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    """Hash of every source file the kernels are built from: a traffic figure
+    measured on other sources does not describe these kernels."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1402_3392_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` on this workload, from the committed
+    counter summary (profiles/traffic.txt: FETCH_SIZE and WRITE_SIZE scaled by
+    the copy-kernel calibration), or None when it was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        if line.startswith("#") or "=" not in line:
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split())
+        if kv.get("kernel") == kernel and kv.get("source") == src:
+            return int(kv["traffic_bytes"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +81,7 @@ def parse():
     ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
     ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
+    ap.add_argument("--source-hash", action="store_true", help="print the kernels' source hash")
     return ap.parse_args()
 
 
@@ -417,6 +448,9 @@ def main():
               "chunk and this build runs no multi-GPU path (--gpus 1).", file=sys.stderr)
         sys.exit(2)
 
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.copy_probe:
         copy_probe()
         return
@@ -514,9 +548,10 @@ def main():
     dom = "decode" if kt["decode"][1] >= kt["encode"][1] else "encode"
     dom_gbps = alg_total / (kt[dom][1] / 1e3) / 1e9
     other = "encode" if dom == "decode" else "decode"
-    roofline = {"bound": "hbm", "kernel": f"k_{dom}", "achieved": round(dom_gbps, 1),
+    kname = {"decode": "k_decode64", "encode": "k_encode64_place"}[dom]
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(dom_gbps, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(dom_gbps / HBM_PEAK_GBPS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(kname),
                 "alg_bytes_per_launch": int(sum(alg) / len(alg))}
 
     res = {

@@ -227,7 +227,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->enc = t.enc;
     ea->enc_bytes = static_cast<uint32_t>(t.enc_bytes);
     ea->slot_bytes = sb;
-    ea->slot_stride = sb + 128;
+    ea->slot_stride = sb + 256;
 
     *sa = ScanArgs{};
     sa->n_chunks = nch;
@@ -238,7 +238,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
 
     *ca = CompactArgs{};
     ca->slot_bytes = sb;
-    ca->slot_stride = sb + 128;
+    ca->slot_stride = sb + 256;
     ca->n_chunks = nch;
     ca->N = N;
     ca->digit_bytes = R / 8;

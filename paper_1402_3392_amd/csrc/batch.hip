@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
             break;
         const BatchJob& jb = a.jobs[j];
         if (j != cur) {
-            c64::stage2(lds, jb.enc, jb.enc_bytes, nullptr, 0);
+            c64::stage_enc(lds, jb.enc, jb.enc_bytes, a.l + R - a.k);
             __syncthreads();
             cur = j;
         }

@@ -415,58 +415,87 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         atomicMin(status, RANS_ECORRUPT);
 }
 
-// Per-wave LDS of the encoder: a 1 KiB symbol block, then a 1 KiB digit ring.
+// Per-wave LDS of the encoder: a 1 KiB symbol block, a 4 KiB digit ring,
+// then 128 bytes where lanes with nothing to emit write.
+constexpr uint32_t kEncRing = 4096;
 constexpr uint32_t kEncWaveLds = kEncWaveLdsBytes;
-static_assert(kEncWaveLds == 2048, "encoder LDS layout");
+static_assert(kEncWaveLds == 1024 + kEncRing + 128, "encoder LDS layout");
+// Window stores per flush: a block of symbols (1 KiB) emits at most 2 KiB
+// of digits, i.e. completes at most 8 windows of 256 bytes.
+constexpr uint32_t kFlushStores = 8;
+
+// Stages the encoder entries of a table into LDS for one parameter set,
+// sh = l + r - k.  Table entry {magic, f | cum << 16, sh1 | sh2 << 8, M - f}
+// becomes {magic, x_max - 1, cum | sh2 << 16, (M - f) | bad << 23 | sh1 << 24}
+// with x_max = f * 2^sh the bound of Algorithm 1's renormalisation (no digit
+// is emitted once x < x_max; x_max >= 2^32 is stored as 2^32 - 1, which no
+// state exceeds) and bad = (f == 0), a symbol the table cannot encode.  The
+// kernel then compares against x_max - 1 directly and reads every field
+// with sub-dword operand selects.
+__device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32_t bytes, uint32_t sh)
+{
+    uint4* d = reinterpret_cast<uint4*>(lds);
+    for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) {
+        const uint4 e = src[i];
+        const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16, sh1 = e.z & 0xFFu, sh2 = e.z >> 8;
+        const uint64_t xm = uint64_t(f) << sh;
+        d[i] = make_uint4(e.x, (f == 0 || xm > 0xFFFFFFFFull) ? 0xFFFFFFFFu : static_cast<uint32_t>(xm - 1),
+                          cum | (sh2 << 16), e.w | (f == 0 ? (1u << 23) : 0u) | (sh1 << 24));
+    }
+}
 
 // One encoder step (Algorithm 1's Encode with rANS's C) for every lane:
 // emits the digits the renormalisation drops into the wave's LDS digit ring
 // (at their slot positions modulo the ring; positions from a ballot prefix,
-// the stream growing downwards), then applies C.  fmin tracks the smallest
-// f seen (0: a symbol the table cannot encode).
+// the stream growing downwards), then applies C.  bad collects the entries'
+// bit 23 (a symbol the table cannot encode).  e: the symbol's staged entry
+// (read ahead by the caller).
 template <int R>
-__device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& fmin, uint32_t s, bool act,
-                                         const uint4* l_enc, uint32_t alphabet, uint32_t sh,
-                                         uint8_t* dring)
+__device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& bad, const uint4& e,
+                                         bool act, uint8_t* dring, uint32_t lane)
 {
-    constexpr uint32_t RD = 1024 / (R / 8);  // ring size in digits
-    const uint4 e = l_enc[min(s, alphabet)];
-    const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16;
+    constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
     if (act)
-        fmin = min(fmin, f);
-    const bool e1 = act && (x >> sh) >= f;
+        bad |= e.w;
+    const bool e1 = act && x > e.y;
     if (R == 16) {
         const uint64_t m = ballot(e1);
         wpos -= __popcll(m);
-        if (e1)
-            reinterpret_cast<uint16_t*>(dring)[mbcnt(m, wpos) & (RD - 1)] = static_cast<uint16_t>(x);
+        const uint32_t o = e1 ? 2 * (mbcnt(m, wpos) & (RD - 1)) : kEncRing + 2 * lane;
+        *reinterpret_cast<uint16_t*>(dring + o) = static_cast<uint16_t>(x);
         x = e1 ? x >> 16 : x;
     } else {
-        const bool e2 = act && (x >> (sh + 8)) >= f;
+        const bool e2 = act && (x >> 8) > e.y;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
         wpos -= __popcll(m1) + __popcll(m2);
         const uint32_t idx = mbcnt(m2, mbcnt(m1, wpos));
-        if (e1)
-            dring[idx & (RD - 1)] = static_cast<uint8_t>(e2 ? x >> 8 : x);
-        if (e2)
-            dring[(idx + 1) & (RD - 1)] = static_cast<uint8_t>(x);
+        const uint32_t o1 = e1 ? idx & (RD - 1) : kEncRing + lane;
+        const uint32_t o2 = e2 ? (idx + 1) & (RD - 1) : kEncRing + 64 + lane;
+        dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
+        dring[o2] = static_cast<uint8_t>(x);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     if (act) {
+        // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
+        // Granlund-Montgomery multiply-high division
         const uint32_t th = __umulhi(e.x, x);
-        const uint32_t q = (th + ((x - th) >> (e.z & 0xFFu))) >> (e.z >> 8);
-        x = x + __umul24(q, e.w) + cum;
+        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> (e.z >> 16);
+        x = __umul24(q, e.w) + x + (e.z & 0xFFFFu);
     }
 }
 
 // Encodes chunk `chunk` of syms_base (n symbols, C per chunk, NL = 32 or 64
 // interleaved coders) into the digit slot `slot` (digits end at slot +
-// slot_bytes, a multiple of 256; 128 more bytes follow), writes the NL final
+// slot_bytes, a multiple of 256; 256 more bytes follow), writes the NL final
 // states to states_out and the digit count to *ndig_out (or to the
-// caller's x_out / nd_out).  l_enc: LDS encoder entries (alphabet + 1);
+// caller's x_out / nd_out).  l_enc: LDS encoder entries staged by stage_enc
+// (alphabet + 1);
 // wave_lds: this wave's kEncWaveLds bytes.  Digits reach the slot from the
-// LDS ring a 256-byte window at a time, one 4-byte store per lane, as soon
-// as the stream has grown past the window.
+// LDS ring a 256-byte window at a time, one 4-byte store per lane: after
+// every block of symbols, the windows the stream has grown past, padded to
+// kFlushStores stores with stores to the 256 bytes after the slot.  A fixed
+// number of memory operations per block lets the compiler's wait for the
+// symbols of the next block leave the recent stores in flight.
 template <int R, int W, int NL>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
@@ -485,27 +514,30 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     const uint64_t first = chunk * C;
     const uint32_t nsym = uni(static_cast<uint32_t>(n - first < C ? n - first : C));
     const InT* in = static_cast<const InT*>(syms_base) + first;
-    const uint32_t sh = l + R - k;
     const uint32_t steps = (nsym + NL - 1) / NL;
     const uint32_t nblk = nsym / (NL * SPB);  // whole blocks
     const uint32_t top = uni(static_cast<uint32_t>(slot_bytes / DB));
     uint32_t x = 1u << l;
-    uint32_t wpos = top;       // lowest digit written so far
-    uint32_t wlo = top - WD;   // first digit of the window being filled
-    uint32_t fmin = 0xFFFFu;
+    uint32_t wpos = top;  // lowest digit written so far
+    uint32_t wtop = top;  // digits from wtop up are in the slot
+    uint32_t bad = 0;
 
-    auto store_window = [&](uint32_t lo) {  // ring window holding digits [lo, lo + WD)
-        lane_fence();
-        const uint32_t v = reinterpret_cast<const uint32_t*>(dring + ((lo * DB) & 1023u))[lane];
-        lane_fence();
-        reinterpret_cast<uint32_t*>(slot + uint64_t(lo) * DB)[lane] = v;
+    auto ring_word = [&](uint32_t lo) {  // this lane's word of the ring window of digits [lo, lo + WD)
+        return reinterpret_cast<const uint32_t*>(dring + ((lo * DB) & (kEncRing - 1)))[lane];
     };
-    // a step emits at most 64 * 2 bytes < 256, so it completes one window at most
-    auto after_step = [&]() {
-        if (wpos < wlo) {
-            store_window(wlo);
-            wlo -= WD;
+    auto flush = [&]() {
+        const uint32_t wc = (wpos + WD - 1) / WD * WD;  // lowest window boundary at or above wpos
+        const uint32_t cnt = (wtop - wc) / WD;          // complete windows not yet stored (<= 8)
+        lane_fence();
+#pragma unroll
+        for (uint32_t j = 0; j < kFlushStores; ++j) {
+            const uint32_t lo = wtop - (j + 1) * WD;
+            uint8_t* dst = j < cnt ? slot + uint64_t(lo) * DB : slot + slot_bytes;
+            const uint32_t v = ring_word(lo);
+            reinterpret_cast<uint32_t*>(dst)[lane] = v;
         }
+        lane_fence();
+        wtop = wc;
     };
 
     // steps above the whole blocks (the partial tail), one at a time
@@ -513,24 +545,39 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         const uint64_t i = uint64_t(t) * NL + lane;
         const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
-        enc_step<R>(x, wpos, fmin, s, act, l_enc, alphabet, sh, dring);
-        after_step();
+        enc_step<R>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
     }
+    flush();  // the tail is shorter than a block: at most 8 windows
 
     if (nblk > 0) {
         // block b = symbols [b*NL*SPB, (b+1)*NL*SPB); lane loads 16 bytes
         const uint4* blk = reinterpret_cast<const uint4*>(in) + lane;
         auto load_blk = [&](int64_t b) { return blk[(b < 0 ? 0 : b) * 64]; };
+        // The block's symbols are read from LDS up front and each step's
+        // entry PF steps ahead, in program order before the steps' digit
+        // writes: the reads stay off the state's dependency chain.
+        constexpr int PF = 3;
         auto run_blk = [&](uint4 v) {
             lane_fence();
             *reinterpret_cast<uint4*>(sbuf + 16 * lane) = v;
             lane_fence();
             const InT* sb = reinterpret_cast<const InT*>(sbuf) + lane;
+            uint32_t sy[SPB];
+#pragma unroll
+            for (int q = 0; q < int(SPB); ++q)
+                sy[q] = min(static_cast<uint32_t>(sb[q * NL]), alphabet);
+            lane_fence();  // the symbols are in registers before the ring writes
+            uint4 ent[SPB];
+#pragma unroll
+            for (int q = SPB - 1; q >= int(SPB) - PF && q >= 0; --q)
+                ent[q] = l_enc[sy[q]];
 #pragma unroll
             for (int q = SPB - 1; q >= 0; --q) {
-                enc_step<R>(x, wpos, fmin, sb[q * NL], live, l_enc, alphabet, sh, dring);
-                after_step();
+                if (q - PF >= 0)
+                    ent[q - PF] = l_enc[sy[q - PF]];
+                enc_step<R>(x, wpos, bad, ent[q], live, dring, lane);
             }
+            flush();
         };
         int64_t b = int64_t(nblk) - 1;
         uint4 A = load_blk(b);
@@ -548,8 +595,11 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             --b;
         }
     }
-    if (wpos < wlo + WD)  // the window holding the stream's first digits
-        store_window(wlo);
+    if (wpos < wtop) {  // the window holding the stream's first digits
+        lane_fence();
+        const uint32_t v = ring_word(wtop - WD);
+        reinterpret_cast<uint32_t*>(slot + uint64_t(wtop - WD) * DB)[lane] = v;
+    }
     if (states_out && live)
         states_out[lane] = x;
     if (ndig_out && lane == 0)
@@ -558,7 +608,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         *x_out = x;
     if (nd_out)
         *nd_out = top - wpos;
-    if (ballot(fmin == 0) && lane == 0)
+    if (ballot((bad >> 23) & 1) && lane == 0)
         atomicMin(status, RANS_ENOSYM);
 }
 

@@ -13,7 +13,7 @@ template <int R, int W, int NL>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    c64::stage2(lds, a.enc, a.enc_bytes, nullptr, 0);
+    c64::stage_enc(lds, a.enc, a.enc_bytes, a.l + R - a.k);
     __syncthreads();
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
     uint32_t t = 0;

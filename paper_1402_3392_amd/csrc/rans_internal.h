@@ -76,7 +76,7 @@ struct EncodeArgs {
     uint8_t* slots;       // n_chunks slots, slot_stride apart
     uint64_t slot_bytes;  // digit capacity of a slot in bytes (multiple of 16);
                           // digits end at slot + slot_bytes
-    uint64_t slot_stride; // slot_bytes + 128-byte junk area for idle lanes
+    uint64_t slot_stride; // slot_bytes + a 256-byte junk area
     uint32_t* states;     // n_chunks * N final states
     uint32_t* ndig;       // n_chunks digit counts
     int32_t* status;
@@ -175,9 +175,9 @@ hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hip
 hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
                                  hipStream_t stream);
 uint32_t decode64_lds_per_wave(Layout layout);
-// LDS per wave of the one-wave-per-chunk encoder: 1 KiB symbol block + 1 KiB
-// digit ring.
-constexpr uint32_t kEncWaveLdsBytes = 2048;
+// LDS per wave of the one-wave-per-chunk encoder: 1 KiB symbol block, 4 KiB
+// digit ring, 128 bytes for the writes of lanes with nothing to emit.
+constexpr uint32_t kEncWaveLdsBytes = 5248;
 
 // Batched pass (batch.hip).  `decode` selects the direction.
 hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, Layout layout,
