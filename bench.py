@@ -298,7 +298,7 @@ def run_sweep(args):
         key = (p["alphabet"], p["dist"])
         if key not in cache:
             cache.clear()
-            cache[key] = datagen.config3_data(p["alphabet"], p["dist"])
+            cache[key] = datagen.config3_data(p["alphabet"], p["dist"])[0]
         syms = cache[key]
         w = 1 if p["alphabet"] <= 256 else 2
         row = {"idx": idx, "alphabet": p["alphabet"], "dist": p["dist"], "k": p["k"], "r": p["r"],
@@ -311,10 +311,15 @@ def run_sweep(args):
         counts = datagen.counts(syms, p["alphabet"])
         f = oracle.quantize(counts, p["k"])
         table = lr.rans_tables_build(counts, p["k"])
-        params = lr.rans_params.make(p["k"], p["r"], p["l"], w, p["N"], 65536 // w)
-        C = 65536 // w
-        cont = oracle.encode(f, syms, p["k"], p["r"], p["l"], p["N"], C, threads=threads)
         d_syms = torch.from_numpy(syms.view(np.uint8)).cuda()
+        # chunk size and batched launch shape from the autotuner, on this buffer
+        tune = lr.rans_autotune(table, d_syms, syms.size,
+                                lr.rans_params.make(p["k"], p["r"], p["l"], w, 64, 65536 // w))
+        C = int(tune["chunk_syms"])
+        row.update(C=C, G=int(tune["waves_per_group"]), gpc=int(tune["groups_per_cu"]),
+                   layout=int(tune["table_layout"]))
+        params = lr.rans_params.make(p["k"], p["r"], p["l"], w, p["N"], C)
+        cont = oracle.encode(f, syms, p["k"], p["r"], p["l"], p["N"], C, threads=threads)
         cap = lr.rans_encode_bound(syms.size, params)
         d_enc = torch.empty(cap, dtype=torch.uint8, device="cuda")
         nb = lr.rans_encode(table, params, d_syms, syms.size, d_enc, cap)
@@ -363,7 +368,7 @@ def run_sweep(args):
                       best, "GB/s", args,
                       {"workload": "64 MiB symbol bytes per point; alphabets 2/16/256/4096, "
                                    "M=2^11/2^15, p0=0.995 / Zipf(1.1) / near-uniform, "
-                                   "(b,L)=(2^8,2^23)/(2^16,2^16), N=32/64, 64 KiB chunks"})
+                                   "(b,L)=(2^8,2^23)/(2^16,2^16), N=32/64, autotuned chunk size"})
     out["points"] = rows
     print(json.dumps(out), flush=True)
 

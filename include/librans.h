@@ -223,10 +223,11 @@ int rans_batch_get_config(rans_batch_config *cfg);
  * device, 16-byte aligned, coded with `table` and base's k, r, l, w) over
  * chunk sizes C in {4096 .. 65536} (chosen at encode time, written into
  * the container) and decode launch shapes (waves per work item, blocks per
- * CU, table layout), with 64 coders per chunk.  A candidate's score is its
- * encode + decode time, penalised when its container exceeds the 64 KiB-
- * chunk container by more than 1%.  The best shape becomes the process-wide
- * rans_batch_config; *out reports it with the measured rates.  Results are
+ * CU, table layout), with 64 coders per chunk, then whether the best shape
+ * runs faster replayed as a HIP graph or launched directly.  A candidate's
+ * score is its encode + decode time, penalised when its container exceeds
+ * the 64 KiB-chunk container by more than 1%.  The best shape becomes the
+ * process-wide rans_batch_config; *out reports it with the measured rates.  Results are
  * appended to cache_path (text, one line per device / parameter / alphabet
  * class / size class; NULL disables the cache) and reused on a hit. */
 typedef struct rans_tune_result {
@@ -236,6 +237,8 @@ typedef struct rans_tune_result {
     uint32_t table_layout;
     double encode_gbps;
     double decode_gbps;
+    uint32_t use_graph;
+    uint32_t reserved;
 } rans_tune_result;
 int rans_autotune(const rans_table *table, const void *d_syms, uint64_t n_syms,
                   const rans_params *base, const char *cache_path, rans_tune_result *out);

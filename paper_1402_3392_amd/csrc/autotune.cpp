@@ -64,7 +64,7 @@ bool cache_lookup(const char* path, const std::string& key, rans_tune_result* r)
         std::string k;
         rans_tune_result t{};
         if (is >> k >> t.chunk_syms >> t.waves_per_group >> t.groups_per_cu >> t.table_layout >>
-                t.encode_gbps >> t.decode_gbps &&
+                t.encode_gbps >> t.decode_gbps >> t.use_graph &&
             k == key) {
             *r = t;
             return true;
@@ -79,7 +79,7 @@ void cache_store(const char* path, const std::string& key, const rans_tune_resul
         return;
     std::ofstream out(path, std::ios::app);
     out << key << ' ' << r.chunk_syms << ' ' << r.waves_per_group << ' ' << r.groups_per_cu << ' '
-        << r.table_layout << ' ' << r.encode_gbps << ' ' << r.decode_gbps << '\n';
+        << r.table_layout << ' ' << r.encode_gbps << ' ' << r.decode_gbps << ' ' << r.use_graph << '\n';
 }
 
 // Median time (ms) of `reps` runs of fn() on stream st.
@@ -130,7 +130,7 @@ extern "C" int rans_autotune(const rans_table* table, const void* d_syms, uint64
     const uint32_t w = p.sym_bytes;
     const std::string key = cache_key(p, t->alphabet, n_syms * w);
     if (cache_lookup(cache_path, key, out)) {
-        rans_batch_config cfg{out->waves_per_group, out->groups_per_cu, out->table_layout, 1};
+        rans_batch_config cfg{out->waves_per_group, out->groups_per_cu, out->table_layout, out->use_graph};
         return rans_batch_set_config(&cfg);
     }
     if (n_syms == 0)
@@ -202,11 +202,30 @@ extern "C" int rans_autotune(const rans_table* table, const void* d_syms, uint64
             }
         }
     }
-    (void)hipStreamSynchronize(st);
     if (best.chunk_syms == 0)
         return RANS_EDEVICE;
+    // graph replay against direct launches, for the best shape
+    {
+        rans_params pc = p;
+        pc.chunk_syms = best.chunk_syms;
+        double t[2] = {0, 0};
+        for (uint32_t g = 0; g < 2; ++g) {
+            rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, g};
+            rans_job ej{table, d_syms, n_syms * w, cont.p, cap, d_len, d_status};
+            int e = RANS_OK;
+            t[g] = time_ms(st, 5, [&] { return run_batch(&ej, 1, &pc, st, false, &cfg); }, &e);
+            uint64_t clen = 0;
+            (void)hipMemcpy(&clen, d_len, 8, hipMemcpyDeviceToHost);
+            rans_job dj{table, cont.p, clen, dec.p, n_syms * w, d_len, d_status};
+            t[g] += time_ms(st, 5, [&] { return run_batch(&dj, 1, &pc, st, true, &cfg); }, &e);
+            if (e != RANS_OK)
+                t[g] = 1e30;
+        }
+        best.use_graph = t[1] <= t[0] ? 1u : 0u;
+    }
+    (void)hipStreamSynchronize(st);
     *out = best;
     cache_store(cache_path, key, best);
-    rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, 1};
+    rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, best.use_graph};
     return rans_batch_set_config(&cfg);
 }

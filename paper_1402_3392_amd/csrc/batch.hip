@@ -1,8 +1,9 @@
 // Batched encode/decode of many independent streams (each with its own
-// table) in one pass: a planning kernel completes each job's description on
-// the device (a decode job's chunk count lives in its container header), a
-// scan turns chunk counts into work items of G chunks, and a persistent grid
-// pulls work items from an atomic counter.  A block restages its LDS table
+// table) in one pass: a single-block preparation kernel completes each job's
+// description on the device (a decode job's chunk count lives in its
+// container header), turns chunk counts into work items of G chunks and maps
+// items to jobs; a persistent grid then pulls work items from an atomic
+// counter.  A block restages its LDS table
 // whenever the next work item belongs to another job; each of its G waves
 // codes one chunk with the same N = 32 or 64 chunk coder as the single-buffer
 // kernels.  Encode jobs then get their container laid out per job (scan of
@@ -15,12 +16,10 @@ namespace {
 
 __device__ __forceinline__ uint64_t align16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
 
-// One thread per job.
-__global__ void k_batch_plan(BatchArgs a, bool decode)
+// Completes job j's description: chunk size, symbol count and chunk count
+// (a decode job's come from its container header, which is checked).
+__device__ void plan_job(const BatchArgs& a, uint32_t j, bool decode)
 {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.njobs)
-        return;
     BatchJob& jb = a.jobs[j];
     int32_t st = RANS_OK;
     uint64_t n = 0;
@@ -69,15 +68,31 @@ __global__ void k_batch_plan(BatchArgs a, bool decode)
     jb.nch = nch;
 }
 
-// Single block: exclusive scans of work items and chunks over the jobs.
-__global__ void __launch_bounds__(1024) k_batch_scan(BatchArgs a)
+// Single block, one launch before the persistent kernel: plans every job,
+// scans work items and chunks over the jobs, fills the item -> job (and, to
+// encode, chunk -> job) maps and zeroes the work-queue counter.  A job's map
+// entries are written by the thread that planned it, or by the whole block
+// when the job has many of them.
+constexpr uint32_t kPrepThreads = 1024;
+constexpr uint32_t kBigJobs = 256;
+constexpr uint32_t kSmallEntries = 32;
+
+__global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, bool decode)
 {
-    __shared__ uint32_t part_i[1024], part_c[1024];
+    __shared__ uint32_t part_i[kPrepThreads], part_c[kPrepThreads];
+    __shared__ uint32_t big[kBigJobs];
+    __shared__ uint32_t nbig;
     const uint32_t T = blockDim.x, tid = threadIdx.x;
+    if (tid == 0) {
+        a.counter[0] = a.grid;  // items below grid are taken by block index
+        nbig = 0;
+    }
+    // contiguous job ranges per thread, so the scan below is ordered
     const uint32_t per = (a.njobs + T - 1) / T;
     const uint32_t lo = min(a.njobs, tid * per), hi = min(a.njobs, lo + per);
     uint32_t si = 0, sc = 0;
     for (uint32_t j = lo; j < hi; ++j) {
+        plan_job(a, j, decode);
         si += (a.jobs[j].nch + a.G - 1) / a.G;
         sc += a.jobs[j].nch;
     }
@@ -93,42 +108,65 @@ __global__ void __launch_bounds__(1024) k_batch_scan(BatchArgs a)
     }
     uint32_t bi = tid ? part_i[tid - 1] : 0, bc = tid ? part_c[tid - 1] : 0;
     for (uint32_t j = lo; j < hi; ++j) {
-        a.jobs[j].item_base = bi;
-        a.jobs[j].chunk_base = bc;
-        bi += (a.jobs[j].nch + a.G - 1) / a.G;
-        bc += a.jobs[j].nch;
+        BatchJob& jb = a.jobs[j];
+        jb.item_base = bi;
+        jb.chunk_base = bc;
+        const uint32_t items = (jb.nch + a.G - 1) / a.G;
+        if (items <= kSmallEntries && (decode || jb.nch <= kSmallEntries)) {
+            // the host sized the maps from the jobs' lengths; never exceed them
+            for (uint32_t i = 0; i < items; ++i)
+                if (bi + i < a.max_items)
+                    a.item_job[bi + i] = j;
+            if (!decode)
+                for (uint32_t c = 0; c < jb.nch; ++c)
+                    if (bc + c < a.max_chunks)
+                        a.chunk_job[bc + c] = j;
+        } else {
+            const uint32_t slot = atomicAdd(&nbig, 1u);
+            if (slot < kBigJobs) {
+                big[slot] = j;
+            } else {
+                for (uint32_t i = 0; i < items; ++i)
+                    if (bi + i < a.max_items)
+                        a.item_job[bi + i] = j;
+                if (!decode)
+                    for (uint32_t c = 0; c < jb.nch; ++c)
+                        if (bc + c < a.max_chunks)
+                            a.chunk_job[bc + c] = j;
+            }
+        }
+        bi += items;
+        bc += jb.nch;
     }
     if (tid == T - 1) {
-        // the host sized the maps from the jobs' lengths; never exceed them
         a.totals[0] = min(part_i[T - 1], a.max_items);
         a.totals[1] = min(part_c[T - 1], a.max_chunks);
     }
-}
-
-// Block per job: fills the item -> job (and chunk -> job) maps.
-__global__ void k_batch_maps(BatchArgs a, bool decode)
-{
-    const uint32_t j = blockIdx.x;
-    if (j >= a.njobs)
-        return;
-    const BatchJob& jb = a.jobs[j];
-    const uint32_t items = (jb.nch + a.G - 1) / a.G;
-    for (uint32_t i = threadIdx.x; i < items; i += blockDim.x)
-        if (jb.item_base + i < a.max_items)
-            a.item_job[jb.item_base + i] = j;
-    if (!decode)
-        for (uint32_t c = threadIdx.x; c < jb.nch; c += blockDim.x)
-            if (jb.chunk_base + c < a.max_chunks)
-                a.chunk_job[jb.chunk_base + c] = j;
+    __syncthreads();
+    const uint32_t nb = min(nbig, kBigJobs);
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint32_t j = big[b];
+        const BatchJob& jb = a.jobs[j];
+        const uint32_t items = (jb.nch + a.G - 1) / a.G;
+        for (uint32_t i = tid; i < items; i += T)
+            if (jb.item_base + i < a.max_items)
+                a.item_job[jb.item_base + i] = j;
+        if (!decode)
+            for (uint32_t c = tid; c < jb.nch; c += T)
+                if (jb.chunk_base + c < a.max_chunks)
+                    a.chunk_job[jb.chunk_base + c] = j;
+    }
 }
 
 // Fetches the block's next work item; returns its job or -1 when the queue
-// is exhausted (the same value for every thread of the block).
-__device__ __forceinline__ int next_item(const BatchArgs& a, uint32_t* s_slot, uint32_t* item)
+// is exhausted (the same value for every thread of the block).  A block's
+// first item is its own index; later ones come from the atomic counter,
+// which starts at the grid size.
+__device__ __forceinline__ int next_item(const BatchArgs& a, uint32_t* s_slot, uint32_t* item, bool first)
 {
     __syncthreads();  // everyone is done with the previous item
     if (threadIdx.x == 0) {
-        const uint32_t it = atomicAdd(a.counter, 1u);
+        const uint32_t it = first ? blockIdx.x : atomicAdd(a.counter, 1u);
         s_slot[0] = it;
         const uint32_t j = it < a.totals[0] ? a.item_job[it] : 0xFFFFFFFFu;
         s_slot[1] = j < a.njobs ? j : 0xFFFFFFFFu;
@@ -150,8 +188,8 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
     uint8_t* tab = lds + a.G * c64::wave_lds_bytes(LAYOUT);
     int cur = -1;
     uint32_t item;
-    for (;;) {
-        const int j = next_item(a, s_slot, &item);
+    for (bool first = true;; first = false) {
+        const int j = next_item(a, s_slot, &item, first);
         if (j < 0)
             break;
         const BatchJob& jb = a.jobs[j];
@@ -181,8 +219,8 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
     uint8_t* sbuf = lds + a.tab_lds + wave * c64::kEncWaveLds;
     int cur = -1;
     uint32_t item;
-    for (;;) {
-        const int j = next_item(a, s_slot, &item);
+    for (bool first = true;; first = false) {
+        const int j = next_item(a, s_slot, &item, first);
         if (j < 0)
             break;
         const BatchJob& jb = a.jobs[j];
@@ -298,12 +336,6 @@ __global__ void __launch_bounds__(256) k_batch_compact(BatchArgs a)
     }
 }
 
-__global__ void k_zero_words(uint32_t* p, uint32_t count)
-{
-    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x)
-        p[i] = 0;
-}
-
 template <typename K>
 hipError_t set_lds(K kernel, uint32_t bytes)
 {
@@ -369,14 +401,9 @@ hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, L
 {
     if (a.njobs == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, a.counter, 1u);
+    hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(kPrepThreads), 0, st, a, decode);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_batch_plan, dim3((a.njobs + 255) / 256), dim3(256), 0, st, a, decode);
-    hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(1024), 0, st, a);
-    hipLaunchKernelGGL(k_batch_maps, dim3(a.njobs), dim3(256), 0, st, a, decode);
-    if ((e = hipGetLastError()) != hipSuccess)
         return e;
     if (decode) {
         e = R == 16 ? persistent_decode_w<16>(a, W, SW, layout, grid, st)

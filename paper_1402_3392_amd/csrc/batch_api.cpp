@@ -218,6 +218,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     a.chunk_off = reinterpret_cast<uint64_t*>(base + rg.chunk_off);
     a.tab_lds = (tab_lds + 15) & ~15u;
     const uint32_t grid = static_cast<uint32_t>(num_cus()) * cfg.groups_per_cu;
+    a.grid = grid;
 
     // job descriptors -> pinned staging -> workspace, ordered on `st`
     std::memcpy(ws->pinned, hj.data(), jb_bytes);

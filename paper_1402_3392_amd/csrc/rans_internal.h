@@ -162,6 +162,7 @@ struct BatchArgs {
     uint32_t* ndig;
     uint64_t* chunk_off;
     uint32_t tab_lds;           // LDS bytes reserved for the largest table
+    uint32_t grid;              // persistent blocks; block b starts with work item b
 };
 
 // Launchers (kernels.hip).  All asynchronous on `stream`.

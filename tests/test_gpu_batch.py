@@ -196,3 +196,35 @@ def test_batch_launch_shapes(lr, G, gpc, layout):
             assert (outs[i] == ref).all() and (dec[i] == s).all(), i
     finally:
         lr.rans_batch_set_config(16, 1, 0, 1)
+
+
+def test_autotune_result_is_valid_applied_and_cached(lr, tmp_path):
+    import torch
+    k, r, l = 14, 16, 16
+    s, _ = streams(1, seed=4500, lo=20, hi=20.5)[0]
+    table = lr.rans_tables_build(datagen.counts(s, 256), k)
+    d = torch.from_numpy(s).cuda()
+    cache = str(tmp_path / "tune.txt")
+    base = lr.rans_params.make(k, r, l, 1, 64, 65536)
+    res = lr.rans_autotune(table, d, s.size, base, cache)
+    assert res["chunk_syms"] in (65536, 32768, 16384, 8192, 4096)
+    assert res["waves_per_group"] in (16, 8, 4) and res["groups_per_cu"] in (1, 2)
+    assert res["table_layout"] in (1, 2, 3) and res["use_graph"] in (0, 1)
+    assert res["encode_gbps"] > 0 and res["decode_gbps"] > 0
+    cfg = lr.rans_batch_get_config()
+    assert (cfg["waves_per_group"], cfg["groups_per_cu"], cfg["table_layout"], cfg["use_graph"]) == \
+        (res["waves_per_group"], res["groups_per_cu"], res["table_layout"], res["use_graph"])
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1
+    lr.rans_batch_set_config(16, 1, 0, 1)
+    again = lr.rans_autotune(table, d, s.size, base, cache)  # a cache hit: same answer, no new line
+    assert again["chunk_syms"] == res["chunk_syms"] and len(open(cache).read().splitlines()) == 1
+    # the tuned shape codes bit-exactly
+    C = res["chunk_syms"]
+    tables, outs, st, _ = run_encode_batch(lr, [(s, None)], k, r, l, C)
+    assert (st == 0).all()
+    ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+    assert outs[0].size == ref.size and (outs[0] == ref).all()
+    dec, st2, _ = run_decode_batch(lr, tables, outs, [s.size], k, r, l)
+    assert (st2 == 0).all() and (dec[0] == s).all()
+    lr.rans_batch_set_config(16, 1, 0, 1)
