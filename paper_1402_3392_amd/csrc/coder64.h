@@ -458,19 +458,22 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
     if (act)
         bad |= e.w;
     const bool e1 = act && x > e.y;
+    // every lane writes (lanes with nothing to emit into the area after the
+    // ring), the address picked by a select on the ballot mask: no exec-mask
+    // changes on the step
     if (R == 16) {
         const uint64_t m = ballot(e1);
         wpos -= __popcll(m);
-        const uint32_t o = e1 ? 2 * (mbcnt(m, wpos) & (RD - 1)) : kEncRing + 2 * lane;
+        const uint32_t o = select_mask(m, kEncRing + 2 * lane, ((wpos + mbcnt(m, 0)) << 1) & (2 * RD - 1));
         *reinterpret_cast<uint16_t*>(dring + o) = static_cast<uint16_t>(x);
         x = e1 ? x >> 16 : x;
     } else {
         const bool e2 = act && (x >> 8) > e.y;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
         wpos -= __popcll(m1) + __popcll(m2);
-        const uint32_t idx = mbcnt(m2, mbcnt(m1, wpos));
-        const uint32_t o1 = e1 ? idx & (RD - 1) : kEncRing + lane;
-        const uint32_t o2 = e2 ? (idx + 1) & (RD - 1) : kEncRing + 64 + lane;
+        const uint32_t idx = wpos + mbcnt(m2, mbcnt(m1, 0));
+        const uint32_t o1 = select_mask(m1, kEncRing + lane, idx & (RD - 1));
+        const uint32_t o2 = select_mask(m2, kEncRing + 64 + lane, (idx + 1) & (RD - 1));
         dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
         dring[o2] = static_cast<uint8_t>(x);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
