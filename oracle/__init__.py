@@ -80,6 +80,8 @@ def _bind(lib):
     lib.orc_encode_bound.restype = u64
     lib.orc_encode.argtypes = [u32p, u32, u32, u32, u32, u32, u32, u32, u8p, u64, u8p, u64,
                                u64p, i32]
+    lib.orc_encode_order.argtypes = [u32p, u32, u32, u32, u32, u32, u32, u32, i32, u8p, u64, u8p,
+                                     u64, u64p, i32]
     lib.orc_decode.argtypes = [u32p, u32, u8p, u64, u8p, u64, u64p, i32]
     lib.orc_header.argtypes = [u8p, u64, u64p]
     return lib
@@ -176,8 +178,10 @@ def encode_bound(n: int, k: int, r: int, N: int, C: int) -> int:
 
 
 def encode(f, syms: np.ndarray, k: int, r: int, l: int, N: int, C: int,
-           threads: int = 1) -> np.ndarray:
-    """Encodes a symbol array (uint8 or uint16) into a container (uint8 array)."""
+           threads: int = 1, order: str = "df") -> np.ndarray:
+    """Encodes a symbol array (uint8 or uint16) into a container (uint8 array).
+    order: digit order of the chunk streams, 'df' depth-first or 'bf'
+    breadth-first (Section 5), recorded in header byte 9."""
     f = _u32(f)
     syms = np.ascontiguousarray(syms)
     w = syms.dtype.itemsize
@@ -188,19 +192,23 @@ def encode(f, syms: np.ndarray, k: int, r: int, l: int, N: int, C: int,
     out = np.zeros(cap, dtype=np.uint8)
     olen = ct.c_uint64()
     raw = syms.view(np.uint8).reshape(-1) if n else np.zeros(1, dtype=np.uint8)
-    rc = _load().orc_encode(_p(f, ct.c_uint32), len(f), k, r, l, w, N, C,
-                            _p(raw, ct.c_uint8), n, _p(out, ct.c_uint8), cap, ct.byref(olen),
-                            threads)
+    if order not in ("df", "bf"):
+        raise ValueError("order must be 'df' or 'bf'")
+    rc = _load().orc_encode_order(_p(f, ct.c_uint32), len(f), k, r, l, w, N, C,
+                                  1 if order == "bf" else 0, _p(raw, ct.c_uint8), n,
+                                  _p(out, ct.c_uint8), cap, ct.byref(olen), threads)
     _check(rc, "encode")
     return out[:olen.value]
 
 
 def header(container: np.ndarray) -> dict:
     buf = np.ascontiguousarray(container, dtype=np.uint8)
-    h = np.zeros(8, dtype=np.uint64)
+    h = np.zeros(9, dtype=np.uint64)
     _check(_load().orc_header(_p(buf, ct.c_uint8), buf.size, _p(h, ct.c_uint64)), "header")
-    keys = ("k", "r", "l", "w", "N", "C", "n", "n_chunks")
-    return {kk: int(v) for kk, v in zip(keys, h)}
+    keys = ("k", "r", "l", "w", "N", "C", "n", "n_chunks", "order")
+    d = {kk: int(v) for kk, v in zip(keys, h)}
+    d["order"] = "bf" if d["order"] else "df"
+    return d
 
 
 def decode(f, container: np.ndarray, threads: int = 1) -> np.ndarray:

@@ -40,7 +40,9 @@
  *   Q7  when the chunk length is not a multiple of N, the last round only
  *       involves coders 0 .. (len mod N)-1; idle coders keep state L.
  *   Q8  container: 32-byte header, chunk directory, chunk streams at 16-byte
- *       aligned offsets with zero padding (layout in orc_encode).
+ *       aligned offsets with zero padding (layout in orc_encode).  Header
+ *       byte 9 names the digit order of the chunk streams: 0 depth-first,
+ *       1 breadth-first (Section 5); the two coincide when b >= M.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -587,6 +589,7 @@ typedef struct {
     const model_t *m;
     geom_t g;
     uint32_t r, w, C;
+    int order; /* 0 depth-first, 1 breadth-first */
     const uint8_t *syms;
     uint64_t nsyms, nch;
     uint8_t **chunk_bytes;
@@ -620,7 +623,8 @@ static void *encode_worker(void *arg)
         int rc;
         for (i = 0; i < len; i++)
             syms[i] = get_sym(jb->syms, jb->w, base + i);
-        rc = encode_df(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL);
+        rc = jb->order ? encode_bf(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL)
+                       : encode_df(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL);
         if (rc != ORC_OK) {
             jb->rc = rc;
             goto out;
@@ -685,10 +689,11 @@ static int run_workers(job_t *proto, int nthreads, void *(*fn)(void *))
     return rc;
 }
 
-/* Encodes nsyms symbols (w bytes each, little-endian) into a container. */
-int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
-               uint32_t w, uint32_t N, uint32_t C, const uint8_t *syms, uint64_t nsyms,
-               uint8_t *out, uint64_t cap, uint64_t *out_len, int nthreads)
+/* Encodes nsyms symbols (w bytes each, little-endian) into a container whose
+ * chunk streams use digit order `order` (0 depth-first, 1 breadth-first). */
+int orc_encode_order(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
+                     uint32_t w, uint32_t N, uint32_t C, int order, const uint8_t *syms,
+                     uint64_t nsyms, uint8_t *out, uint64_t cap, uint64_t *out_len, int nthreads)
 {
     model_t m;
     job_t jb;
@@ -696,6 +701,8 @@ int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint
     int rc = check_container_params(k, r, l, w, N);
     if (rc != ORC_OK)
         return rc;
+    if (order != 0 && order != 1)
+        return ORC_EINVAL;
     if (C == 0) {
         if (nsyms > 0xFFFFFFFFull)
             return ORC_EINVAL;
@@ -715,6 +722,7 @@ int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint
     jb.r = r;
     jb.w = w;
     jb.C = C;
+    jb.order = order;
     jb.syms = syms;
     jb.nsyms = nsyms;
     jb.nch = nch;
@@ -746,7 +754,7 @@ int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint
     out[6] = (uint8_t)r;
     out[7] = (uint8_t)l;
     out[8] = (uint8_t)w;
-    out[9] = 0;
+    out[9] = (uint8_t)order;
     put_u16(out + 10, N);
     put_u32(out + 12, C);
     put_u64(out + 16, nsyms);
@@ -770,15 +778,26 @@ out:
     return rc;
 }
 
+/* Depth-first container (the digit order every caller used before the order
+ * byte existed). */
+int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
+               uint32_t w, uint32_t N, uint32_t C, const uint8_t *syms, uint64_t nsyms,
+               uint8_t *out, uint64_t cap, uint64_t *out_len, int nthreads)
+{
+    return orc_encode_order(f, n_alpha, k, r, l, w, N, C, 0, syms, nsyms, out, cap, out_len,
+                            nthreads);
+}
+
 typedef struct {
-    uint32_t k, r, l, w, N, C;
+    uint32_t k, r, l, w, N, C, order;
     uint64_t n, nch;
 } hdr_t;
 
 static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
 {
-    if (in_len < 32 || get_u32(in) != ORC_MAGIC || in[4] != 1 || in[9] != 0)
+    if (in_len < 32 || get_u32(in) != ORC_MAGIC || in[4] != 1 || in[9] > 1)
         return ORC_ECORRUPT;
+    h->order = in[9];
     h->k = in[5];
     h->r = in[6];
     h->l = in[7];
@@ -796,7 +815,8 @@ static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
     return ORC_OK;
 }
 
-/* Reads the header fields: out[0..7] = k, r, l, w, N, C, n, n_chunks. */
+/* Reads the header fields: out[0..8] = k, r, l, w, N, C, n, n_chunks, digit
+ * order. */
 int orc_header(const uint8_t *in, uint64_t in_len, uint64_t *out)
 {
     hdr_t h;
@@ -811,6 +831,7 @@ int orc_header(const uint8_t *in, uint64_t in_len, uint64_t *out)
     out[5] = h.C;
     out[6] = h.n;
     out[7] = h.nch;
+    out[8] = h.order;
     return ORC_OK;
 }
 
@@ -850,7 +871,8 @@ static void *decode_worker(void *arg)
         for (i = 0; i < nd; i++)
             dig[i] = h->r == 16 ? get_u16(jb->in + off + 4ull * h->N + 2 * i)
                                 : jb->in[off + 4ull * h->N + i];
-        rc = decode_df(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL);
+        rc = h->order ? decode_bf(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL)
+                      : decode_df(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL);
         if (rc != ORC_OK) {
             jb->rc = rc;
             goto out;

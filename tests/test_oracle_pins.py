@@ -374,3 +374,66 @@ def test_uint16_symbols_large_alphabet():
     for r, l in [(16, 16), (8, 23)]:
         buf = oracle.encode(f, syms, 15, r, l, 32, 4096)
         assert (oracle.decode(f, buf, threads=3) == syms).all()
+
+
+# ------------------------------------------------- breadth-first containers --
+
+def _chunk_streams(buf):
+    """(states, digit bytes) of every chunk of a container, from its directory."""
+    import struct
+    raw = buf.tobytes()
+    N = struct.unpack_from("<H", raw, 10)[0]
+    nch = struct.unpack_from("<I", raw, 24)[0]
+    out = []
+    for c in range(nch):
+        off, ln, _ = struct.unpack_from("<QII", raw, 32 + 16 * c)
+        out.append((np.frombuffer(raw[off:off + 4 * N], "<u4"), buf[off + 4 * N:off + ln]))
+    return out
+
+
+def test_breadth_first_container_roundtrip_and_order_byte():
+    rng = np.random.default_rng(21)
+    # half the mass on one symbol, the rest spread over 255 symbols of
+    # frequency below M/b = 16, so many steps emit two 8-bit digits
+    syms = np.where(rng.random(20_000) < 0.5, 0, rng.integers(1, 256, 20_000)).astype(np.uint8)
+    f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), 12)
+    for r, l, N, C in [(8, 23, 64, 4096), (8, 20, 7, 1000), (16, 16, 32, 2048)]:
+        bf = oracle.encode(f, syms, 12, r, l, N, C, order="bf")
+        assert bf[9] == 1 and oracle.header(bf)["order"] == "bf"
+        assert (oracle.decode(f, bf) == syms).all()
+        df = oracle.encode(f, syms, 12, r, l, N, C)
+        assert df[9] == 0 and bf.size == df.size
+        assert (df[:9] == bf[:9]).all() and (df[10:] == bf[10:]).all() if r == 16 else True
+        if r == 8:
+            # b < M: same chunk lengths and states, digits in another order
+            assert (df[32:32 + 16] == bf[32:32 + 16]).all()
+            assert any((a[1] != b[1]).any() for a, b in zip(_chunk_streams(df), _chunk_streams(bf)))
+            # read with the other order the streams fail the end check
+            flipped = bf.copy()
+            flipped[9] = 0
+            with pytest.raises(oracle.OracleError):
+                oracle.decode(f, flipped)
+
+
+def test_breadth_first_container_chunks_equal_digit_level_coder():
+    """Each chunk of a breadth-first container is the digit-level
+    breadth-first coder's stream for that chunk's symbols."""
+    rng = np.random.default_rng(22)
+    syms = rng.integers(0, 60, 5_000).astype(np.uint8)
+    f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), 10)
+    k, r, l, N, C = 10, 8, 23, 16, 1500
+    buf = oracle.encode(f, syms, k, r, l, N, C, order="bf")
+    for c, (states, digs) in enumerate(_chunk_streams(buf)):
+        s, d, _ = oracle.encode_digits(f, k, r, l, N, syms[c * C:(c + 1) * C].tolist(), order="bf")
+        assert (states == s).all() and (digs == np.asarray(d, np.uint8)).all()
+
+
+def test_order_byte_values_above_one_rejected():
+    syms = (np.arange(1000) % 3).astype(np.uint8)
+    f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), 8)
+    buf = oracle.encode(f, syms, 8, 8, 23, 4, 0)
+    buf[9] = 2
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(f, buf)
+    with pytest.raises(ValueError):
+        oracle.encode(f, syms, 8, 8, 23, 4, 0, order="xx")
