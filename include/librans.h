@@ -22,7 +22,8 @@
  *
  * Stream format (container).  All fields little-endian.
  *   header, 32 bytes: u32 magic 0x534E4172 ("rANS"), u8 version 1, u8 k,
- *     u8 r, u8 l, u8 w, u8 0, u16 N, u32 C, u64 n, u32 n_chunks, u32 0
+ *     u8 r, u8 l, u8 w, u8 digit order (0 depth-first, 1 breadth-first),
+ *     u16 N, u32 C, u64 n, u32 n_chunks, u32 0
  *   directory: n_chunks x { u64 offset, u32 length, u32 0 }
  *   chunk streams, each at a 16-byte aligned offset, zero padding between;
  *     the first at align16(32 + 16*n_chunks); the total length is
@@ -30,9 +31,13 @@
  *   chunk c covers symbols [c*C, min(n, (c+1)*C)); its stream is the N final
  *     encoder states (u32, coder 0 first) followed by the digits in decoder
  *     order: u16 words when b = 2^16, bytes when b = 2^8.  A coder that
- *     renormalises by two digits for one symbol stores the more significant
- *     digit first; within one step coders appear in ascending order
- *     (depth-first order, Section 5).  Every coder starts encoding in state L;
+ *     renormalises by two digits for one symbol reads the more significant
+ *     digit first.  Digit order of one step (Section 5): depth-first puts
+ *     each coder's digits together, coders ascending; breadth-first puts the
+ *     first digit of every coder that reads one (coders ascending), then the
+ *     second digit of every coder that reads two.  The orders coincide when
+ *     b >= M (at most one digit per step: always with b = 2^16, as k <= 15),
+ *     so they differ only for b = 2^8 with k > 8.  Every coder starts encoding in state L;
  *     when a chunk's length is not a multiple of N, the last step only
  *     involves coders 0 .. (len mod N)-1.
  *
@@ -71,6 +76,10 @@ extern "C" {
  *                                     the state fits 32 bits
  *   sym_bytes (w) in {1, 2}           uint8 or uint16 symbols
  *   interleave (N) in {1,2,4,...,64}  coders per chunk (one per wave lane)
+ *   digit_order in {0, 1}             0 depth-first, 1 breadth-first digit
+ *                                     order within a step (Section 5);
+ *                                     recorded in the container header, so
+ *                                     decoding takes it from there
  *   reserved == 0
  *   chunk_syms (C)                    symbols per chunk; 0 = the whole input
  *                                     (then n must fit 32 bits)            */
@@ -80,7 +89,8 @@ typedef struct rans_params {
     uint8_t state_lbits;
     uint8_t sym_bytes;
     uint16_t interleave;
-    uint16_t reserved;
+    uint8_t digit_order;
+    uint8_t reserved;
     uint32_t chunk_syms;
 } rans_params;
 
@@ -191,9 +201,9 @@ typedef struct rans_job {
 int rans_encode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *params,
                       void *stream);
 
-/* Batched decode of njobs containers, all encoded with params' k, r, l, w
- * and N (checked per job on the device; a mismatch fails that job with
- * RANS_EINVAL).  Asynchronous, as rans_encode_batch. */
+/* Batched decode of njobs containers, all encoded with params' k, r, l, w,
+ * N and digit order (checked per job on the device; a mismatch fails that
+ * job with RANS_EINVAL).  Asynchronous, as rans_encode_batch. */
 int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *params,
                       void *stream);
 

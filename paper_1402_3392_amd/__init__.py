@@ -33,12 +33,15 @@ class rans_params(ct.Structure):
     """Mirror of the C struct rans_params."""
     _fields_ = [("prob_bits", ct.c_uint8), ("radix_bits", ct.c_uint8),
                 ("state_lbits", ct.c_uint8), ("sym_bytes", ct.c_uint8),
-                ("interleave", ct.c_uint16), ("reserved", ct.c_uint16),
-                ("chunk_syms", ct.c_uint32)]
+                ("interleave", ct.c_uint16), ("digit_order", ct.c_uint8),
+                ("reserved", ct.c_uint8), ("chunk_syms", ct.c_uint32)]
 
     @classmethod
-    def make(cls, k, r, l, w, N, C):
-        return cls(k, r, l, w, N, 0, C)
+    def make(cls, k, r, l, w, N, C, order="df"):
+        """order: "df" (depth-first) or "bf" (breadth-first) digit order."""
+        if order not in ("df", "bf"):
+            raise ValueError(f"digit order {order!r}: expected 'df' or 'bf'")
+        return cls(k, r, l, w, N, 1 if order == "bf" else 0, 0, C)
 
 
 class rans_batch_config(ct.Structure):
@@ -172,7 +175,7 @@ def _params(p) -> rans_params:
     if isinstance(p, rans_params):
         return p
     if isinstance(p, dict):
-        return rans_params.make(p["k"], p["r"], p["l"], p["w"], p["N"], p["C"])
+        return rans_params.make(p["k"], p["r"], p["l"], p["w"], p["N"], p["C"], p.get("order", "df"))
     if hasattr(p, "astuple"):
         return rans_params.make(*p.astuple())
     return rans_params.make(*p)

@@ -28,7 +28,7 @@ int check_params(const rans_params* p)
                    N = p->interleave;
     if (k < 8 || k > 15 || (r != 8 && r != 16) || l < k || l + r > 32 || (w != 1 && w != 2))
         return RANS_EINVAL;
-    if (N < 1 || N > 64 || (N & (N - 1)) != 0 || p->reserved != 0)
+    if (N < 1 || N > 64 || (N & (N - 1)) != 0 || p->digit_order > 1 || p->reserved != 0)
         return RANS_EINVAL;
     return RANS_OK;
 }
@@ -62,7 +62,7 @@ void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint3
     h[6] = p.radix_bits;
     h[7] = p.state_lbits;
     h[8] = p.sym_bytes;
-    h[9] = 0;
+    h[9] = p.digit_order;
     const uint16_t N = p.interleave;
     std::memcpy(h + 10, &N, 2);
     std::memcpy(h + 12, &C, 4);
@@ -80,7 +80,7 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     std::memcpy(&C, h + 12, 4);
     std::memcpy(&n, h + 16, 8);
     std::memcpy(&nch, h + 24, 4);
-    if (magic != kMagic || h[4] != 1 || h[9] != 0)
+    if (magic != kMagic || h[4] != 1 || h[9] > 1)
         return RANS_ECORRUPT;
     rans_params p{};
     p.prob_bits = h[5];
@@ -88,6 +88,7 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     p.state_lbits = h[7];
     p.sym_bytes = h[8];
     p.interleave = N;
+    p.digit_order = h[9];
     p.chunk_syms = C;
     if (check_params(&p) != RANS_OK)
         return RANS_ECORRUPT;
@@ -224,6 +225,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->k = p.prob_bits;
     ea->l = p.state_lbits;
     ea->alphabet = t.alphabet;
+    ea->bf = p.digit_order;
     ea->enc = t.enc;
     ea->enc_bytes = static_cast<uint32_t>(t.enc_bytes);
     ea->slot_bytes = sb;
@@ -432,6 +434,7 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     da->k = h->p.prob_bits;
     da->l = h->p.state_lbits;
     da->alphabet = t.alphabet;
+    da->bf = h->p.digit_order;
     fill_decode_tables(t, *layout, da);
     return RANS_OK;
 }

@@ -47,7 +47,8 @@ std::string cache_key(const rans_params& p, uint32_t alphabet, uint64_t bytes)
         ++alpha_class;
     std::ostringstream os;
     os << prop.gcnArchName << "|k" << int(p.prob_bits) << "|r" << int(p.radix_bits) << "|l"
-       << int(p.state_lbits) << "|w" << int(p.sym_bytes) << "|a" << alpha_class << "|s" << size_class;
+       << int(p.state_lbits) << "|w" << int(p.sym_bytes) << "|o" << int(p.digit_order) << "|a"
+       << alpha_class << "|s" << size_class;
     std::string k = os.str();
     std::replace(k.begin(), k.end(), ' ', '_');
     return k;

@@ -32,11 +32,11 @@ __device__ void plan_job(const BatchArgs& a, uint32_t j, bool decode)
             const uint4 h0 = h4[0], h1 = h4[1];
             const uint32_t magic = h0.x;
             const uint32_t b4 = h0.y;  // version, k, r, l
-            const uint32_t b8 = h0.z;  // w, 0, N (u16)
+            const uint32_t b8 = h0.z;  // w, digit order, N (u16)
             C = h0.w;
             n = uint64_t(h1.x) | (uint64_t(h1.y) << 32);
             nch = h1.z;
-            const bool hdr_ok = magic == kMagic && (b4 & 0xFF) == 1 && ((b8 >> 8) & 0xFF) == 0;
+            const bool hdr_ok = magic == kMagic && (b4 & 0xFF) == 1 && ((b8 >> 8) & 0xFF) <= 1;
             // every chunk takes a directory entry and at least 4N bytes of
             // states: a container that claims more chunks is malformed (and
             // the host sized the work-item map by this bound)
@@ -44,7 +44,8 @@ __device__ void plan_job(const BatchArgs& a, uint32_t j, bool decode)
                 kHeaderBytes + (uint64_t(kDirEntryBytes) + 4ull * a.N) * nch > jb.in_len) {
                 st = RANS_ECORRUPT;
             } else if (((b4 >> 8) & 0xFF) != a.k || ((b4 >> 16) & 0xFF) != a.r ||
-                       (b4 >> 24) != a.l || (b8 & 0xFF) != a.w || (b8 >> 16) != a.N) {
+                       (b4 >> 24) != a.l || (b8 & 0xFF) != a.w || (b8 >> 16) != a.N ||
+                       ((b8 >> 8) & 0xFF) != a.bf) {
                 st = RANS_EINVAL;
             } else if (n * a.w > jb.out_cap) {
                 st = RANS_ENOSPC;
@@ -176,7 +177,7 @@ __device__ __forceinline__ int next_item(const BatchArgs& a, uint32_t* s_slot, u
     return static_cast<int>(s_slot[1]);
 }
 
-template <int R, int W, int SW, int LAYOUT, int NL>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
 __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -202,7 +203,7 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
         if (c < nch) {
             const uint32_t sym_bytes = c64::uni(jb.sym_bytes);
-            c64::decode_chunk<R, W, SW, LAYOUT, NL>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
+            c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
                                                 a.k, a.l, tab,
                                                 reinterpret_cast<const uint32_t*>(tab + sym_bytes),
                                                 wave_lds, jb.d_status);
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
     }
 }
 
-template <int R, int W, int NL>
+template <int R, int W, int NL, bool BF>
 __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
         if (c < nch) {
             const uint64_t g = c64::uni(jb.chunk_base) + uint64_t(c);
-            c64::encode_chunk<R, W, NL>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
+            c64::encode_chunk<R, W, NL, BF>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
                                     reinterpret_cast<const uint4*>(lds), a.slots + g * a.slot_stride,
                                     a.slot_bytes, sbuf, a.states + g * 64, a.ndig + g, jb.d_status);
         }
@@ -284,7 +285,7 @@ __global__ void __launch_bounds__(256) k_batch_cscan(BatchArgs a)
             uint32_t* h = reinterpret_cast<uint32_t*>(jb.out);
             h[0] = kMagic;
             h[1] = 1u | (a.k << 8) | (a.r << 16) | (a.l << 24);
-            h[2] = a.w | (a.N << 16);
+            h[2] = a.w | (a.bf << 8) | (a.N << 16);
             h[3] = jb.C;
             h[4] = static_cast<uint32_t>(jb.n);
             h[5] = static_cast<uint32_t>(jb.n >> 32);
@@ -343,11 +344,11 @@ hipError_t set_lds(K kernel, uint32_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
 }
 
-template <int R, int W, int SW, int LAYOUT, int NL>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
 hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
     const uint32_t lds = a.tab_lds + a.G * c64::wave_lds_bytes(LAYOUT);
-    auto kern = k_batch_decode64<R, W, SW, LAYOUT, NL>;
+    auto kern = k_batch_decode64<R, W, SW, LAYOUT, NL, BF>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)
         return e;
@@ -355,43 +356,51 @@ hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int R, int W, int SW, int LAYOUT>
+template <int R, int W, int SW, int LAYOUT, bool BF>
 hipError_t persistent_decode_n(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
-    return a.N == 32 ? persistent_decode<R, W, SW, LAYOUT, 32>(a, grid, st)
-                     : persistent_decode<R, W, SW, LAYOUT, 64>(a, grid, st);
+    return a.N == 32 ? persistent_decode<R, W, SW, LAYOUT, 32, BF>(a, grid, st)
+                     : persistent_decode<R, W, SW, LAYOUT, 64, BF>(a, grid, st);
 }
 
-template <int R, int W, int SW>
+template <int R, int W, int SW, bool BF>
 hipError_t persistent_decode_l(const BatchArgs& a, Layout layout, uint32_t grid, hipStream_t st)
 {
     if (SW == 1 && layout == kFused)
-        return persistent_decode_n<R, W, 1, kFused>(a, grid, st);
-    return layout == kPacked ? persistent_decode_n<R, W, SW, kPacked>(a, grid, st)
-                             : persistent_decode_n<R, W, SW, kTwoLevel>(a, grid, st);
+        return persistent_decode_n<R, W, 1, kFused, BF>(a, grid, st);
+    return layout == kPacked ? persistent_decode_n<R, W, SW, kPacked, BF>(a, grid, st)
+                             : persistent_decode_n<R, W, SW, kTwoLevel, BF>(a, grid, st);
 }
 
-template <int R>
+template <int R, bool BF>
 hipError_t persistent_decode_w(const BatchArgs& a, int W, int SW, Layout layout, uint32_t grid,
                                hipStream_t st)
 {
     if (W == 1)
-        return persistent_decode_l<R, 1, 1>(a, layout, grid, st);
+        return persistent_decode_l<R, 1, 1, BF>(a, layout, grid, st);
     if (SW == 1)
-        return persistent_decode_l<R, 2, 1>(a, layout, grid, st);
-    return persistent_decode_l<R, 2, 2>(a, layout, grid, st);
+        return persistent_decode_l<R, 2, 1, BF>(a, layout, grid, st);
+    return persistent_decode_l<R, 2, 2, BF>(a, layout, grid, st);
 }
 
-template <int R, int W, int NL>
+template <int R, int W, int NL, bool BF>
 hipError_t persistent_encode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
     const uint32_t lds = a.tab_lds + a.G * c64::kEncWaveLds;
-    auto kern = k_batch_encode64<R, W, NL>;
+    auto kern = k_batch_encode64<R, W, NL, BF>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * a.G), lds, st, a);
     return hipGetLastError();
+}
+
+template <int R, bool BF>
+hipError_t persistent_encode_w(const BatchArgs& a, int W, uint32_t grid, hipStream_t st)
+{
+    if (a.N == 32)
+        return W == 1 ? persistent_encode<R, 1, 32, BF>(a, grid, st) : persistent_encode<R, 2, 32, BF>(a, grid, st);
+    return W == 1 ? persistent_encode<R, 1, 64, BF>(a, grid, st) : persistent_encode<R, 2, 64, BF>(a, grid, st);
 }
 
 }  // namespace
@@ -405,21 +414,19 @@ hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, L
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
+    // 16-bit digits: one digit per step at most (b >= M), both orders coincide
     if (decode) {
-        e = R == 16 ? persistent_decode_w<16>(a, W, SW, layout, grid, st)
-                    : persistent_decode_w<8>(a, W, SW, layout, grid, st);
-        return e;
-    }
-    if (a.N == 32) {
         if (R == 16)
-            e = W == 1 ? persistent_encode<16, 1, 32>(a, grid, st) : persistent_encode<16, 2, 32>(a, grid, st);
-        else
-            e = W == 1 ? persistent_encode<8, 1, 32>(a, grid, st) : persistent_encode<8, 2, 32>(a, grid, st);
-    } else if (R == 16) {
-        e = W == 1 ? persistent_encode<16, 1, 64>(a, grid, st) : persistent_encode<16, 2, 64>(a, grid, st);
-    } else {
-        e = W == 1 ? persistent_encode<8, 1, 64>(a, grid, st) : persistent_encode<8, 2, 64>(a, grid, st);
+            return persistent_decode_w<16, false>(a, W, SW, layout, grid, st);
+        return a.bf ? persistent_decode_w<8, true>(a, W, SW, layout, grid, st)
+                    : persistent_decode_w<8, false>(a, W, SW, layout, grid, st);
     }
+    if (R == 16)
+        e = persistent_encode_w<16, false>(a, W, grid, st);
+    else if (a.bf)
+        e = persistent_encode_w<8, true>(a, W, grid, st);
+    else
+        e = persistent_encode_w<8, false>(a, W, grid, st);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_batch_cscan, dim3(a.njobs), dim3(256), 0, st, a);

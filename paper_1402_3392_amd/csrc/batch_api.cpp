@@ -203,6 +203,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     a.w = w;
     a.N = p.interleave;
     a.C = p.chunk_syms;
+    a.bf = p.digit_order;
     a.G = G;
     a.counter = reinterpret_cast<uint32_t*>(base + rg.ctrl);
     a.totals = a.counter + 4;

@@ -124,7 +124,9 @@ __device__ __forceinline__ void stage2(uint8_t* lds, const void* a, uint32_t aby
 // per-symbol f|cum entries or the fused entries), wave_lds this wave's
 // wave_lds_bytes(LAYOUT) bytes.  Every argument must be wave-uniform.  When
 // it returns, every load it issued has completed, so wave_lds can be reused.
-template <int R, int W, int SW, int LAYOUT, int NL>
+// BF: the chunk's digits are in breadth-first order (Section 5; only byte
+// digits can differ from depth-first).
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false>
 __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                              uint64_t chunk, uint32_t C, uint64_t n, void* out_base,
                                              uint32_t k_, uint32_t l, const void* l_sym_v,
@@ -267,6 +269,10 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     // Refill: every lane reads the ring at its would-be digit (the ring
     // position, a scalar, plus the prefix count of refilling lanes below it)
     // and a select on the ballot keeps the digit in the lanes that need it.
+    // With byte digits a lane may read two: depth-first they are adjacent
+    // (after the digits of the lanes below); breadth-first the first digits
+    // of all reading lanes come first, then the second digits.  Either way
+    // the step reads digits [pos, pos + |m1| + |m2|).
     // In sparse chunks the step is skipped as a whole when no lane refills;
     // in dense ones (dense = std::true_type) it runs unconditionally, which
     // takes a branch off every step's dependency chain.
@@ -284,9 +290,16 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             const bool n2 = act && x < (L >> 8);
             const uint64_t m2 = ballot(n2);
             if (dense || m1) {
-                const uint8_t* r = ring + (pos & DMASK) + mbcnt(m2, mbcnt(m1, 0));
-                const uint32_t x1 = (x << 8) | r[0];
-                const uint32_t x2 = (x1 << 8) | r[1];
+                const uint8_t* r = ring + (pos & DMASK);
+                uint32_t x1, x2;
+                if (BF) {
+                    x1 = (x << 8) | r[mbcnt(m1, 0)];
+                    x2 = (x1 << 8) | r[mbcnt(m2, __popcll(m1))];
+                } else {
+                    const uint8_t* q = r + mbcnt(m2, mbcnt(m1, 0));
+                    x1 = (x << 8) | q[0];
+                    x2 = (x1 << 8) | q[1];
+                }
                 x = select_mask(m1, x, select_mask(m2, x1, x2));
                 pos += __popcll(m1) + __popcll(m2);
             }
@@ -449,8 +462,11 @@ __device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32
 // (at their slot positions modulo the ring; positions from a ballot prefix,
 // the stream growing downwards), then applies C.  bad collects the entries'
 // bit 23 (a symbol the table cannot encode).  e: the symbol's staged entry
-// (read ahead by the caller).
-template <int R>
+// (read ahead by the caller).  BF: breadth-first digit order (Section 5):
+// the step's block holds the first digit of every emitting lane, then the
+// second digit of every lane that emits two; depth-first keeps a lane's two
+// digits together.  Either way a lane's more significant digit is read first.
+template <int R, bool BF = false>
 __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& bad, const uint4& e,
                                          bool act, uint8_t* dring, uint32_t lane)
 {
@@ -471,9 +487,16 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         const bool e2 = act && (x >> 8) > e.y;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
         wpos -= __popcll(m1) + __popcll(m2);
-        const uint32_t idx = wpos + mbcnt(m2, mbcnt(m1, 0));
-        const uint32_t o1 = select_mask(m1, kEncRing + lane, idx & (RD - 1));
-        const uint32_t o2 = select_mask(m2, kEncRing + 64 + lane, (idx + 1) & (RD - 1));
+        uint32_t i1, i2;
+        if (BF) {
+            i1 = wpos + mbcnt(m1, 0);
+            i2 = wpos + mbcnt(m2, __popcll(m1));
+        } else {
+            i1 = wpos + mbcnt(m2, mbcnt(m1, 0));
+            i2 = i1 + 1;
+        }
+        const uint32_t o1 = select_mask(m1, kEncRing + lane, i1 & (RD - 1));
+        const uint32_t o2 = select_mask(m2, kEncRing + 64 + lane, i2 & (RD - 1));
         dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
         dring[o2] = static_cast<uint8_t>(x);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
@@ -498,8 +521,9 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
 // every block of symbols, the windows the stream has grown past, padded to
 // kFlushStores stores with stores to the 256 bytes after the slot.  A fixed
 // number of memory operations per block lets the compiler's wait for the
-// symbols of the next block leave the recent stores in flight.
-template <int R, int W, int NL>
+// symbols of the next block leave the recent stores in flight.  BF: as in
+// enc_step.
+template <int R, int W, int NL, bool BF = false>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
                                              const uint4* l_enc, uint8_t* slot, uint64_t slot_bytes,
@@ -548,7 +572,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         const uint64_t i = uint64_t(t) * NL + lane;
         const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
-        enc_step<R>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
+        enc_step<R, BF>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
     }
     flush();  // the tail is shorter than a block: at most 8 windows
 
@@ -578,7 +602,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             for (int q = SPB - 1; q >= 0; --q) {
                 if (q - PF >= 0)
                     ent[q - PF] = l_enc[sy[q - PF]];
-                enc_step<R>(x, wpos, bad, ent[q], live, dring, lane);
+                enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
             }
             flush();
         };

@@ -6,7 +6,7 @@
 namespace rans {
 namespace {
 
-template <int R, int W, int SW, int LAYOUT, int NL>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
 __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -27,18 +27,18 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
     const uint64_t chunk = uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (chunk >= a.n_chunks)
         return;  // no barrier follows
-    c64::decode_chunk<R, W, SW, LAYOUT, NL>(a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, tab,
+    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, tab,
                                         reinterpret_cast<const uint32_t*>(tab + sym_bytes),
                                         lds + wave * c64::wave_lds_bytes(LAYOUT), a.status);
 }
 
-template <int R, int W, int SW, int LAYOUT, int NL>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
 hipError_t run(const DecodeArgs& a, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
     const uint32_t lds = a.tab0_bytes + a.tab1_bytes + wpb * c64::wave_lds_bytes(LAYOUT);
-    auto kern = k_decode64<R, W, SW, LAYOUT, NL>;
+    auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -47,28 +47,28 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int R, int W, int SW, int LAYOUT>
+template <int R, int W, int SW, int LAYOUT, bool BF>
 hipError_t run_n(const DecodeArgs& a, hipStream_t st)
 {
-    return a.N == 32 ? run<R, W, SW, LAYOUT, 32>(a, st) : run<R, W, SW, LAYOUT, 64>(a, st);
+    return a.N == 32 ? run<R, W, SW, LAYOUT, 32, BF>(a, st) : run<R, W, SW, LAYOUT, 64, BF>(a, st);
 }
 
-template <int R, int W, int SW>
+template <int R, int W, int SW, bool BF>
 hipError_t run_l(const DecodeArgs& a, Layout layout, hipStream_t st)
 {
     if (SW == 1 && layout == kFused)
-        return run_n<R, W, 1, kFused>(a, st);
-    return layout == kPacked ? run_n<R, W, SW, kPacked>(a, st) : run_n<R, W, SW, kTwoLevel>(a, st);
+        return run_n<R, W, 1, kFused, BF>(a, st);
+    return layout == kPacked ? run_n<R, W, SW, kPacked, BF>(a, st) : run_n<R, W, SW, kTwoLevel, BF>(a, st);
 }
 
-template <int R>
+template <int R, bool BF>
 hipError_t run_w(const DecodeArgs& a, int W, Layout layout, hipStream_t st)
 {
     if (W == 1)
-        return run_l<R, 1, 1>(a, layout, st);
+        return run_l<R, 1, 1, BF>(a, layout, st);
     if (a.alphabet <= 256)
-        return run_l<R, 2, 1>(a, layout, st);
-    return run_l<R, 2, 2>(a, layout, st);
+        return run_l<R, 2, 1, BF>(a, layout, st);
+    return run_l<R, 2, 2, BF>(a, layout, st);
 }
 
 }  // namespace
@@ -79,7 +79,10 @@ hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hip
 {
     if (a.n_chunks == 0)
         return hipSuccess;
-    return R == 16 ? run_w<16>(a, W, layout, stream) : run_w<8>(a, W, layout, stream);
+    // 16-bit digits: one digit per step at most (b >= M), both orders coincide
+    if (R == 16)
+        return run_w<16, false>(a, W, layout, stream);
+    return a.bf ? run_w<8, true>(a, W, layout, stream) : run_w<8, false>(a, W, layout, stream);
 }
 
 }  // namespace rans

@@ -74,10 +74,13 @@ __device__ __forceinline__ Lanes lane_geometry(uint32_t log2N)
 //   then while x < L: x = b*x + next digit.
 // With b = 2^16 >= M at most one digit is read (Section 5); with b = 2^8 and
 // L = 2^l, l >= 16, at most two, and the count is known before reading:
-// d = [x < L] + [x < L/256] since L is a multiple of 256.  The digits of one
-// step are laid out coder by coder, each coder's more significant digit first
-// (depth-first order), so coder j's first digit sits at
-//   pos + #{lanes below j with d >= 1} + #{lanes below j with d >= 2}.
+// d = [x < L] + [x < L/256] since L is a multiple of 256.  Depth-first
+// order (Section 5) lays the digits of one step out coder by coder, each
+// coder's more significant digit first, so coder j's digits sit at
+//   pos + #{lanes below j with d >= 1} + #{lanes below j with d >= 2} (+1);
+// breadth-first order puts every coder's first digit before any second one:
+//   pos + #{lanes below j with d >= 1}  and
+//   pos + #{lanes with d >= 1} + #{lanes below j with d >= 2}.
 
 template <int R, int W, int SW, int LAYOUT, bool FULL>
 __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
@@ -149,14 +152,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
         const bool n2 = R == 8 && act && x < (L >> 8);
         const uint64_t m1 = ballot(n1);
         const uint64_t m2 = R == 8 ? ballot(n2) : 0ull;
-        uint32_t o, adv;
-        if (FULL) {
-            o = prefix(m1) + (R == 8 ? prefix(m2) : 0u);
-            adv = popc(m1) + (R == 8 ? popc(m2) : 0u);
-        } else {
-            o = popc(m1 & g.below) + (R == 8 ? popc(m2 & g.below) : 0u);
-            adv = popc(m1 & g.segmask) + (R == 8 ? popc(m2 & g.segmask) : 0u);
-        }
+        const uint32_t b1 = FULL ? prefix(m1) : popc(m1 & g.below);
+        const uint32_t b2 = FULL ? prefix(m2) : popc(m2 & g.below);
+        const uint32_t t1 = FULL ? popc(m1) : popc(m1 & g.segmask);
+        const uint32_t t2 = FULL ? popc(m2) : popc(m2 & g.segmask);
+        const uint32_t o = a.bf ? b1 : b1 + b2;
         if (n1) {
             uint32_t idx = pos + o;
             uint32_t d = 0;
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
                 bad = true;
             x = (x << R) | d;
             if (R == 8 && n2) {
-                ++idx;
+                idx = a.bf ? pos + t1 + b2 : idx + 1;
                 d = 0;
                 if (idx < ndig)
                     d = dig[idx];
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
                 x = (x << 8) | d;
             }
         }
-        pos += adv;
+        pos += t1 + t2;
         if (act)
             out[i] = static_cast<OutT>(s);
     }
@@ -196,7 +196,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
 //   x = C(s,x) = M*floor(x/f) + (x mod f) + cum = x + q*(M - f) + cum, q = floor(x/f)
 // C(s,x) >= bL  <=>  x >= f * 2^(l+r-k)  <=>  (x >> (l+r-k)) >= f.
 // The digits of the step are prepended as one block laid out like the
-// decoder reads it: coders ascending, each coder's high digit first.
+// decoder reads it: coders ascending, each coder's high digit first, in
+// depth-first or breadth-first order (as the decoder above describes).
 
 template <int R, int W, bool FULL>
 __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
@@ -244,17 +245,13 @@ __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
         const bool e2 = R == 8 && act && (x >> (sh + 8)) >= f;
         const uint64_t m1 = ballot(e1);
         const uint64_t m2 = R == 8 ? ballot(e2) : 0ull;
-        uint32_t o, tot;
-        if (FULL) {
-            o = prefix(m1) + (R == 8 ? prefix(m2) : 0u);
-            tot = popc(m1) + (R == 8 ? popc(m2) : 0u);
-        } else {
-            o = popc(m1 & g.below) + (R == 8 ? popc(m2 & g.below) : 0u);
-            tot = popc(m1 & g.segmask) + (R == 8 ? popc(m2 & g.segmask) : 0u);
-        }
-        wpos -= tot;
+        const uint32_t b1 = FULL ? prefix(m1) : popc(m1 & g.below);
+        const uint32_t b2 = FULL ? prefix(m2) : popc(m2 & g.below);
+        const uint32_t t1 = FULL ? popc(m1) : popc(m1 & g.segmask);
+        const uint32_t t2 = FULL ? popc(m2) : popc(m2 & g.segmask);
+        wpos -= t1 + t2;
         if (e1) {
-            const uint32_t idx = wpos + o;
+            const uint32_t idx = wpos + (a.bf ? b1 : b1 + b2);
             if (R == 16) {
                 if (idx < cap)
                     reinterpret_cast<uint16_t*>(slot)[idx] = static_cast<uint16_t>(x);
@@ -262,9 +259,10 @@ __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
                     overflow = true;
                 x >>= 16;
             } else if (e2) {
-                if (idx + 1 < cap) {
+                const uint32_t idx2 = a.bf ? wpos + t1 + b2 : idx + 1;
+                if (idx < cap && idx2 < cap) {
                     slot[idx] = static_cast<uint8_t>(x >> 8);
-                    slot[idx + 1] = static_cast<uint8_t>(x);
+                    slot[idx2] = static_cast<uint8_t>(x);
                 } else {
                     overflow = true;
                 }

@@ -56,6 +56,7 @@ struct DecodeArgs {
     uint32_t log2N;
     uint32_t k, l;
     uint32_t alphabet;
+    uint32_t bf;         // breadth-first digit order (Section 5)
     const void* tab0;    // kPacked: dec; kTwoLevel: sym
     const void* tab1;    // kPacked: sym; kTwoLevel: fc
     uint32_t tab0_bytes, tab1_bytes;  // multiples of 16
@@ -71,6 +72,7 @@ struct EncodeArgs {
     uint32_t log2N;
     uint32_t k, l;
     uint32_t alphabet;
+    uint32_t bf;          // breadth-first digit order (Section 5)
     const uint4* enc;     // alphabet + 1 entries
     uint32_t enc_bytes;   // multiple of 16
     uint8_t* slots;       // n_chunks slots, slot_stride apart
@@ -150,6 +152,7 @@ struct BatchArgs {
     BatchJob* jobs;
     uint32_t njobs;
     uint32_t k, r, l, w, N, C;  // C: encode chunk size (0 = whole input)
+    uint32_t bf;                // breadth-first digit order (Section 5)
     uint32_t G;                 // chunks per work item = waves per block
     uint32_t* counter;          // work-queue head, zeroed before the pass
     uint32_t* totals;           // [0] work items, [1] chunks

@@ -76,6 +76,15 @@ def test_params_check(lr):
         assert lr.rans_params_check(p) == 0, p
     for p in bad:
         assert lr.rans_params_check(p) == lr.RANS_EINVAL, p
+    # digit order: 0 depth-first, 1 breadth-first, nothing else
+    for order in ("df", "bf"):
+        assert lr.rans_params_check(lr.rans_params.make(15, 8, 23, 1, 64, 4096, order)) == 0
+    p = lr.rans_params.make(15, 8, 23, 1, 64, 4096)
+    p.digit_order = 2
+    assert lr.rans_params_check(p) == lr.RANS_EINVAL
+    assert lr.rans_encode_bound(1000, p) == 0
+    with pytest.raises(ValueError):
+        lr.rans_params.make(15, 8, 23, 1, 64, 4096, "zz")
 
 
 def test_encode_bound_covers_oracle(lr):

@@ -54,9 +54,9 @@ class Pool:
         return self.buf[o:o + nbytes].cpu().numpy()
 
 
-def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64):
+def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64, order="df"):
     import torch
-    params = lr.rans_params.make(k, r, l, 1, N, C)
+    params = lr.rans_params.make(k, r, l, 1, N, C, order)
     tables, specs = [], []
     total = sum(s.size for s, _ in data)
     pool = Pool(sum(lr.rans_encode_bound(s.size, params) + s.size + 1024 for s, _ in data))
@@ -81,9 +81,9 @@ def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64):
     return tables, outs, st.cpu().numpy(), lens.cpu().numpy()
 
 
-def run_decode_batch(lr, tables, containers, sizes, k, r, l, corrupt=None, N=64):
+def run_decode_batch(lr, tables, containers, sizes, k, r, l, corrupt=None, N=64, order="df"):
     import torch
-    params = lr.rans_params.make(k, r, l, 1, N, 0)
+    params = lr.rans_params.make(k, r, l, 1, N, 0, order)
     pool = Pool(sum(c.size + n + 1024 for c, n in zip(containers, sizes)))
     lens = torch.zeros(len(containers), dtype=torch.int64, device="cuda")
     st = torch.full((len(containers),), 99, dtype=torch.int32, device="cuda")
@@ -119,6 +119,33 @@ def test_batch_encode_decode_match_oracle(lr, k, r, l, C, N):
     for i, (s, _) in enumerate(data):
         assert n2[i] == s.size
         assert (dec[i] == s).all(), i
+
+
+@pytest.mark.parametrize("N,C,layout", [(64, 8192, 1), (64, 2048, 2), (32, 4096, 3), (32, 1024, 0)])
+def test_batch_breadth_first_match_oracle(lr, N, C, layout):
+    """Breadth-first containers (Section 5) through the batched kernels, on
+    every decoder table layout; a depth-first decode of them fails per job."""
+    lr.rans_batch_set_config(16, 1, layout, 1)
+    try:
+        k, r, l = 12, 8, 23
+        data = streams(24, seed=4600 + N + layout)
+        tables, outs, st, _ = run_encode_batch(lr, data, k, r, l, C, N=N, order="bf")
+        assert (st == 0).all(), st
+        refs = []
+        for i, (s, _) in enumerate(data):
+            ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, N, C,
+                                order="bf")
+            refs.append(ref)
+            assert outs[i].size == ref.size and (outs[i] == ref).all(), (i, first_diff(outs[i], ref))
+        sizes = [s.size for s, _ in data]
+        dec, st2, n2 = run_decode_batch(lr, tables, refs, sizes, k, r, l, N=N, order="bf")
+        assert (st2 == 0).all(), st2
+        for i, (s, _) in enumerate(data):
+            assert n2[i] == s.size and (dec[i] == s).all(), i
+        _, st3, _ = run_decode_batch(lr, tables, refs, sizes, k, r, l, N=N, order="df")
+        assert (st3 == lr.RANS_EINVAL).all(), st3
+    finally:
+        lr.rans_batch_set_config(16, 1, 0, 1)
 
 
 def test_batch_failures_are_isolated(lr):

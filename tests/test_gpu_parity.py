@@ -100,6 +100,63 @@ def test_bitstream_and_symbols_match_oracle(lr, case):
     assert (dec == syms).all(), first_diff(dec.view(np.uint8), syms.view(np.uint8))
 
 
+# Breadth-first digit order (Section 5).  It differs from depth-first only
+# when a step can read two digits (b = 2^8 < M): one-wave-per-chunk kernels
+# (N = 32, 64; w = 1 and 2; sparse and dense refills; ragged last chunks) and
+# the generic kernels (N < 32); a 16-bit-digit case must give the depth-first
+# payload.
+BF_CASES = [
+    (256, "zipf", 15, 8, 23, 64, 4096, 100_000),
+    (256, "zipf", 12, 8, 23, 32, 8192, 150_001),
+    (256, "zipf", 12, 8, 23, 64, 1024, 5 * 1024 + 960),
+    (4096, "near_uniform", 15, 8, 23, 64, 8192, 70_001),
+    (4096, "near_uniform", 15, 8, 23, 32, 2048, 2 * 2048 + 15 * 32 + 5),
+    (256, "dominant", 15, 8, 23, 32, 4096, 300_000),
+    (4096, "near_uniform", 14, 8, 22, 64, 1024, 7 * 1024 + 999),
+    (256, "zipf", 12, 8, 20, 16, 1000, 20_011),
+    (256, "zipf", 14, 8, 23, 4, 999, 20_011),
+    (256, "zipf", 13, 8, 23, 1, 0, 20_011),
+    (256, "zipf", 14, 16, 16, 64, 4096, 200_007),
+]
+
+
+@pytest.mark.parametrize("case", BF_CASES, ids=[ids(c) for c in BF_CASES])
+def test_breadth_first_matches_oracle(lr, case):
+    alphabet, dist, k, r, l, N, C, n = case
+    syms = make_syms(alphabet, dist, n, seed=zlib.crc32(("bf" + ids(case)).encode()))
+    w = syms.dtype.itemsize
+    counts = datagen.counts(syms, alphabet)
+    f_or = oracle.quantize(counts, k)
+    table = lr.rans_tables_build(counts, k)
+    print(f"[parity-bf] {ids(case)}", flush=True)
+    ref = oracle.encode(f_or, syms, k, r, l, N, C, threads=4, order="bf")
+    df = oracle.encode(f_or, syms, k, r, l, N, C, threads=4)
+    if r == 16 or N == 1:
+        assert (ref[10:] == df[10:]).all()   # one digit per step, or one coder
+    else:
+        assert (ref[32:] != df[32:]).any()   # the case exercises the order
+    got = gpu_encode(lr, table, (k, r, l, w, N, C, "bf"), syms)
+    assert got[9] == 1
+    assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
+    dec = gpu_decode(lr, table, ref, n, w)
+    assert (dec == syms).all(), first_diff(dec.view(np.uint8), syms.view(np.uint8))
+    if r == 8 and N > 1:
+        # read in the other order, the streams fail the end-of-chunk check
+        flipped = ref.copy()
+        flipped[9] = 0
+        assert _decode_rc(lr, table, flipped, n) == lr.RANS_ECORRUPT
+        flipped = df.copy()
+        flipped[9] = 1
+        assert _decode_rc(lr, table, flipped, n) == lr.RANS_ECORRUPT
+
+
+def test_unknown_digit_order_rejected(lr):
+    syms, table, ref = _container(lr)
+    bad = ref.copy()
+    bad[9] = 2
+    assert _decode_rc(lr, table, bad, syms.size) == lr.RANS_ECORRUPT
+
+
 def test_single_symbol_alphabet(lr):
     """f = M: C and D are the identity and nothing is ever emitted."""
     syms = np.zeros(10_000, dtype=np.uint8)
