@@ -81,6 +81,11 @@ def parse():
     ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
     ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
+    ap.add_argument("--chunk-syms", type=int, default=0,
+                    help="sweep: fixed chunk size in symbols (0: autotune per point)")
+    ap.add_argument("--order", default="df", choices=["df", "bf"],
+                    help="sweep: digit order within a step, depth-first or breadth-first "
+                         "(differs only with byte digits)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernels' source hash")
     return ap.parse_args()
 
@@ -302,7 +307,7 @@ def run_sweep(args):
         syms = cache[key]
         w = 1 if p["alphabet"] <= 256 else 2
         row = {"idx": idx, "alphabet": p["alphabet"], "dist": p["dist"], "k": p["k"], "r": p["r"],
-               "l": p["l"], "N": p["N"]}
+               "l": p["l"], "N": p["N"], "order": args.order}
         if not p["feasible"]:
             row["status"] = "n/a (more symbols present than 2^k)"
             rows.append(row)
@@ -312,14 +317,22 @@ def run_sweep(args):
         f = oracle.quantize(counts, p["k"])
         table = lr.rans_tables_build(counts, p["k"])
         d_syms = torch.from_numpy(syms.view(np.uint8)).cuda()
-        # chunk size and batched launch shape from the autotuner, on this buffer
-        tune = lr.rans_autotune(table, d_syms, syms.size,
-                                lr.rans_params.make(p["k"], p["r"], p["l"], w, 64, 65536 // w))
-        C = int(tune["chunk_syms"])
-        row.update(C=C, G=int(tune["waves_per_group"]), gpc=int(tune["groups_per_cu"]),
-                   layout=int(tune["table_layout"]))
-        params = lr.rans_params.make(p["k"], p["r"], p["l"], w, p["N"], C)
-        cont = oracle.encode(f, syms, p["k"], p["r"], p["l"], p["N"], C, threads=threads)
+        if args.chunk_syms:
+            C = args.chunk_syms
+            cfg = lr.rans_batch_get_config()
+            row.update(C=C, G=cfg["waves_per_group"], gpc=cfg["groups_per_cu"],
+                       layout=cfg["table_layout"])
+        else:
+            # chunk size and batched launch shape from the autotuner, on this buffer
+            tune = lr.rans_autotune(table, d_syms, syms.size,
+                                    lr.rans_params.make(p["k"], p["r"], p["l"], w, 64, 65536 // w,
+                                                        args.order))
+            C = int(tune["chunk_syms"])
+            row.update(C=C, G=int(tune["waves_per_group"]), gpc=int(tune["groups_per_cu"]),
+                       layout=int(tune["table_layout"]))
+        params = lr.rans_params.make(p["k"], p["r"], p["l"], w, p["N"], C, args.order)
+        cont = oracle.encode(f, syms, p["k"], p["r"], p["l"], p["N"], C, threads=threads,
+                             order=args.order)
         cap = lr.rans_encode_bound(syms.size, params)
         d_enc = torch.empty(cap, dtype=torch.uint8, device="cuda")
         nb = lr.rans_encode(table, params, d_syms, syms.size, d_enc, cap)
@@ -368,7 +381,8 @@ def run_sweep(args):
                       best, "GB/s", args,
                       {"workload": "64 MiB symbol bytes per point; alphabets 2/16/256/4096, "
                                    "M=2^11/2^15, p0=0.995 / Zipf(1.1) / near-uniform, "
-                                   "(b,L)=(2^8,2^23)/(2^16,2^16), N=32/64, autotuned chunk size"})
+                                   "(b,L)=(2^8,2^23)/(2^16,2^16), N=32/64, autotuned chunk size",
+                                   "digit_order": args.order})
     out["points"] = rows
     print(json.dumps(out), flush=True)
 

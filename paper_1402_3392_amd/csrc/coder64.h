@@ -293,10 +293,16 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
                 const uint8_t* r = ring + (pos & DMASK);
                 uint32_t x1, x2;
                 if (BF) {
+                    // the second digits start after every first digit: a
+                    // scalar base, so each address is one mbcnt pair plus
+                    // one add
+                    const uint8_t* r2 = r + __popcll(m1);
                     x1 = (x << 8) | r[mbcnt(m1, 0)];
-                    x2 = (x1 << 8) | r[mbcnt(m2, __popcll(m1))];
+                    x2 = (x1 << 8) | r2[mbcnt(m2, 0)];
                 } else {
-                    const uint8_t* q = r + mbcnt(m2, mbcnt(m1, 0));
+                    // two independent prefix counts (a shorter chain than
+                    // accumulating one into the other)
+                    const uint8_t* q = r + (mbcnt(m1, 0) + mbcnt(m2, 0));
                     x1 = (x << 8) | q[0];
                     x2 = (x1 << 8) | q[1];
                 }
@@ -490,9 +496,9 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         uint32_t i1, i2;
         if (BF) {
             i1 = wpos + mbcnt(m1, 0);
-            i2 = wpos + mbcnt(m2, __popcll(m1));
+            i2 = (wpos + __popcll(m1)) + mbcnt(m2, 0);
         } else {
-            i1 = wpos + mbcnt(m2, mbcnt(m1, 0));
+            i1 = wpos + (mbcnt(m1, 0) + mbcnt(m2, 0));
             i2 = i1 + 1;
         }
         const uint32_t o1 = select_mask(m1, kEncRing + lane, i1 & (RD - 1));
