@@ -73,11 +73,12 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="roundtrip",
-                    choices=["roundtrip", "batched", "sweep", "serving"],
+                    choices=["roundtrip", "batched", "sweep", "serving", "dequant"],
                     help="roundtrip: the headline line (3 x 256 MiB encode+decode); "
                          "batched: 4096 uneven streams, one persistent launch vs plain calls; "
                          "sweep: radix/precision/alphabet sweep, batched vs plain decode; "
-                         "serving: Poisson request loop, p50/p99 latency")
+                         "serving: Poisson request loop, p50/p99 latency; "
+                         "dequant: decode fused with a codebook lookup vs decode + gather")
     ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
     ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
@@ -387,6 +388,103 @@ def run_sweep(args):
     print(json.dumps(out), flush=True)
 
 
+def run_dequant(args):
+    """Decode fused with a codebook lookup (a consumer in the same kernel):
+    256 MiB of 8-bit quantisation codes of a normally distributed tensor,
+    decoded straight to bf16 (or fp32) values, against the unfused pair
+    decode-to-codes + a separate gather."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1402_3392_amd as lr
+
+    K, R, L, W, N, C = 14, 16, 16, 1, 64, 65536
+    n = 1 << args.size_log2
+    log(f"generating {n >> 20} MiB of Gaussian 8-bit codes")
+    rng = np.random.Generator(np.random.PCG64(6001))
+    syms = datagen.sample(datagen.gaussian_codes_probs(256, 24.0), n, rng)
+    counts = datagen.counts(syms, 256)
+    table = lr.rans_tables_build(counts, K)
+    params = lr.rans_params.make(K, R, L, W, N, C)
+    d_in = torch.from_numpy(syms).cuda()
+    cap = lr.rans_encode_bound(n, params)
+    d_cont = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    clen = lr.rans_encode(table, params, d_in, n, d_cont, cap)
+    hdr = bytes(d_cont[:32].cpu().numpy().tobytes())
+    vals = (torch.arange(256, dtype=torch.float32) - 128.0) / 64.0
+    lut2 = vals.to(torch.bfloat16).cuda()
+    lut4 = vals.cuda()
+    out2 = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    out4 = torch.empty(n, dtype=torch.float32, device="cuda")
+    codes = torch.empty(n, dtype=torch.uint8, device="cuda")
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    out_u = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+
+    def fused2():
+        lr.rans_decode_lut_async(table, d_cont, clen, hdr, lut2, 2, out2, n, st[0:1])
+
+    def fused4():
+        lr.rans_decode_lut_async(table, d_cont, clen, hdr, lut4, 4, out4, n, st[1:2])
+
+    def decode():
+        lr.rans_decode_async(table, d_cont, clen, hdr, codes, n, st[2:3])
+
+    def gather():
+        torch.index_select(lut2, 0, idx.copy_(codes), out=out_u)
+
+    def unfused():
+        decode()
+        gather()
+
+    def copy():  # device copy of the bf16 output: 2n bytes read, 2n written
+        out_u.copy_(out2)
+
+    reps = max(5, args.steps)
+    res = {}
+    for name, fn in [("fused_bf16", fused2), ("fused_fp32", fused4), ("decode_codes", decode),
+                     ("gather", gather), ("unfused_bf16", unfused), ("copy_bf16", copy)]:
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = timed(fn, reps)
+        log(f"{name}: {res[name] * 1e6:.1f} us")
+    assert int(st.abs().sum()) == 0, f"status {st.tolist()}"
+    ref = lut2[d_in.long()]
+    assert torch.equal(out2.view(torch.int16), ref.view(torch.int16)), "fused bf16 output"
+    assert torch.equal(out4, lut4[d_in.long()]), "fused fp32 output"
+    assert torch.equal(out_u.view(torch.int16), ref.view(torch.int16)), "unfused output"
+    t = res["fused_bf16"]
+    alg = clen + 2 * n + 2 * 256 + 8 * (1 << K)
+    # the best a separate gather pass could do: n bytes of codes in, 2n out,
+    # at the rate of a plain device copy
+    copy_rate = 4 * n / res["copy_bf16"]
+    unfused_bound = res["decode_codes"] + 3 * n / copy_rate
+    out = base_result("rANS decode fused with a codebook lookup, GB/s of codes", round(n / t / 1e9, 2),
+                      "GB/s", args,
+                      {"workload": f"{n >> 20} MiB of 8-bit codes, discretised normal (sigma 24 codes), "
+                                   f"M=2^{K}, b=L=2^16, N=64, 64 KiB chunks, bf16 codebook"})
+    out.update({
+        "fused_bf16_us": round(t * 1e6, 1),
+        "fused_fp32_us": round(res["fused_fp32"] * 1e6, 1),
+        "unfused_bf16_us": round(res["unfused_bf16"] * 1e6, 1),
+        "decode_codes_us": round(res["decode_codes"] * 1e6, 1),
+        "gather_us": round(res["gather"] * 1e6, 1),
+        "fused_speedup": round(res["unfused_bf16"] / t, 3),
+        "unfused_bound_us": round(unfused_bound * 1e6, 1),
+        "fused_speedup_vs_bound": round(unfused_bound / t, 3),
+        "copy_gbps": round(copy_rate / 1e9, 1),
+        "unfused_note": "gather = torch index_select after a uint8->int32 index copy; "
+                        "bound = decode + 3 bytes per code at the device-copy rate",
+        "compression_ratio": round(clen / n, 4),
+        "roofline": {"bound": "hbm", "kernel": "k_decode64 (LUT output)", "unit": "GB/s",
+                     "achieved": round(alg / t / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "frac": round(alg / t / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None},
+    })
+    print(json.dumps(out), flush=True)
+
+
 def run_serving(args):
     """Request loop: Poisson arrivals of mixed encode/decode requests under an
     8 GiB HBM budget, rates swept around the saturated throughput; p50/p99
@@ -474,7 +572,8 @@ def main():
         copy_probe()
         return
     if args.workload != "roundtrip":
-        {"batched": run_batched, "sweep": run_sweep, "serving": run_serving}[args.workload](args)
+        {"batched": run_batched, "sweep": run_sweep, "serving": run_serving,
+         "dequant": run_dequant}[args.workload](args)
         return
 
     import numpy as np

@@ -45,6 +45,21 @@ def near_uniform_probs(n: int, rng: np.random.Generator) -> np.ndarray:
     return p / p.sum()
 
 
+def gaussian_codes_probs(n: int = 256, sigma: float = 24.0) -> np.ndarray:
+    """8-bit quantisation codes of normally distributed values (a symmetric
+    weight tensor quantised to n levels around n/2): p_c is the normal mass
+    of [c - 0.5, c + 0.5) about n/2 with standard deviation sigma (in code
+    steps), the two end codes taking the tails."""
+    c = np.arange(n, dtype=np.float64)
+    lo = (c - 0.5 - n / 2) / (sigma * math.sqrt(2.0))
+    hi = (c + 0.5 - n / 2) / (sigma * math.sqrt(2.0))
+    erf = np.vectorize(math.erf)
+    p = 0.5 * (erf(hi) - erf(lo))
+    p[0] += 0.5 * (1.0 + math.erf(lo[0]))
+    p[-1] += 0.5 * (1.0 - math.erf(hi[-1]))
+    return p / p.sum()
+
+
 def entropy_bits(p: np.ndarray) -> float:
     p = np.asarray(p, dtype=np.float64)
     p = p[p > 0]

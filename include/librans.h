@@ -176,6 +176,27 @@ int rans_decode_async(const rans_table *table, const void *d_in, uint64_t in_len
                       const void *h_header, void *d_syms, uint64_t syms_cap, int32_t *d_status,
                       void *stream);
 
+/* Decode fused with a table-lookup consumer (Section 6: the decoder is small
+ * enough to be fused into the kernel that uses its output).  Output element
+ * i is d_lut[symbol i]: lut_bytes (2 or 4) bytes copied bit for bit, e.g. the
+ * bf16 / fp16 / fp32 value of a codebook index when a tensor was stored as
+ * entropy-coded codes.  The symbols themselves never reach memory.
+ *   d_lut   device, the table's alphabet entries of lut_bytes each, aligned
+ *           to lut_bytes; read once per block into LDS.
+ *   d_out   device, out_cap elements of lut_bytes, 16-byte aligned.
+ * Needs a container with N = 32 or 64 and chunk_syms * lut_bytes a multiple
+ * of 16 (the one-wave-per-chunk kernels), else RANS_EINVAL.  *n_syms, errors
+ * and blocking as rans_decode (RANS_ENOSPC when out_cap < n). */
+int rans_decode_lut(const rans_table *table, const void *d_in, uint64_t in_len, const void *d_lut,
+                    uint32_t lut_bytes, void *d_out, uint64_t out_cap, uint64_t *n_syms,
+                    void *stream);
+
+/* Stream-ordered form of rans_decode_lut; h_header and d_status as for
+ * rans_decode_async. */
+int rans_decode_lut_async(const rans_table *table, const void *d_in, uint64_t in_len,
+                          const void *h_header, const void *d_lut, uint32_t lut_bytes, void *d_out,
+                          uint64_t out_cap, int32_t *d_status, void *stream);
+
 /* One stream of a batch.  `table` is a host handle; every other pointer is
  * device memory.  Encode: in = symbols, in_len = their count in BYTES
  * (a multiple of sym_bytes), out = container buffer of out_cap bytes,

@@ -109,6 +109,11 @@ _sig = {
                                      ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "rans_decode_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_char_p,
                                      ct.c_void_p, ct.c_uint64, ct.c_void_p, ct.c_void_p]),
+    "rans_decode_lut": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_void_p, ct.c_uint32,
+                                   ct.c_void_p, ct.c_uint64, _u64p, ct.c_void_p]),
+    "rans_decode_lut_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_char_p,
+                                         ct.c_void_p, ct.c_uint32, ct.c_void_p, ct.c_uint64,
+                                         ct.c_void_p, ct.c_void_p]),
     "rans_encode_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_void_p]),
     "rans_decode_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_void_p]),
     "rans_strerror": (ct.c_char_p, [ct.c_int]),
@@ -278,6 +283,26 @@ def rans_decode_async(table: Table, d_in, in_len: int, header: bytes, d_syms, sy
     hb = bytes(header[:32])
     _check(_lib.rans_decode_async(table.handle, _ptr(d_in), in_len, hb, _ptr(d_syms), syms_cap,
                                   _ptr(d_status), _stream(stream)), "rans_decode_async")
+
+
+def rans_decode_lut(table: Table, d_in, in_len: int, d_lut, lut_bytes: int, d_out, out_cap: int,
+                    stream=None) -> int:
+    """Decode fused with a lookup: d_out[i] = d_lut[symbol i] (lut_bytes = 2 or 4 bytes per
+    element); returns the element count."""
+    n = ct.c_uint64()
+    rc = _lib.rans_decode_lut(table.handle, _ptr(d_in), in_len, _ptr(d_lut), lut_bytes, _ptr(d_out),
+                              out_cap, ct.byref(n), _stream(stream))
+    _check(rc, "rans_decode_lut")
+    return int(n.value)
+
+
+def rans_decode_lut_async(table: Table, d_in, in_len: int, header: bytes, d_lut, lut_bytes: int,
+                          d_out, out_cap: int, d_status, stream=None):
+    """Stream-ordered rans_decode_lut given a host copy of the 32-byte header."""
+    hb = bytes(header[:32])
+    _check(_lib.rans_decode_lut_async(table.handle, _ptr(d_in), in_len, hb, _ptr(d_lut), lut_bytes,
+                                      _ptr(d_out), out_cap, _ptr(d_status), _stream(stream)),
+           "rans_decode_lut_async")
 
 
 # ---------------------------------------------------------------- batches --

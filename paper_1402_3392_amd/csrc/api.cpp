@@ -102,24 +102,25 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     return RANS_OK;
 }
 
-bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds)
+bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra)
 {
     const uint64_t maxl = static_cast<uint64_t>(max_lds_bytes());
-    const uint64_t packed = t.dec_bytes + t.sym_bytes, two = t.sym_bytes + t.fc_bytes;
+    const uint64_t packed = t.dec_bytes + t.sym_bytes + extra, two = t.sym_bytes + t.fc_bytes + extra;
     // One LDS read per symbol when the fused table leaves room for 16 waves'
     // rings; else the packed table (two independent reads) while it leaves
-    // room for a second block; else the small two-level table.
-    if (t.fused && t.fused_bytes + 16 * decode64_lds_per_wave(kFused) <= maxl) {
+    // room for a second block; else the small two-level table with room for
+    // at least one wave.  `extra`: LDS the kernel stages beside the table.
+    if (t.fused && t.fused_bytes + extra + 16 * decode64_lds_per_wave(kFused) <= maxl) {
         *layout = kFused;
-        *lds = static_cast<uint32_t>(t.fused_bytes);
+        *lds = static_cast<uint32_t>(t.fused_bytes + extra);
         return true;
     }
-    if (packed <= maxl && packed <= 96 * 1024) {
+    if (packed + decode64_lds_per_wave(kPacked) <= maxl && packed <= 96 * 1024) {
         *layout = kPacked;
         *lds = static_cast<uint32_t>(packed);
         return true;
     }
-    if (two <= maxl) {
+    if (two + decode64_lds_per_wave(kTwoLevel) <= maxl) {
         *layout = kTwoLevel;
         *lds = static_cast<uint32_t>(two);
         return true;
@@ -321,6 +322,8 @@ static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const
 static hipError_t enqueue_decode(const DecodeArgs& da, int R, int W, Layout layout, hipStream_t st)
 {
     TimingScope ts(RANS_KERNEL_DECODE, st);
+    if (da.lut_w)
+        return launch_decode64_lut(da, R, layout, st);
     return fast64(da.N, da.C, W, da.out) ? launch_decode64(da, R, W, layout, st)
                                          : launch_decode(da, R, W, layout, st);
 }
@@ -402,10 +405,13 @@ extern "C" int rans_encode(const rans_table* table, const rans_params* params, c
     return code;
 }
 
-// Validates a decode call against a host copy of the header.
+// Validates a decode call against a host copy of the header.  lut_w != 0:
+// the fused lookup variant (output element i = d_lut[symbol i], lut_w
+// bytes; the one-wave-per-chunk kernels only).
 static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in_len,
                           const uint8_t* h_header, void* d_syms, uint64_t syms_cap,
-                          DecodeArgs* da, Header* h, Layout* layout)
+                          DecodeArgs* da, Header* h, Layout* layout, const void* d_lut = nullptr,
+                          uint32_t lut_w = 0)
 {
     int rc = parse_header(h_header, in_len, h);
     if (rc != RANS_OK)
@@ -413,14 +419,23 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     const DevTable& t = *dev_table(table);
     if (t.k != h->p.prob_bits)
         return RANS_EINVAL;
-    if (h->p.sym_bytes == 1 && t.sym_w != 1)
-        return RANS_EINVAL;
-    if (h->n > syms_cap)
-        return RANS_ENOSPC;
-    if (h->n && (!d_syms || (reinterpret_cast<uintptr_t>(d_syms) & (h->p.sym_bytes - 1))))
-        return RANS_EINVAL;
+    if (lut_w == 0) {
+        if (h->p.sym_bytes == 1 && t.sym_w != 1)
+            return RANS_EINVAL;
+        if (h->n > syms_cap)
+            return RANS_ENOSPC;
+        if (h->n && (!d_syms || (reinterpret_cast<uintptr_t>(d_syms) & (h->p.sym_bytes - 1))))
+            return RANS_EINVAL;
+    } else {
+        if ((lut_w != 2 && lut_w != 4) || !d_lut || (reinterpret_cast<uintptr_t>(d_lut) & (lut_w - 1)))
+            return RANS_EINVAL;
+        if (h->n > syms_cap)
+            return RANS_ENOSPC;
+        if (h->n && (!d_syms || !fast64(h->p.interleave, h->p.chunk_syms, lut_w, d_syms)))
+            return RANS_EINVAL;
+    }
     uint32_t lds;
-    if (!choose_layout(t, layout, &lds))
+    if (!choose_layout(t, layout, &lds, lut_w ? lut_lds_bytes(t.alphabet, lut_w) : 0))
         return RANS_EINVAL;
     *da = DecodeArgs{};
     da->in = static_cast<const uint8_t*>(d_in);
@@ -435,13 +450,16 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     da->l = h->p.state_lbits;
     da->alphabet = t.alphabet;
     da->bf = h->p.digit_order;
+    da->lut = d_lut;
+    da->lut_w = lut_w;
     fill_decode_tables(t, *layout, da);
     return RANS_OK;
 }
 
-extern "C" int rans_decode_async(const rans_table* table, const void* d_in, uint64_t in_len,
-                                 const void* h_header, void* d_syms, uint64_t syms_cap,
-                                 int32_t* d_status, void* stream)
+// Shared body of the stream-ordered decodes.
+static int decode_async(const rans_table* table, const void* d_in, uint64_t in_len,
+                        const void* h_header, void* d_out, uint64_t cap, const void* d_lut,
+                        uint32_t lut_w, int32_t* d_status, void* stream)
 {
     if (!table || !d_in || !h_header || !d_status)
         return RANS_EINVAL;
@@ -452,8 +470,8 @@ extern "C" int rans_decode_async(const rans_table* table, const void* d_in, uint
     DecodeArgs da;
     Header h;
     Layout layout;
-    int rc = prepare_decode(table, d_in, in_len, static_cast<const uint8_t*>(h_header), d_syms,
-                            syms_cap, &da, &h, &layout);
+    int rc = prepare_decode(table, d_in, in_len, static_cast<const uint8_t*>(h_header), d_out, cap,
+                            &da, &h, &layout, d_lut, lut_w);
     if (rc != RANS_OK || h.n == 0)
         return rc;
     da.status = d_status;
@@ -463,8 +481,9 @@ extern "C" int rans_decode_async(const rans_table* table, const void* d_in, uint
                : RANS_EDEVICE;
 }
 
-extern "C" int rans_decode(const rans_table* table, const void* d_in, uint64_t in_len, void* d_syms,
-                           uint64_t syms_cap, uint64_t* n_syms, void* stream)
+// Shared body of the synchronous decodes (header read back, status read back).
+static int decode_sync(const rans_table* table, const void* d_in, uint64_t in_len, void* d_out,
+                       uint64_t cap, const void* d_lut, uint32_t lut_w, uint64_t* n_syms, void* stream)
 {
     if (!table || !d_in || !n_syms)
         return RANS_EINVAL;
@@ -489,7 +508,7 @@ extern "C" int rans_decode(const rans_table* table, const void* d_in, uint64_t i
     DecodeArgs da;
     Header h;
     Layout layout;
-    rc = prepare_decode(table, d_in, in_len, hdr, d_syms, syms_cap, &da, &h, &layout);
+    rc = prepare_decode(table, d_in, in_len, hdr, d_out, cap, &da, &h, &layout, d_lut, lut_w);
     if (rc == RANS_OK || rc == RANS_ENOSPC)
         *n_syms = h.n;
     if (rc != RANS_OK || h.n == 0)
@@ -508,4 +527,36 @@ extern "C" int rans_decode(const rans_table* table, const void* d_in, uint64_t i
     int32_t code;
     std::memcpy(&code, ws->host, 4);
     return code;
+}
+
+extern "C" int rans_decode_async(const rans_table* table, const void* d_in, uint64_t in_len,
+                                 const void* h_header, void* d_syms, uint64_t syms_cap,
+                                 int32_t* d_status, void* stream)
+{
+    return decode_async(table, d_in, in_len, h_header, d_syms, syms_cap, nullptr, 0, d_status, stream);
+}
+
+extern "C" int rans_decode(const rans_table* table, const void* d_in, uint64_t in_len, void* d_syms,
+                           uint64_t syms_cap, uint64_t* n_syms, void* stream)
+{
+    return decode_sync(table, d_in, in_len, d_syms, syms_cap, nullptr, 0, n_syms, stream);
+}
+
+extern "C" int rans_decode_lut_async(const rans_table* table, const void* d_in, uint64_t in_len,
+                                     const void* h_header, const void* d_lut, uint32_t lut_bytes,
+                                     void* d_out, uint64_t out_cap, int32_t* d_status, void* stream)
+{
+    if (lut_bytes == 0)
+        return RANS_EINVAL;
+    return decode_async(table, d_in, in_len, h_header, d_out, out_cap, d_lut, lut_bytes, d_status,
+                        stream);
+}
+
+extern "C" int rans_decode_lut(const rans_table* table, const void* d_in, uint64_t in_len,
+                               const void* d_lut, uint32_t lut_bytes, void* d_out, uint64_t out_cap,
+                               uint64_t* n_syms, void* stream)
+{
+    if (lut_bytes == 0)
+        return RANS_EINVAL;
+    return decode_sync(table, d_in, in_len, d_out, out_cap, d_lut, lut_bytes, n_syms, stream);
 }

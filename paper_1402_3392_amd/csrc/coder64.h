@@ -125,16 +125,28 @@ __device__ __forceinline__ void stage2(uint8_t* lds, const void* a, uint32_t aby
 // wave_lds_bytes(LAYOUT) bytes.  Every argument must be wave-uniform.  When
 // it returns, every load it issued has completed, so wave_lds can be reused.
 // BF: the chunk's digits are in breadth-first order (Section 5; only byte
-// digits can differ from depth-first).
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false>
+// digits can differ from depth-first).  LW = 2 or 4: a consumer fused into
+// the decoder -- output element i is l_lut[symbol i] (LW bytes, staged in
+// LDS), so the symbols never reach memory; W is then irrelevant.
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false, int LW = 0>
 __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                              uint64_t chunk, uint32_t C, uint64_t n, void* out_base,
                                              uint32_t k_, uint32_t l, const void* l_sym_v,
                                              const uint32_t* l_ent, uint8_t* wave_lds,
-                                             int32_t* status)
+                                             int32_t* status, const void* l_lut = nullptr)
 {
     using SymT = typename std::conditional<SW == 1, uint8_t, uint16_t>::type;
-    using OutT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
+    using SymOutT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
+    using LutT = typename std::conditional<LW == 4, uint32_t, uint16_t>::type;
+    using OutT = typename std::conditional<LW == 0, SymOutT, LutT>::type;
+    constexpr uint32_t OW = sizeof(OutT);  // output bytes per symbol
+    const LutT* lut = static_cast<const LutT*>(l_lut);
+    // what a decoded symbol becomes in the output
+    auto emit = [&](uint32_t s) -> OutT {
+        if (LW == 0)
+            return static_cast<OutT>(s);
+        return static_cast<OutT>(lut[s]);
+    };
     const SymT* l_sym = static_cast<const SymT*>(l_sym_v);
     const uint32_t lane = threadIdx.x & 63;
     constexpr uint32_t OB = obuf_bytes(LAYOUT);
@@ -231,7 +243,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     if (!live)
         x = L;  // idle lanes stay at L and never refill
 
-    constexpr uint32_t SPB = OB / (NL * W);    // steps per output block
+    constexpr uint32_t SPB = OB / (NL * OW);   // steps per output block
     constexpr uint32_t PIECE = OB / 64;         // bytes each lane moves per block
     constexpr uint32_t DB = R / 8;                 // bytes per digit
     constexpr uint32_t DMASK = S * kWin / DB - 1;  // ring size in digits, minus 1
@@ -323,7 +335,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         decode_one(s);
         refill(live, dense);
         if (live)
-            *dst = static_cast<OutT>(s);
+            *dst = emit(s);
     };
     // TB full steps; t is a multiple of TB here (and TB divides SPB), so the
     // output offsets are immediates and an output block ends on a test block
@@ -350,7 +362,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             decode_one(s);
         refill(act, std::false_type{});
         if (live)
-            ob[(t & (SPB - 1)) * NL] = static_cast<OutT>(s);
+            ob[(t & (SPB - 1)) * NL] = emit(s);
         ++t;
     };
     // A step reads at most 2 NL <= 128 digit bytes, so TB steps that start
@@ -419,7 +431,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     const uint32_t tb = (full / SPB) * SPB;
     lane_fence();
     if (tb < steps) {
-        const uint32_t nbytes = (nsym - tb * NL) * W;  // valid bytes of this block
+        const uint32_t nbytes = (nsym - tb * NL) * OW;  // valid bytes of this block
         uint8_t* dst = reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL);
         if (PIECE * lane + PIECE <= nbytes) {
             *reinterpret_cast<Piece*>(dst + PIECE * lane) = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);

@@ -1,0 +1,119 @@
+// Single-buffer decode kernel for N = 32 or 64 interleaved coders: one wave
+// per chunk, tables staged in LDS once per block; the chunk coder itself is
+// c64::decode_chunk.  LW = 0 writes the symbols; LW = 2 or 4 writes
+// lut[symbol] (a consumer fused into the decoder).  Included by the
+// translation units that instantiate each output kind.
+#pragma once
+
+#include "coder64.h"
+
+namespace rans {
+namespace {
+
+// Copies `count` LUT elements of T to LDS (element-wise: the caller's buffer
+// holds exactly count elements).
+template <typename T>
+__device__ __forceinline__ void stage_lut(uint8_t* lds, const void* src, uint32_t count)
+{
+    const T* s = static_cast<const T*>(src);
+    T* d = reinterpret_cast<T*>(lds);
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x)
+        d[i] = s[i];
+}
+
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW>
+__global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    // symbol map first (small immediate offsets), then the entries; the
+    // fused layout has no separate symbol map
+    const void* symsrc = LAYOUT == kPacked ? a.tab1 : (LAYOUT == kFused ? nullptr : a.tab0);
+    const void* ent = LAYOUT == kPacked ? a.tab0 : (LAYOUT == kFused ? a.tab0 : a.tab1);
+    const uint32_t sym_bytes = LAYOUT == kPacked ? a.tab1_bytes : (LAYOUT == kFused ? 0 : a.tab0_bytes);
+    const uint32_t ent_bytes = LAYOUT == kPacked ? a.tab0_bytes : (LAYOUT == kFused ? a.tab0_bytes : a.tab1_bytes);
+    // the waves' rings and output blocks first (low LDS addresses for the
+    // direct-to-LDS loads), the tables after them, then the LUT
+    uint8_t* tab = lds + c64::uni(blockDim.x >> 6) * c64::wave_lds_bytes(LAYOUT);
+    uint8_t* lut = tab + sym_bytes + ent_bytes;
+    c64::stage2(tab, symsrc, sym_bytes, ent, ent_bytes);
+    if (LW == 2)
+        stage_lut<uint16_t>(lut, a.lut, a.alphabet);
+    else if (LW == 4)
+        stage_lut<uint32_t>(lut, a.lut, a.alphabet);
+    __syncthreads();
+    // wave-uniform by construction; readfirstlane lets the compiler keep
+    // everything derived from it in SGPRs
+    const uint32_t wave = c64::uni(threadIdx.x >> 6);
+    const uint64_t chunk = uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
+    if (chunk >= a.n_chunks)
+        return;  // no barrier follows
+    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, LW>(
+        a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, tab,
+        reinterpret_cast<const uint32_t*>(tab + sym_bytes), lds + wave * c64::wave_lds_bytes(LAYOUT),
+        a.status, lut);
+}
+
+// Waves per block: 16 when the tables leave room for them, fewer otherwise.
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW>
+hipError_t run(const DecodeArgs& a, hipStream_t st)
+{
+    const uint32_t tabs = a.tab0_bytes + a.tab1_bytes + lut_lds_bytes(a.alphabet, LW);
+    const uint32_t per = c64::wave_lds_bytes(LAYOUT);
+    const uint32_t maxl = static_cast<uint32_t>(max_lds_bytes());
+    const uint32_t fit = tabs + per <= maxl ? (maxl - tabs) / per : 0;
+    if (fit == 0)
+        return hipErrorInvalidValue;
+    uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
+    wpb = wpb < fit ? wpb : fit;
+    const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
+    const uint32_t lds = tabs + wpb * per;
+    auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF, LW>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int R, int W, int SW, int LAYOUT, bool BF, int LW>
+hipError_t run_n(const DecodeArgs& a, hipStream_t st)
+{
+    return a.N == 32 ? run<R, W, SW, LAYOUT, 32, BF, LW>(a, st) : run<R, W, SW, LAYOUT, 64, BF, LW>(a, st);
+}
+
+template <int R, int W, int SW, bool BF, int LW>
+hipError_t run_l(const DecodeArgs& a, Layout layout, hipStream_t st)
+{
+    if (SW == 1 && layout == kFused)
+        return run_n<R, W, 1, kFused, BF, LW>(a, st);
+    return layout == kPacked ? run_n<R, W, SW, kPacked, BF, LW>(a, st)
+                             : run_n<R, W, SW, kTwoLevel, BF, LW>(a, st);
+}
+
+template <int R, bool BF, int LW>
+hipError_t run_w(const DecodeArgs& a, int W, Layout layout, hipStream_t st)
+{
+    const bool wide_map = a.alphabet > 256;  // u16 slot -> symbol map
+    if constexpr (LW != 0) {
+        // the output is lut[symbol]: only the symbol map's width matters
+        (void)W;
+        return wide_map ? run_l<R, 1, 2, BF, LW>(a, layout, st) : run_l<R, 1, 1, BF, LW>(a, layout, st);
+    } else {
+        if (W == 1)  // 8-bit symbols come from tables of at most 256 symbols
+            return run_l<R, 1, 1, BF, LW>(a, layout, st);
+        return wide_map ? run_l<R, 2, 2, BF, LW>(a, layout, st) : run_l<R, 2, 1, BF, LW>(a, layout, st);
+    }
+}
+
+template <int LW>
+hipError_t run_r(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t st)
+{
+    // 16-bit digits: one digit per step at most (b >= M), both orders coincide
+    if (R == 16)
+        return run_w<16, false, LW>(a, W, layout, st);
+    return a.bf ? run_w<8, true, LW>(a, W, layout, st) : run_w<8, false, LW>(a, W, layout, st);
+}
+
+}  // namespace
+}  // namespace rans

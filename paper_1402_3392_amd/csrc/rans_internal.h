@@ -57,6 +57,8 @@ struct DecodeArgs {
     uint32_t k, l;
     uint32_t alphabet;
     uint32_t bf;         // breadth-first digit order (Section 5)
+    const void* lut;     // fused consumer: alphabet entries of lut_w bytes (device)
+    uint32_t lut_w;      // 0 (symbol output), 2 or 4
     const void* tab0;    // kPacked: dec; kTwoLevel: sym
     const void* tab1;    // kPacked: sym; kTwoLevel: fc
     uint32_t tab0_bytes, tab1_bytes;  // multiples of 16
@@ -179,6 +181,10 @@ hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hip
 hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
                                  hipStream_t stream);
 uint32_t decode64_lds_per_wave(Layout layout);
+// Decode fused with a table lookup: out[i] = lut[symbol i] (a.lut, a.lut_w).
+hipError_t launch_decode64_lut(const DecodeArgs& a, int R, Layout layout, hipStream_t stream);
+// LDS bytes of a staged lookup table of `alphabet` entries of lw bytes.
+inline uint32_t lut_lds_bytes(uint32_t alphabet, int lw) { return (alphabet * uint32_t(lw) + 15) & ~15u; }
 // LDS per wave of the one-wave-per-chunk encoder: 1 KiB symbol block, 4 KiB
 // digit ring, 128 bytes for the writes of lanes with nothing to emit.
 constexpr uint32_t kEncWaveLdsBytes = 5248;

@@ -61,7 +61,7 @@ uint32_t max_digits(uint32_t k, uint32_t r);
 uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r);
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch);
 int parse_header(const uint8_t* h, uint64_t in_len, Header* out);
-bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds);
+bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra = 0);
 int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
               bool decode, const rans_batch_config* cfg_override);
 rans_batch_config batch_config();
