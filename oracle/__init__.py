@@ -82,6 +82,10 @@ def _bind(lib):
                                u64p, i32]
     lib.orc_encode_order.argtypes = [u32p, u32, u32, u32, u32, u32, u32, u32, i32, u8p, u64, u8p,
                                      u64, u64p, i32]
+    lib.orc_encode_flags.argtypes = [u32p, u32, u32, u32, u32, u32, u32, u32, i32, u8p, u64, u8p,
+                                     u64, u64p, i32]
+    lib.orc_encode_bound_raw.argtypes = [u64, u32, u32, u32, u32, u32]
+    lib.orc_encode_bound_raw.restype = u64
     lib.orc_decode.argtypes = [u32p, u32, u8p, u64, u8p, u64, u64p, i32]
     lib.orc_header.argtypes = [u8p, u64, u64p]
     return lib
@@ -178,36 +182,41 @@ def encode_bound(n: int, k: int, r: int, N: int, C: int) -> int:
 
 
 def encode(f, syms: np.ndarray, k: int, r: int, l: int, N: int, C: int,
-           threads: int = 1, order: str = "df") -> np.ndarray:
+           threads: int = 1, order: str = "df", escape: bool = False) -> np.ndarray:
     """Encodes a symbol array (uint8 or uint16) into a container (uint8 array).
     order: digit order of the chunk streams, 'df' depth-first or 'bf'
-    breadth-first (Section 5), recorded in header byte 9."""
+    breadth-first (Section 5).  escape: escape coding with raw digits
+    (uint16 symbols, depth-first; the last symbol of f is the escape).  Both
+    are recorded in header byte 9."""
     f = _u32(f)
     syms = np.ascontiguousarray(syms)
     w = syms.dtype.itemsize
     if syms.dtype not in (np.uint8, np.uint16):
         raise ValueError("symbols must be uint8 or uint16")
     n = syms.size
-    cap = encode_bound(n, k, r, N, C)
+    nraw = (8 * w + r - 1) // r if escape else 0
+    cap = int(_load().orc_encode_bound_raw(n, k, r, N, C, nraw))
     out = np.zeros(cap, dtype=np.uint8)
     olen = ct.c_uint64()
     raw = syms.view(np.uint8).reshape(-1) if n else np.zeros(1, dtype=np.uint8)
     if order not in ("df", "bf"):
         raise ValueError("order must be 'df' or 'bf'")
-    rc = _load().orc_encode_order(_p(f, ct.c_uint32), len(f), k, r, l, w, N, C,
-                                  1 if order == "bf" else 0, _p(raw, ct.c_uint8), n,
-                                  _p(out, ct.c_uint8), cap, ct.byref(olen), threads)
+    flags = (1 if order == "bf" else 0) | (2 if escape else 0)
+    rc = _load().orc_encode_flags(_p(f, ct.c_uint32), len(f), k, r, l, w, N, C, flags,
+                                  _p(raw, ct.c_uint8), n, _p(out, ct.c_uint8), cap,
+                                  ct.byref(olen), threads)
     _check(rc, "encode")
     return out[:olen.value]
 
 
 def header(container: np.ndarray) -> dict:
     buf = np.ascontiguousarray(container, dtype=np.uint8)
-    h = np.zeros(9, dtype=np.uint64)
+    h = np.zeros(10, dtype=np.uint64)
     _check(_load().orc_header(_p(buf, ct.c_uint8), buf.size, _p(h, ct.c_uint64)), "header")
-    keys = ("k", "r", "l", "w", "N", "C", "n", "n_chunks", "order")
+    keys = ("k", "r", "l", "w", "N", "C", "n", "n_chunks", "order", "nraw")
     d = {kk: int(v) for kk, v in zip(keys, h)}
     d["order"] = "bf" if d["order"] else "df"
+    d["escape"] = d["nraw"] > 0
     return d
 
 

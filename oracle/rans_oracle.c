@@ -41,8 +41,14 @@
  *       involves coders 0 .. (len mod N)-1; idle coders keep state L.
  *   Q8  container: 32-byte header, chunk directory, chunk streams at 16-byte
  *       aligned offsets with zero padding (layout in orc_encode).  Header
- *       byte 9 names the digit order of the chunk streams: 0 depth-first,
- *       1 breadth-first (Section 5); the two coincide when b >= M.
+ *       byte 9 holds flags: bit 0 breadth-first digit order (Section 5; the
+ *       two orders coincide when b >= M), bit 1 escape coding (Q16).
+ *   Q16 raw digits (Section 3 says raw data can be mixed into an ANS stream
+ *       at agreed points): escape coding of 16-bit symbols.  The model's
+ *       last symbol E is an escape; a value v is coded as symbol v when
+ *       v < E and f_v > 0, else as E followed by 16/r raw digits holding v
+ *       (most significant first); in each coder's share of a step the raw
+ *       digits follow the renormalisation digits; depth-first order only.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -463,6 +469,85 @@ out:
     return rc;
 }
 
+/* Escape coding with raw digits (Section 3: because decoder and encoder run
+ * in lockstep, an encoder may put raw digits into the stream at any point
+ * both sides agree on, with no bypass mechanism).  The model's last symbol
+ * E = n - 1 is the escape: a value v is coded as the symbol v when v < E and
+ * f_v > 0, and otherwise as E plus nraw raw digits that hold v, most
+ * significant first in stream order.  The encoder sends the raw digits just
+ * before it encodes the escape, so the decoder reads them just after it has
+ * decoded the escape and renormalised: per coder and step the stream holds
+ * the symbol's renormalisation digits, then its raw digits.  Depth-first
+ * order, coders ascending (reading Q16). */
+static int encode_esc(const model_t *m, const geom_t *g, uint32_t nraw, const uint32_t *vals,
+                      uint64_t len, uint64_t *states, uint32_t *digits, uint64_t cap,
+                      uint64_t *start)
+{
+    uint64_t i, pos = cap;
+    uint32_t j, q, E = m->n - 1;
+    int rc;
+    for (j = 0; j < g->N; j++)
+        states[j] = g->L; /* reading Q3 */
+    for (i = len; i-- > 0;) {
+        uint32_t v = vals[i], s = v;
+        j = (uint32_t)(i % g->N);
+        if (v >= E || m->f[v] == 0) {
+            uint64_t rest = v;
+            for (q = 0; q < nraw; q++) { /* least significant digit is prepended first */
+                if (pos == 0)
+                    return ORC_ENOSPC;
+                digits[--pos] = (uint32_t)(rest % g->b);
+                rest /= g->b;
+            }
+            s = E;
+        }
+        rc = encode_symbol(m, g, s, &states[j], digits, &pos);
+        if (rc != ORC_OK)
+            return rc;
+    }
+    *start = pos;
+    return ORC_OK;
+}
+
+static int decode_esc(const model_t *m, const geom_t *g, uint32_t nraw, const uint64_t *states_in,
+                      const uint32_t *dig, uint64_t ndig, uint32_t *vals, uint64_t len)
+{
+    uint64_t *x, i, rd = 0;
+    uint32_t j, q, s, E = m->n - 1;
+    int rc = ORC_OK;
+    x = (uint64_t *)malloc(sizeof(uint64_t) * g->N);
+    if (!x)
+        return ORC_ENOMEM;
+    memcpy(x, states_in, sizeof(uint64_t) * g->N);
+    for (i = 0; i < len; i++) {
+        j = (uint32_t)(i % g->N);
+        rc = decode_symbol(m, g, &x[j], dig, ndig, &rd, &s);
+        if (rc != ORC_OK)
+            goto out;
+        if (s == E) {
+            uint64_t v = 0;
+            for (q = 0; q < nraw; q++) {
+                if (rd >= ndig) {
+                    rc = ORC_ECORRUPT;
+                    goto out;
+                }
+                v = v * g->b + dig[rd++];
+            }
+            vals[i] = (uint32_t)v;
+        } else {
+            vals[i] = s;
+        }
+    }
+    for (j = 0; j < g->N; j++)
+        if (x[j] != g->L)
+            rc = ORC_ECORRUPT;
+    if (rd != ndig)
+        rc = ORC_ECORRUPT;
+out:
+    free(x);
+    return rc;
+}
+
 /* Digit-level entry points (tests).  order: 0 = depth-first, 1 = breadth-
  * first.  digits: caller buffer of cap entries; on success the stream is
  * moved to digits[0 .. *ndigits).  trace (optional, len entries): state of
@@ -519,7 +604,8 @@ int orc_decode_digits(const uint32_t *f, uint32_t n, uint32_t k, uint32_t r, uin
 /* Container (reading Q8), all fields little-endian:
  *   header, 32 bytes:
  *     0: u32 magic   4: u8 version=1   5: u8 k   6: u8 r   7: u8 l
- *     8: u8 w (symbol bytes)   9: u8 0   10: u16 N   12: u32 C (symbols per
+ *     8: u8 w (symbol bytes)   9: u8 flags (bit 0 breadth-first digit order,
+ *     bit 1 escape coding, not both; reading Q16)   10: u16 N   12: u32 C (symbols per
  *     chunk)   16: u64 n (symbols)   24: u32 n_chunks = ceil(n/C)   28: u32 0
  *   directory at 32: n_chunks entries {u64 offset, u32 length, u32 0}
  *   chunk streams at 16-byte aligned offsets, zero padding in between;
@@ -568,7 +654,9 @@ static int check_container_params(uint32_t k, uint32_t r, uint32_t l, uint32_t w
  * at most ceil(k/r) divisions by b. */
 static uint64_t max_digits_per_symbol(uint32_t k, uint32_t r) { return (k + r - 1) / r; }
 
-uint64_t orc_encode_bound(uint64_t nsyms, uint32_t k, uint32_t r, uint32_t N, uint32_t C)
+/* nraw: raw digits an escaped symbol adds (0 without escape coding). */
+uint64_t orc_encode_bound_raw(uint64_t nsyms, uint32_t k, uint32_t r, uint32_t N, uint32_t C,
+                              uint32_t nraw)
 {
     uint64_t nch, c, total, per;
     if (C == 0)
@@ -577,7 +665,7 @@ uint64_t orc_encode_bound(uint64_t nsyms, uint32_t k, uint32_t r, uint32_t N, ui
         return 32;
     nch = (nsyms + C - 1) / C;
     total = align16(32 + 16 * nch);
-    per = max_digits_per_symbol(k, r) * (r / 8);
+    per = (max_digits_per_symbol(k, r) + nraw) * (r / 8);
     for (c = 0; c < nch; c++) {
         uint64_t len = (c + 1 == nch) ? nsyms - c * (uint64_t)C : C;
         total += align16(4ull * N + per * len);
@@ -585,11 +673,17 @@ uint64_t orc_encode_bound(uint64_t nsyms, uint32_t k, uint32_t r, uint32_t N, ui
     return total;
 }
 
+uint64_t orc_encode_bound(uint64_t nsyms, uint32_t k, uint32_t r, uint32_t N, uint32_t C)
+{
+    return orc_encode_bound_raw(nsyms, k, r, N, C, 0);
+}
+
 typedef struct {
     const model_t *m;
     geom_t g;
     uint32_t r, w, C;
-    int order; /* 0 depth-first, 1 breadth-first */
+    int order;     /* 0 depth-first, 1 breadth-first */
+    uint32_t nraw; /* escape coding: raw digits per escaped value; 0 = off */
     const uint8_t *syms;
     uint64_t nsyms, nch;
     uint8_t **chunk_bytes;
@@ -607,7 +701,7 @@ static void *encode_worker(void *arg)
     job_t *jb = (job_t *)arg;
     uint64_t c;
     uint32_t *syms = (uint32_t *)malloc(sizeof(uint32_t) * (jb->C ? jb->C : 1));
-    uint64_t cap = max_digits_per_symbol(jb->m->k, jb->r) * jb->C + 1;
+    uint64_t cap = (max_digits_per_symbol(jb->m->k, jb->r) + jb->nraw) * jb->C + 1;
     uint32_t *dig = (uint32_t *)malloc(sizeof(uint32_t) * cap);
     uint64_t *states = (uint64_t *)malloc(sizeof(uint64_t) * jb->g.N);
     jb->rc = ORC_OK;
@@ -623,8 +717,12 @@ static void *encode_worker(void *arg)
         int rc;
         for (i = 0; i < len; i++)
             syms[i] = get_sym(jb->syms, jb->w, base + i);
-        rc = jb->order ? encode_bf(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL)
-                       : encode_df(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL);
+        if (jb->nraw)
+            rc = encode_esc(jb->m, &jb->g, jb->nraw, syms, len, states, dig, cap, &start);
+        else if (jb->order)
+            rc = encode_bf(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL);
+        else
+            rc = encode_df(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL);
         if (rc != ORC_OK) {
             jb->rc = rc;
             goto out;
@@ -689,10 +787,14 @@ static int run_workers(job_t *proto, int nthreads, void *(*fn)(void *))
     return rc;
 }
 
-/* Encodes nsyms symbols (w bytes each, little-endian) into a container whose
- * chunk streams use digit order `order` (0 depth-first, 1 breadth-first). */
-int orc_encode_order(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
-                     uint32_t w, uint32_t N, uint32_t C, int order, const uint8_t *syms,
+/* Raw digits an escaped w-byte value takes (all 8w bits). */
+static uint32_t raw_digits(uint32_t w, uint32_t r) { return (8 * w + r - 1) / r; }
+
+/* Encodes nsyms symbols (w bytes each, little-endian) into a container.
+ * flags (header byte 9): bit 0 breadth-first digit order, bit 1 escape
+ * coding (16-bit symbols, depth-first only). */
+int orc_encode_flags(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
+                     uint32_t w, uint32_t N, uint32_t C, int flags, const uint8_t *syms,
                      uint64_t nsyms, uint8_t *out, uint64_t cap, uint64_t *out_len, int nthreads)
 {
     model_t m;
@@ -701,7 +803,7 @@ int orc_encode_order(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r
     int rc = check_container_params(k, r, l, w, N);
     if (rc != ORC_OK)
         return rc;
-    if (order != 0 && order != 1)
+    if (flags < 0 || flags > 2 || (flags == 2 && w != 2))
         return ORC_EINVAL;
     if (C == 0) {
         if (nsyms > 0xFFFFFFFFull)
@@ -722,7 +824,8 @@ int orc_encode_order(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r
     jb.r = r;
     jb.w = w;
     jb.C = C;
-    jb.order = order;
+    jb.order = flags & 1;
+    jb.nraw = (flags & 2) ? raw_digits(w, r) : 0;
     jb.syms = syms;
     jb.nsyms = nsyms;
     jb.nch = nch;
@@ -754,7 +857,7 @@ int orc_encode_order(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r
     out[6] = (uint8_t)r;
     out[7] = (uint8_t)l;
     out[8] = (uint8_t)w;
-    out[9] = (uint8_t)order;
+    out[9] = (uint8_t)flags;
     put_u16(out + 10, N);
     put_u32(out + 12, C);
     put_u64(out + 16, nsyms);
@@ -778,6 +881,17 @@ out:
     return rc;
 }
 
+/* Container with digit order `order` (0 depth-first, 1 breadth-first). */
+int orc_encode_order(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
+                     uint32_t w, uint32_t N, uint32_t C, int order, const uint8_t *syms,
+                     uint64_t nsyms, uint8_t *out, uint64_t cap, uint64_t *out_len, int nthreads)
+{
+    if (order != 0 && order != 1)
+        return ORC_EINVAL;
+    return orc_encode_flags(f, n_alpha, k, r, l, w, N, C, order, syms, nsyms, out, cap, out_len,
+                            nthreads);
+}
+
 /* Depth-first container (the digit order every caller used before the order
  * byte existed). */
 int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
@@ -789,15 +903,16 @@ int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint
 }
 
 typedef struct {
-    uint32_t k, r, l, w, N, C, order;
+    uint32_t k, r, l, w, N, C, order, nraw;
     uint64_t n, nch;
 } hdr_t;
 
 static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
 {
-    if (in_len < 32 || get_u32(in) != ORC_MAGIC || in[4] != 1 || in[9] > 1)
+    if (in_len < 32 || get_u32(in) != ORC_MAGIC || in[4] != 1 || in[9] > 2 ||
+        (in[9] == 2 && in[8] != 2))
         return ORC_ECORRUPT;
-    h->order = in[9];
+    h->order = in[9] & 1;
     h->k = in[5];
     h->r = in[6];
     h->l = in[7];
@@ -808,6 +923,7 @@ static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
     h->nch = get_u32(in + 24);
     if (check_container_params(h->k, h->r, h->l, h->w, h->N) != ORC_OK)
         return ORC_ECORRUPT;
+    h->nraw = (in[9] & 2) ? raw_digits(h->w, h->r) : 0;
     if (h->n == 0 ? h->nch != 0 : (h->C == 0 || h->nch != (h->n + h->C - 1) / h->C))
         return ORC_ECORRUPT;
     if (32 + 16 * h->nch > in_len)
@@ -815,8 +931,8 @@ static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
     return ORC_OK;
 }
 
-/* Reads the header fields: out[0..8] = k, r, l, w, N, C, n, n_chunks, digit
- * order. */
+/* Reads the header fields: out[0..9] = k, r, l, w, N, C, n, n_chunks, digit
+ * order, raw digits per escaped value (0: no escape coding). */
 int orc_header(const uint8_t *in, uint64_t in_len, uint64_t *out)
 {
     hdr_t h;
@@ -832,6 +948,7 @@ int orc_header(const uint8_t *in, uint64_t in_len, uint64_t *out)
     out[6] = h.n;
     out[7] = h.nch;
     out[8] = h.order;
+    out[9] = h.nraw;
     return ORC_OK;
 }
 
@@ -841,7 +958,7 @@ static void *decode_worker(void *arg)
     const hdr_t *h = (const hdr_t *)jb->hdr;
     uint64_t c;
     uint32_t *syms = (uint32_t *)malloc(sizeof(uint32_t) * (h->C ? h->C : 1));
-    uint64_t cap = max_digits_per_symbol(h->k, h->r) * h->C + 1;
+    uint64_t cap = (max_digits_per_symbol(h->k, h->r) + h->nraw) * h->C + 1;
     uint32_t *dig = (uint32_t *)malloc(sizeof(uint32_t) * cap);
     uint64_t *states = (uint64_t *)malloc(sizeof(uint64_t) * h->N);
     jb->rc = ORC_OK;
@@ -871,8 +988,12 @@ static void *decode_worker(void *arg)
         for (i = 0; i < nd; i++)
             dig[i] = h->r == 16 ? get_u16(jb->in + off + 4ull * h->N + 2 * i)
                                 : jb->in[off + 4ull * h->N + i];
-        rc = h->order ? decode_bf(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL)
-                      : decode_df(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL);
+        if (h->nraw)
+            rc = decode_esc(jb->m, &jb->g, h->nraw, states, dig, nd, syms, nsy);
+        else if (h->order)
+            rc = decode_bf(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL);
+        else
+            rc = decode_df(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL);
         if (rc != ORC_OK) {
             jb->rc = rc;
             goto out;

@@ -432,8 +432,111 @@ def test_order_byte_values_above_one_rejected():
     syms = (np.arange(1000) % 3).astype(np.uint8)
     f = oracle.quantize(np.bincount(syms, minlength=256).astype(np.uint64), 8)
     buf = oracle.encode(f, syms, 8, 8, 23, 4, 0)
-    buf[9] = 2
+    buf[9] = 2  # escape coding, which 8-bit symbols cannot use
     with pytest.raises(oracle.OracleError):
         oracle.decode(f, buf)
     with pytest.raises(ValueError):
         oracle.encode(f, syms, 8, 8, 23, 4, 0, order="xx")
+
+
+# ----------------------------------------------------- escape / raw digits --
+
+def _escape_case(seed, n=6000, alpha=300, k=12):
+    """uint16 values: most drawn from a Zipf table over `alpha` symbols (the
+    last of which is the escape), the rest anywhere in 0..65535."""
+    rng = np.random.default_rng(seed)
+    p = 1.0 / np.arange(1, alpha + 1) ** 1.1
+    v = rng.choice(alpha, size=n, p=p / p.sum()).astype(np.uint16)
+    wild = rng.random(n) < 0.1
+    v[wild] = rng.integers(0, 65536, int(wild.sum()))
+    counts = np.bincount(np.minimum(v, alpha - 1), minlength=alpha).astype(np.uint64)
+    counts[alpha - 1] += 1
+    return v, oracle.quantize(counts, k)
+
+
+def _tokens(v, f):
+    E = len(f) - 1
+    vi = v.astype(np.int64)
+    esc = (vi >= E) | (np.asarray(f)[np.minimum(vi, E)] == 0)
+    return np.where(esc, E, vi).astype(np.uint16), esc
+
+
+@pytest.mark.parametrize("r,l", [(16, 16), (8, 23)])
+@pytest.mark.parametrize("N,C", [(1, 0), (4, 1000), (64, 2048), (32, 777)])
+def test_escape_roundtrip_and_states_equal_token_stream(r, l, N, C):
+    """Raw digits never touch a coder state (Section 3): the states of an
+    escape container are those of the plain container of the token
+    sequence, and each escape adds exactly 16/r raw digits."""
+    v, f = _escape_case(31 + N + r)
+    buf = oracle.encode(f, v, 12, r, l, N, C, escape=True)
+    h = oracle.header(buf)
+    assert buf[9] == 2 and h["escape"] and h["nraw"] == 16 // r
+    assert (oracle.decode(f, buf) == v).all()
+    tok, esc = _tokens(v, f)
+    plain = oracle.encode(f, tok, 12, r, l, N, C)
+    Ce = C or v.size
+    for c, (a, b) in enumerate(zip(_chunk_streams(buf), _chunk_streams(plain))):
+        assert (a[0] == b[0]).all(), c
+        nesc = int(esc[c * Ce:(c + 1) * Ce].sum())
+        assert a[1].size == b[1].size + nesc * 2, c  # 16 raw bits per escape
+
+
+def test_escape_without_escapes_is_the_plain_stream():
+    rng = np.random.default_rng(33)
+    v = rng.integers(0, 40, 5000).astype(np.uint16)
+    f = oracle.quantize(np.bincount(np.r_[v, [40]], minlength=41).astype(np.uint64), 11)
+    assert (f[:40] > 0).all() and f[40] > 0
+    for r, l in [(16, 16), (8, 23)]:
+        a = oracle.encode(f, v, 11, r, l, 16, 1000, escape=True)
+        b = oracle.encode(f, v, 11, r, l, 16, 1000)
+        assert a[9] == 2 and b[9] == 0
+        assert (a[:9] == b[:9]).all() and (a[10:] == b[10:]).all()
+
+
+@pytest.mark.parametrize("r,l", [(16, 16), (8, 23)])
+def test_escape_with_one_symbol_table_is_raw_storage(r, l):
+    """With f = (M): C and D are the identity and nothing renormalises, so every
+    value escapes and each chunk stream is the states (all L) followed by the
+    values themselves in message order, 16 bits each, high digit first."""
+    rng = np.random.default_rng(34)
+    v = rng.integers(0, 65536, 3001).astype(np.uint16)
+    f = np.array([1 << 10], np.uint32)
+    N, C = 8, 1000
+    buf = oracle.encode(f, v, 10, r, l, N, C, escape=True)
+    for c, (st, dig) in enumerate(_chunk_streams(buf)):
+        assert (st == (1 << l)).all()
+        part = v[c * C:(c + 1) * C]
+        want = (part.astype("<u2").view(np.uint8) if r == 16
+                else part.astype(">u2").view(np.uint8))
+        assert (dig == want).all(), c
+    # a raw digit sits where that closed form says: flipping the one of value
+    # 1234 changes that value only, and the end check still passes
+    bad = buf.copy()
+    off = int(np.frombuffer(bad[32 + 16:32 + 24].tobytes(), "<u8")[0])  # chunk 1
+    bad[off + 4 * N + 2 * (1234 - C) + (1 if r == 8 else 0)] ^= 0x81
+    out = oracle.decode(f, bad)
+    diff = np.flatnonzero(out != v)
+    assert diff.tolist() == [1234] and int(out[1234]) == int(v[1234]) ^ 0x81
+
+
+def test_escape_flags_checked():
+    v, f = _escape_case(35, n=500)
+    buf = oracle.encode(f, v, 12, 16, 16, 4, 0, escape=True)
+    plainread = buf.copy()
+    plainread[9] = 0  # raw digits read as renormalisation digits
+    try:
+        out = oracle.decode(f, plainread)
+        assert (out != v).any()
+    except oracle.OracleError:
+        pass
+    for bad_flags in (3, 4, 0x80):
+        b = buf.copy()
+        b[9] = bad_flags
+        with pytest.raises(oracle.OracleError):
+            oracle.decode(f, b)
+    w1 = (np.arange(100) % 3).astype(np.uint8)
+    f1 = oracle.quantize(np.array([40, 30, 30, 1], np.uint64), 8)
+    with pytest.raises(oracle.OracleError):
+        oracle.encode(f1, w1, 8, 16, 16, 4, 0, escape=True)  # 16-bit symbols only
+    with pytest.raises(oracle.OracleError):
+        oracle.encode(f, v, 12, 16, 16, 4, 0, order="bf", escape=True)
