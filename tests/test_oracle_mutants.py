@@ -24,11 +24,13 @@ MUTANTS = [
     ("interval upper bound off by one", "return x >= g->L && x < g->b * g->L;",
      "return x >= g->L && x <= g->b * g->L;", 1),
     ("coder order reversed", "j = (uint32_t)(i % g->N);",
-     "j = (uint32_t)(g->N - 1 - i % g->N);", 2),
+     "j = (uint32_t)(g->N - 1 - i % g->N);", 4),
     ("initial state off by one", "states[j] = g->L; /* reading Q3 */",
-     "states[j] = g->L + 1;", 1),
+     "states[j] = g->L + 1;", 2),
     ("emit wrong digit", "buf[--*pos] = (uint32_t)(*x % g->b);",
      "buf[--*pos] = (uint32_t)(*x / g->b % g->b);", 1),
+    ("raw digit weight", "v = v * g->b + dig[rd++];", "v = v + g->b * dig[rd++];", 1),
+    ("escape ignores zero frequency", "if (v >= E || m->f[v] == 0) {", "if (v >= E) {", 1),
 ]
 
 
@@ -42,6 +44,8 @@ def _checks(golden):
         lambda: pins.test_precursor_sets_are_b_unique_bruteforce(),
         lambda: pins.test_exhaustive_roundtrip_and_injectivity(2),
         lambda: pins.test_interleaved_stream_equals_instrumented_mux(3),
+        lambda: pins.test_escape_with_one_symbol_table_is_raw_storage(16, 16),
+        lambda: pins.test_escape_roundtrip_and_states_equal_token_stream(8, 23, 4, 1000),
     ]
 
 
