@@ -22,8 +22,8 @@
  *
  * Stream format (container).  All fields little-endian.
  *   header, 32 bytes: u32 magic 0x534E4172 ("rANS"), u8 version 1, u8 k,
- *     u8 r, u8 l, u8 w, u8 digit order (0 depth-first, 1 breadth-first),
- *     u16 N, u32 C, u64 n, u32 n_chunks, u32 0
+ *     u8 r, u8 l, u8 w, u8 flags (bit 0: breadth-first digit order, bit 1:
+ *     escape coding; not both), u16 N, u32 C, u64 n, u32 n_chunks, u32 0
  *   directory: n_chunks x { u64 offset, u32 length, u32 0 }
  *   chunk streams, each at a 16-byte aligned offset, zero padding between;
  *     the first at align16(32 + 16*n_chunks); the total length is
@@ -37,7 +37,18 @@
  *     first digit of every coder that reads one (coders ascending), then the
  *     second digit of every coder that reads two.  The orders coincide when
  *     b >= M (at most one digit per step: always with b = 2^16, as k <= 15),
- *     so they differ only for b = 2^8 with k > 8.  Every coder starts encoding in state L;
+ *     so they differ only for b = 2^8 with k > 8.
+ *   escape coding (flags bit 1; 16-bit symbols, depth-first): the table's
+ *     last symbol E = alphabet - 1 is an escape.  A value v is coded as the
+ *     symbol v when v < E and its frequency is not 0, otherwise as E followed
+ *     by 16 raw bits holding v (one u16 word, or two bytes high first); in a
+ *     coder's share of a step the raw digits follow its renormalisation
+ *     digits.  Raw digits never touch a coder state (Section 3: encoder and
+ *     decoder run in lockstep, so raw data needs no bypass mode), so any
+ *     16-bit value can be coded with a table of the frequent ones.  The
+ *     one-wave-per-chunk and generic kernels support it; the batched entry
+ *     points, the server and rans_decode_lut reject it (RANS_EINVAL).
+ *     Every coder starts encoding in state L;
  *     when a chunk's length is not a multiple of N, the last step only
  *     involves coders 0 .. (len mod N)-1.
  *
@@ -80,7 +91,10 @@ extern "C" {
  *                                     order within a step (Section 5);
  *                                     recorded in the container header, so
  *                                     decoding takes it from there
- *   reserved == 0
+ *   escape in {0, 1}                  escape coding with raw digits (Section
+ *                                     3: raw data interleaved in the stream
+ *                                     at agreed points); needs sym_bytes 2
+ *                                     and digit_order 0; see below
  *   chunk_syms (C)                    symbols per chunk; 0 = the whole input
  *                                     (then n must fit 32 bits)            */
 typedef struct rans_params {
@@ -90,7 +104,7 @@ typedef struct rans_params {
     uint8_t sym_bytes;
     uint16_t interleave;
     uint8_t digit_order;
-    uint8_t reserved;
+    uint8_t escape;
     uint32_t chunk_syms;
 } rans_params;
 
@@ -131,8 +145,9 @@ void rans_table_destroy(rans_table *table);
 int rans_params_check(const rans_params *params);
 
 /* Host only.  An upper bound on the container length rans_encode can
- * produce for n_syms symbols (each symbol emits at most ceil(k/r) digits).
- * Returns 0 for invalid parameters. */
+ * produce for n_syms symbols (each symbol emits at most ceil(k/r) digits,
+ * plus 16/r raw digits with escape coding).  Returns 0 for invalid
+ * parameters. */
 uint64_t rans_encode_bound(uint64_t n_syms, const rans_params *params);
 
 /* Encodes d_syms[n_syms] (device; uint8 or uint16 per params->sym_bytes)

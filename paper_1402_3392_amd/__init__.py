@@ -34,14 +34,15 @@ class rans_params(ct.Structure):
     _fields_ = [("prob_bits", ct.c_uint8), ("radix_bits", ct.c_uint8),
                 ("state_lbits", ct.c_uint8), ("sym_bytes", ct.c_uint8),
                 ("interleave", ct.c_uint16), ("digit_order", ct.c_uint8),
-                ("reserved", ct.c_uint8), ("chunk_syms", ct.c_uint32)]
+                ("escape", ct.c_uint8), ("chunk_syms", ct.c_uint32)]
 
     @classmethod
-    def make(cls, k, r, l, w, N, C, order="df"):
-        """order: "df" (depth-first) or "bf" (breadth-first) digit order."""
+    def make(cls, k, r, l, w, N, C, order="df", escape=False):
+        """order: "df" (depth-first) or "bf" (breadth-first) digit order;
+        escape: escape coding with raw digits (16-bit symbols)."""
         if order not in ("df", "bf"):
             raise ValueError(f"digit order {order!r}: expected 'df' or 'bf'")
-        return cls(k, r, l, w, N, 1 if order == "bf" else 0, 0, C)
+        return cls(k, r, l, w, N, 1 if order == "bf" else 0, 1 if escape else 0, C)
 
 
 class rans_batch_config(ct.Structure):
@@ -180,7 +181,8 @@ def _params(p) -> rans_params:
     if isinstance(p, rans_params):
         return p
     if isinstance(p, dict):
-        return rans_params.make(p["k"], p["r"], p["l"], p["w"], p["N"], p["C"], p.get("order", "df"))
+        return rans_params.make(p["k"], p["r"], p["l"], p["w"], p["N"], p["C"], p.get("order", "df"),
+                                p.get("escape", False))
     if hasattr(p, "astuple"):
         return rans_params.make(*p.astuple())
     return rans_params.make(*p)

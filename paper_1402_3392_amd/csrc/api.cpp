@@ -28,7 +28,10 @@ int check_params(const rans_params* p)
                    N = p->interleave;
     if (k < 8 || k > 15 || (r != 8 && r != 16) || l < k || l + r > 32 || (w != 1 && w != 2))
         return RANS_EINVAL;
-    if (N < 1 || N > 64 || (N & (N - 1)) != 0 || p->digit_order > 1 || p->reserved != 0)
+    if (N < 1 || N > 64 || (N & (N - 1)) != 0 || p->digit_order > 1 || p->escape > 1)
+        return RANS_EINVAL;
+    // escape coding: 16-bit symbols, depth-first digit order
+    if (p->escape && (w != 2 || p->digit_order != 0))
         return RANS_EINVAL;
     return RANS_OK;
 }
@@ -45,11 +48,15 @@ uint32_t log2u(uint32_t v)
 // most ceil(k/r) divisions by b.
 uint32_t max_digits(uint32_t k, uint32_t r) { return (k + r - 1) / r; }
 
+// Raw digits an escaped 16-bit value adds (escape coding).
+uint32_t raw_digits(uint32_t r) { return 16 / r; }
+
 // Digit slot of one chunk: room for its largest stream, rounded to 256 bytes
 // (the encoder writes whole 256-byte windows, aligned to the slot).
-uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r)
+uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r, bool esc)
 {
-    return (uint64_t(C) * max_digits(k, r) * (r / 8) + 255) & ~uint64_t(255);
+    const uint64_t per = max_digits(k, r) + (esc ? raw_digits(r) : 0);
+    return (uint64_t(C) * per * (r / 8) + 255) & ~uint64_t(255);
 }
 
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch)
@@ -62,7 +69,7 @@ void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint3
     h[6] = p.radix_bits;
     h[7] = p.state_lbits;
     h[8] = p.sym_bytes;
-    h[9] = p.digit_order;
+    h[9] = static_cast<uint8_t>(p.digit_order | (p.escape << 1));
     const uint16_t N = p.interleave;
     std::memcpy(h + 10, &N, 2);
     std::memcpy(h + 12, &C, 4);
@@ -80,7 +87,7 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     std::memcpy(&C, h + 12, 4);
     std::memcpy(&n, h + 16, 8);
     std::memcpy(&nch, h + 24, 4);
-    if (magic != kMagic || h[4] != 1 || h[9] > 1)
+    if (magic != kMagic || h[4] != 1 || h[9] > 3)
         return RANS_ECORRUPT;
     rans_params p{};
     p.prob_bits = h[5];
@@ -88,7 +95,8 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     p.state_lbits = h[7];
     p.sym_bytes = h[8];
     p.interleave = N;
-    p.digit_order = h[9];
+    p.digit_order = h[9] & 1;
+    p.escape = h[9] >> 1;
     p.chunk_syms = C;
     if (check_params(&p) != RANS_OK)
         return RANS_ECORRUPT;
@@ -164,7 +172,9 @@ extern "C" uint64_t rans_encode_bound(uint64_t n, const rans_params* p)
     if (C > 0xFFFFFFFFull)
         return 0;
     const uint64_t nch = (n + C - 1) / C;
-    const uint64_t per = uint64_t(max_digits(p->prob_bits, p->radix_bits)) * (p->radix_bits / 8);
+    const uint64_t per = uint64_t(max_digits(p->prob_bits, p->radix_bits) +
+                                  (p->escape ? raw_digits(p->radix_bits) : 0)) *
+                         (p->radix_bits / 8);
     const uint64_t full = nch - 1, last = n - full * C;
     auto a16 = [](uint64_t v) { return (v + 15) & ~uint64_t(15); };
     return a16(kHeaderBytes + kDirEntryBytes * nch) +
@@ -212,7 +222,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
         return RANS_EINVAL;
     const uint32_t nch = static_cast<uint32_t>(nch64);
     const uint32_t R = p.radix_bits, N = p.interleave;
-    const uint64_t sb = slot_bytes_for(C, p.prob_bits, R);
+    const uint64_t sb = slot_bytes_for(C, p.prob_bits, R, p.escape != 0);
     const EncodeLayout el = encode_layout(nch, N, sb);
     *ws_need = el.total;
 
@@ -227,6 +237,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->l = p.state_lbits;
     ea->alphabet = t.alphabet;
     ea->bf = p.digit_order;
+    ea->esc = p.escape;
     ea->enc = t.enc;
     ea->enc_bytes = static_cast<uint32_t>(t.enc_bytes);
     ea->slot_bytes = sb;
@@ -429,6 +440,8 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     } else {
         if ((lut_w != 2 && lut_w != 4) || !d_lut || (reinterpret_cast<uintptr_t>(d_lut) & (lut_w - 1)))
             return RANS_EINVAL;
+        if (h->p.escape)  // escaped values lie outside the table, so outside the LUT
+            return RANS_EINVAL;
         if (h->n > syms_cap)
             return RANS_ENOSPC;
         if (h->n && (!d_syms || !fast64(h->p.interleave, h->p.chunk_syms, lut_w, d_syms)))
@@ -450,6 +463,7 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     da->l = h->p.state_lbits;
     da->alphabet = t.alphabet;
     da->bf = h->p.digit_order;
+    da->esc = h->p.escape;
     da->lut = d_lut;
     da->lut_w = lut_w;
     fill_decode_tables(t, *layout, da);

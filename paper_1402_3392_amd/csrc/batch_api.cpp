@@ -63,6 +63,8 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     // chunks must start 16-byte aligned in the symbol buffers
     if (p.interleave != 64 && p.interleave != 32)
         return RANS_EINVAL;
+    if (p.escape)  // escape coding runs on the single-buffer entry points only
+        return RANS_EINVAL;
     if (!decode && (p.chunk_syms == 0 || (uint64_t(p.chunk_syms) * w) % 16 != 0))
         return RANS_EINVAL;
     if (njobs == 0)

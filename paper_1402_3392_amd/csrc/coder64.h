@@ -127,14 +127,21 @@ __device__ __forceinline__ void stage2(uint8_t* lds, const void* a, uint32_t aby
 // BF: the chunk's digits are in breadth-first order (Section 5; only byte
 // digits can differ from depth-first).  LW = 2 or 4: a consumer fused into
 // the decoder -- output element i is l_lut[symbol i] (LW bytes, staged in
-// LDS), so the symbols never reach memory; W is then irrelevant.
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false, int LW = 0>
+// LDS), so the symbols never reach memory; W is then irrelevant.  ESC
+// (16-bit symbols, depth-first): escape coding -- the table's last symbol
+// E = alphabet - 1 is followed in its coder's share of the step by 16 / R
+// raw digits that hold the output value (Section 3's raw data mixed into
+// the stream).
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false, int LW = 0, bool ESC = false>
 __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                              uint64_t chunk, uint32_t C, uint64_t n, void* out_base,
                                              uint32_t k_, uint32_t l, const void* l_sym_v,
                                              const uint32_t* l_ent, uint8_t* wave_lds,
-                                             int32_t* status, const void* l_lut = nullptr)
+                                             int32_t* status, const void* l_lut = nullptr,
+                                             uint32_t alphabet = 0)
 {
+    static_assert(!ESC || (W == 2 && !BF && LW == 0), "escape coding: 16-bit symbols, depth-first");
+    const uint32_t E = alphabet - 1;  // the escape symbol (ESC)
     using SymT = typename std::conditional<SW == 1, uint8_t, uint16_t>::type;
     using SymOutT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
     using LutT = typename std::conditional<LW == 4, uint32_t, uint16_t>::type;
@@ -152,10 +159,13 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     constexpr uint32_t OB = obuf_bytes(LAYOUT);
     uint8_t* obuf = wave_lds;              // output block (first: the initial states)
     constexpr uint32_t S = ring_slots(LAYOUT), TB = test_steps(LAYOUT);
-    // a block of TB steps reads at most 128 TB bytes starting below the end
+    // a block of TB steps reads at most MAXB TB bytes starting below the end
     // of window kw, so windows kw .. kw + RES - 1 must have landed; the
-    // loads of the other S - RES slots may still be in flight
-    constexpr uint32_t RES = 1 + TB / 2;
+    // loads of the other S - RES slots may still be in flight.  A step reads
+    // at most 2 digit bytes per coder, 4 with escapes (a renormalisation
+    // digit and a raw digit of 16 bits, or two bytes of each).
+    constexpr uint32_t MAXB = ESC ? 256 : 128;
+    constexpr uint32_t RES = 1 + TB * MAXB / kWin;
     constexpr int AHEAD = static_cast<int>(S - RES);
     const uint8_t* ring = wave_lds + OB;   // S windows + copy of slot 0
     const uint8_t* de = in + kHeaderBytes + kDirEntryBytes * chunk;
@@ -323,6 +333,38 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             }
         }
     };
+    // Refill with escapes: a lane's digits in the step are its
+    // renormalisation digits, then (escape lanes) 16 raw bits; every lane
+    // reads at the prefix count of all digits below it, the escape lanes'
+    // raw digits replace the decoded symbol.
+    auto refill_esc = [&](bool act, auto dense, uint32_t& s) {
+        const bool n1 = act && x < L;
+        const bool ne = act && s == E;
+        const uint64_t m1 = ballot(n1), me = ballot(ne);
+        if (R == 16) {
+            if (dense || (m1 | me)) {
+                const uint16_t* rp = reinterpret_cast<const uint16_t*>(ring) + (pos & DMASK);
+                const uint16_t* q = rp + (mbcnt(m1, 0) + mbcnt(me, 0));
+                const uint32_t v0 = q[0], v1 = q[1];
+                x = select_mask(m1, x, (x << 16) | v0);
+                s = select_mask(me, s, select_mask(m1, v0, v1));
+                pos += __popcll(m1) + __popcll(me);
+            }
+        } else {
+            const bool n2 = act && x < (L >> 8);
+            const uint64_t m2 = ballot(n2);
+            if (dense || (m1 | me)) {
+                const uint8_t* q = ring + (pos & DMASK) + (mbcnt(m1, 0) + mbcnt(m2, 0) + 2 * mbcnt(me, 0));
+                const uint32_t b0 = q[0], b1 = q[1], b2 = q[2], b3 = q[3];
+                const uint32_t x1 = (x << 8) | b0, x2 = (x1 << 8) | b1;
+                x = select_mask(m1, x, select_mask(m2, x1, x2));
+                // raw value after 0, 1 or 2 renormalisation bytes
+                const uint32_t r0 = (b0 << 8) | b1, r1 = (b1 << 8) | b2, r2 = (b2 << 8) | b3;
+                s = select_mask(me, s, select_mask(m1, r0, select_mask(m2, r1, r2)));
+                pos += __popcll(m1) + __popcll(m2) + 2 * __popcll(me);
+            }
+        }
+    };
     auto flush = [&](uint32_t tb) {  // output block starting at step tb
         lane_fence();
         const Piece v = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
@@ -333,7 +375,10 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     auto step1 = [&](OutT* dst, auto dense) {
         uint32_t s;
         decode_one(s);
-        refill(live, dense);
+        if (ESC)
+            refill_esc(live, dense, s);
+        else
+            refill(live, dense);
         if (live)
             *dst = emit(s);
     };
@@ -360,13 +405,16 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         uint32_t s = 0;
         if (act)
             decode_one(s);
-        refill(act, std::false_type{});
+        if (ESC)
+            refill_esc(act, std::false_type{}, s);
+        else
+            refill(act, std::false_type{});
         if (live)
             ob[(t & (SPB - 1)) * NL] = emit(s);
         ++t;
     };
-    // A step reads at most 2 NL <= 128 digit bytes, so TB steps that start
-    // below wend = 256 (kw + 1) stay inside windows kw .. kw + RES - 1.
+    // A step reads at most MAXB digit bytes, so TB steps that start below
+    // wend = 256 (kw + 1) stay inside windows kw .. kw + RES - 1.
     // Moving kw on issues window kw + S - 1 into the slot of the window just
     // finished, then waits until at most S - RES later loads are pending:
     // window kw + RES - 1 is in.
@@ -392,7 +440,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             }
         }
     };
-    static_assert(SPB % TB == 0 && 128 * TB <= (RES - 1) * kWin && RES < S, "ring geometry");
+    static_assert(SPB % TB == 0 && MAXB * TB <= (RES - 1) * kWin && RES < S, "ring geometry");
 
     // whole output blocks: every offset is an immediate, one flush per block
     constexpr uint32_t NB = SPB / TB;
@@ -528,6 +576,57 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
     }
 }
 
+// Encoder step with escape coding (16-bit symbols, depth-first).  The value
+// v is coded as the symbol v when the table has it (v < E, f_v > 0) and as
+// the escape E otherwise; an escape lane also emits 16 raw bits holding v.
+// The decoder reads them after the lane's renormalisation digits, so they
+// follow those digits in the stream (Section 3: the encoder sends raw data
+// just before it encodes the symbol they belong to).  e: the staged entry of
+// min(v, alphabet), whose bad bit marks f_v = 0; eE: the escape's entry.
+template <int R>
+__device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32_t& bad, uint4 e,
+                                             const uint4& eE, uint32_t v, uint32_t E, bool act,
+                                             uint8_t* dring, uint32_t lane)
+{
+    constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
+    const bool esc = act && (v >= E || ((e.w >> 23) & 1u));
+    if (esc)
+        e = eE;
+    if (act)
+        bad |= e.w;
+    const bool e1 = act && x > e.y;
+    const uint64_t m1 = ballot(e1), me = ballot(esc);
+    if (R == 16) {
+        wpos -= __popcll(m1) + __popcll(me);
+        const uint32_t i1 = wpos + (mbcnt(m1, 0) + mbcnt(me, 0));
+        const uint32_t o1 = select_mask(m1, kEncRing + 2 * lane, (i1 << 1) & (2 * RD - 1));
+        const uint32_t o2 = select_mask(me, kEncRing + 2 * lane, ((i1 + (e1 ? 1u : 0u)) << 1) & (2 * RD - 1));
+        *reinterpret_cast<uint16_t*>(dring + o1) = static_cast<uint16_t>(x);
+        *reinterpret_cast<uint16_t*>(dring + o2) = static_cast<uint16_t>(v);
+        x = e1 ? x >> 16 : x;
+    } else {
+        const bool e2 = act && (x >> 8) > e.y;
+        const uint64_t m2 = ballot(e2);
+        wpos -= __popcll(m1) + __popcll(m2) + 2 * __popcll(me);
+        const uint32_t i1 = wpos + (mbcnt(m1, 0) + mbcnt(m2, 0) + 2 * mbcnt(me, 0));
+        const uint32_t ir = i1 + (e1 ? 1u : 0u) + (e2 ? 1u : 0u);  // raw bytes after the renormalisation bytes
+        const uint32_t o1 = select_mask(m1, kEncRing + lane, i1 & (RD - 1));
+        const uint32_t o2 = select_mask(m2, kEncRing + 64 + lane, (i1 + 1) & (RD - 1));
+        const uint32_t o3 = select_mask(me, kEncRing + lane, ir & (RD - 1));
+        const uint32_t o4 = select_mask(me, kEncRing + 64 + lane, (ir + 1) & (RD - 1));
+        dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
+        dring[o2] = static_cast<uint8_t>(x);
+        dring[o3] = static_cast<uint8_t>(v >> 8);
+        dring[o4] = static_cast<uint8_t>(v);
+        x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
+    }
+    if (act) {
+        const uint32_t th = __umulhi(e.x, x);
+        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> (e.z >> 16);
+        x = __umul24(q, e.w) + x + (e.z & 0xFFFFu);
+    }
+}
+
 // Encodes chunk `chunk` of syms_base (n symbols, C per chunk, NL = 32 or 64
 // interleaved coders) into the digit slot `slot` (digits end at slot +
 // slot_bytes, a multiple of 256; 256 more bytes follow), writes the NL final
@@ -540,8 +639,9 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
 // kFlushStores stores with stores to the 256 bytes after the slot.  A fixed
 // number of memory operations per block lets the compiler's wait for the
 // symbols of the next block leave the recent stores in flight.  BF: as in
-// enc_step.
-template <int R, int W, int NL, bool BF = false>
+// enc_step.  ESC: escape coding, as in enc_step_esc (a 1 KiB block of 16-bit
+// symbols still emits at most 2 KiB: 4 bytes per symbol).
+template <int R, int W, int NL, bool BF = false, bool ESC = false>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
                                              const uint4* l_enc, uint8_t* slot, uint64_t slot_bytes,
@@ -549,6 +649,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
                                              int32_t* status, uint32_t* x_out = nullptr,
                                              uint32_t* nd_out = nullptr)
 {
+    static_assert(!ESC || (W == 2 && !BF), "escape coding: 16-bit symbols, depth-first");
     using InT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
     constexpr uint32_t SPB = 1024 / (W * NL);  // steps per 1 KiB symbol block
     constexpr uint32_t DB = R / 8, WD = 256 / DB;  // bytes per digit, digits per window
@@ -562,6 +663,8 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     const uint32_t steps = (nsym + NL - 1) / NL;
     const uint32_t nblk = nsym / (NL * SPB);  // whole blocks
     const uint32_t top = uni(static_cast<uint32_t>(slot_bytes / DB));
+    const uint32_t E = alphabet - 1;                 // the escape (ESC)
+    const uint4 eE = ESC ? l_enc[E] : make_uint4(0, 0, 0, 0);
     uint32_t x = 1u << l;
     uint32_t wpos = top;  // lowest digit written so far
     uint32_t wtop = top;  // digits from wtop up are in the slot
@@ -590,7 +693,10 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         const uint64_t i = uint64_t(t) * NL + lane;
         const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
-        enc_step<R, BF>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
+        if (ESC)
+            enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], eE, s, E, act, dring, lane);
+        else
+            enc_step<R, BF>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
     }
     flush();  // the tail is shorter than a block: at most 8 windows
 
@@ -607,20 +713,24 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             *reinterpret_cast<uint4*>(sbuf + 16 * lane) = v;
             lane_fence();
             const InT* sb = reinterpret_cast<const InT*>(sbuf) + lane;
-            uint32_t sy[SPB];
+            uint32_t sy[SPB];  // entry index (ESC: the value itself)
 #pragma unroll
             for (int q = 0; q < int(SPB); ++q)
-                sy[q] = min(static_cast<uint32_t>(sb[q * NL]), alphabet);
+                sy[q] = ESC ? static_cast<uint32_t>(sb[q * NL]) : min(static_cast<uint32_t>(sb[q * NL]), alphabet);
             lane_fence();  // the symbols are in registers before the ring writes
+            auto entry = [&](int q) { return l_enc[ESC ? min(sy[q], alphabet) : sy[q]]; };
             uint4 ent[SPB];
 #pragma unroll
             for (int q = SPB - 1; q >= int(SPB) - PF && q >= 0; --q)
-                ent[q] = l_enc[sy[q]];
+                ent[q] = entry(q);
 #pragma unroll
             for (int q = SPB - 1; q >= 0; --q) {
                 if (q - PF >= 0)
-                    ent[q - PF] = l_enc[sy[q - PF]];
-                enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
+                    ent[q - PF] = entry(q - PF);
+                if (ESC)
+                    enc_step_esc<R>(x, wpos, bad, ent[q], eE, sy[q], E, live, dring, lane);
+                else
+                    enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
             }
             flush();
         };

@@ -1,8 +1,9 @@
 // Single-buffer decode kernel for N = 32 or 64 interleaved coders: one wave
 // per chunk, tables staged in LDS once per block; the chunk coder itself is
 // c64::decode_chunk.  LW = 0 writes the symbols; LW = 2 or 4 writes
-// lut[symbol] (a consumer fused into the decoder).  Included by the
-// translation units that instantiate each output kind.
+// lut[symbol] (a consumer fused into the decoder); ESC decodes escape-coded
+// 16-bit symbols.  Included by the translation units that instantiate each
+// output kind.
 #pragma once
 
 #include "coder64.h"
@@ -21,7 +22,7 @@ __device__ __forceinline__ void stage_lut(uint8_t* lds, const void* src, uint32_
         d[i] = s[i];
 }
 
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC>
 __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -47,14 +48,14 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
     const uint64_t chunk = uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (chunk >= a.n_chunks)
         return;  // no barrier follows
-    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, LW>(
+    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, LW, ESC>(
         a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, tab,
         reinterpret_cast<const uint32_t*>(tab + sym_bytes), lds + wave * c64::wave_lds_bytes(LAYOUT),
-        a.status, lut);
+        a.status, lut, a.alphabet);
 }
 
 // Waves per block: 16 when the tables leave room for them, fewer otherwise.
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC>
 hipError_t run(const DecodeArgs& a, hipStream_t st)
 {
     const uint32_t tabs = a.tab0_bytes + a.tab1_bytes + lut_lds_bytes(a.alphabet, LW);
@@ -67,7 +68,7 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
     wpb = wpb < fit ? wpb : fit;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
     const uint32_t lds = tabs + wpb * per;
-    auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF, LW>;
+    auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF, LW, ESC>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -76,19 +77,20 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int R, int W, int SW, int LAYOUT, bool BF, int LW>
+template <int R, int W, int SW, int LAYOUT, bool BF, int LW, bool ESC>
 hipError_t run_n(const DecodeArgs& a, hipStream_t st)
 {
-    return a.N == 32 ? run<R, W, SW, LAYOUT, 32, BF, LW>(a, st) : run<R, W, SW, LAYOUT, 64, BF, LW>(a, st);
+    return a.N == 32 ? run<R, W, SW, LAYOUT, 32, BF, LW, ESC>(a, st)
+                     : run<R, W, SW, LAYOUT, 64, BF, LW, ESC>(a, st);
 }
 
-template <int R, int W, int SW, bool BF, int LW>
+template <int R, int W, int SW, bool BF, int LW, bool ESC = false>
 hipError_t run_l(const DecodeArgs& a, Layout layout, hipStream_t st)
 {
     if (SW == 1 && layout == kFused)
-        return run_n<R, W, 1, kFused, BF, LW>(a, st);
-    return layout == kPacked ? run_n<R, W, SW, kPacked, BF, LW>(a, st)
-                             : run_n<R, W, SW, kTwoLevel, BF, LW>(a, st);
+        return run_n<R, W, 1, kFused, BF, LW, ESC>(a, st);
+    return layout == kPacked ? run_n<R, W, SW, kPacked, BF, LW, ESC>(a, st)
+                             : run_n<R, W, SW, kTwoLevel, BF, LW, ESC>(a, st);
 }
 
 template <int R, bool BF, int LW>
@@ -106,9 +108,21 @@ hipError_t run_w(const DecodeArgs& a, int W, Layout layout, hipStream_t st)
     }
 }
 
+// escape coding: 16-bit symbols, depth-first, symbol output
+template <int R>
+hipError_t run_esc(const DecodeArgs& a, Layout layout, hipStream_t st)
+{
+    return a.alphabet > 256 ? run_l<R, 2, 2, false, 0, true>(a, layout, st)
+                            : run_l<R, 2, 1, false, 0, true>(a, layout, st);
+}
+
 template <int LW>
 hipError_t run_r(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t st)
 {
+    if constexpr (LW == 0) {
+        if (a.esc)
+            return R == 16 ? run_esc<16>(a, layout, st) : run_esc<8>(a, layout, st);
+    }
     // 16-bit digits: one digit per step at most (b >= M), both orders coincide
     if (R == 16)
         return run_w<16, false, LW>(a, W, layout, st);

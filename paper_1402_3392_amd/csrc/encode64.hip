@@ -9,7 +9,7 @@ namespace {
 
 // Chunk indices come from a ticket in start order so that every look-back
 // only waits on chunks that are already running.
-template <int R, int W, int NL, bool BF>
+template <int R, int W, int NL, bool BF, bool ESC>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -24,20 +24,20 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
         return;
     uint8_t* slot = a.slots + uint64_t(chunk) * a.slot_stride;
     uint32_t x = 0, nd = 0;
-    c64::encode_chunk<R, W, NL, BF>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
+    c64::encode_chunk<R, W, NL, BF, ESC>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
                                 reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
                                 lds + a.enc_bytes + wave * c64::kEncWaveLds, nullptr, nullptr, a.status,
                                 &x, &nd);
     c64::place_chunk<R, NL>(chunk, a.n_chunks, x, c64::uni(nd), slot, a.slot_bytes, p, a.status);
 }
 
-template <int R, int W, int NL, bool BF>
+template <int R, int W, int NL, bool BF, bool ESC = false>
 hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
     const uint32_t lds = a.enc_bytes + wpb * c64::kEncWaveLds;
-    auto kern = k_encode64_place<R, W, NL, BF>;
+    auto kern = k_encode64_place<R, W, NL, BF, ESC>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -49,6 +49,8 @@ hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 template <int NL>
 hipError_t run_n(const EncodeArgs& a, const PlaceArgs& p, int R, int W, hipStream_t st)
 {
+    if (a.esc)  // escape coding: 16-bit symbols, depth-first
+        return R == 16 ? run_place<16, 2, NL, false, true>(a, p, st) : run_place<8, 2, NL, false, true>(a, p, st);
     // 16-bit digits: one digit per step at most (b >= M), both orders coincide
     if (R == 16)
         return W == 1 ? run_place<16, 1, NL, false>(a, p, st) : run_place<16, 2, NL, false>(a, p, st);

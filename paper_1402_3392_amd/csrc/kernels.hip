@@ -81,6 +81,9 @@ __device__ __forceinline__ Lanes lane_geometry(uint32_t log2N)
 // breadth-first order puts every coder's first digit before any second one:
 //   pos + #{lanes below j with d >= 1}  and
 //   pos + #{lanes with d >= 1} + #{lanes below j with d >= 2}.
+// Escape coding (a.esc; 16-bit symbols, depth-first): a lane that decodes the
+// escape E = alphabet - 1 then reads 16/R raw digits right after its own
+// renormalisation digits; they hold its output value.
 
 template <int R, int W, int SW, int LAYOUT, bool FULL>
 __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
@@ -150,13 +153,18 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
         }
         const bool n1 = act && x < L;
         const bool n2 = R == 8 && act && x < (L >> 8);
+        const bool ne = act && a.esc && s == a.alphabet - 1;
         const uint64_t m1 = ballot(n1);
         const uint64_t m2 = R == 8 ? ballot(n2) : 0ull;
+        const uint64_t me = ballot(ne);
         const uint32_t b1 = FULL ? prefix(m1) : popc(m1 & g.below);
         const uint32_t b2 = FULL ? prefix(m2) : popc(m2 & g.below);
+        const uint32_t be = FULL ? prefix(me) : popc(me & g.below);
         const uint32_t t1 = FULL ? popc(m1) : popc(m1 & g.segmask);
         const uint32_t t2 = FULL ? popc(m2) : popc(m2 & g.segmask);
-        const uint32_t o = a.bf ? b1 : b1 + b2;
+        const uint32_t te = FULL ? popc(me) : popc(me & g.segmask);
+        constexpr uint32_t RW = 16 / R;  // raw digits of an escaped value
+        const uint32_t o = a.bf ? b1 : b1 + b2 + RW * be;
         if (n1) {
             uint32_t idx = pos + o;
             uint32_t d = 0;
@@ -175,7 +183,19 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
                 x = (x << 8) | d;
             }
         }
-        pos += t1 + t2;
+        if (ne) {
+            uint32_t idx = pos + o + (n1 ? 1u : 0u) + (n2 ? 1u : 0u), v = 0;
+            for (uint32_t q = 0; q < RW; ++q, ++idx) {
+                uint32_t d = 0;
+                if (idx < ndig)
+                    d = R == 16 ? reinterpret_cast<const uint16_t*>(dig)[idx] : dig[idx];
+                else
+                    bad = true;
+                v = (v << R) | d;
+            }
+            s = v;
+        }
+        pos += t1 + t2 + RW * te;
         if (act)
             out[i] = static_cast<OutT>(s);
     }
@@ -198,6 +218,9 @@ __global__ void __launch_bounds__(kMaxThreads) k_decode(const DecodeArgs a)
 // The digits of the step are prepended as one block laid out like the
 // decoder reads it: coders ascending, each coder's high digit first, in
 // depth-first or breadth-first order (as the decoder above describes).
+// Escape coding (a.esc): a value the table lacks (v >= E = alphabet - 1 or
+// f_v = 0) is coded as E, and the lane also emits 16/R raw digits holding
+// v, after its renormalisation digits in decoder order.
 
 template <int R, int W, bool FULL>
 __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
@@ -233,9 +256,12 @@ __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
     for (uint32_t t = steps; t-- > 0;) {
         const uint64_t i = uint64_t(t) * N + g.j;
         bool act = i < nsym;
-        uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
-        s = min(s, a.alphabet);  // entry `alphabet` has f = 0
-        const uint4 e = l_enc[s];
+        const uint32_t v = act ? static_cast<uint32_t>(in[i]) : 0u;
+        uint32_t s = min(v, a.alphabet);  // entry `alphabet` has f = 0
+        uint4 e = l_enc[s];
+        const bool esc = act && a.esc && (v >= a.alphabet - 1 || (e.y & 0xFFFFu) == 0);
+        if (esc)
+            e = l_enc[a.alphabet - 1];
         const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16;
         if (act && f == 0) {
             nosym = true;
@@ -245,13 +271,32 @@ __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
         const bool e2 = R == 8 && act && (x >> (sh + 8)) >= f;
         const uint64_t m1 = ballot(e1);
         const uint64_t m2 = R == 8 ? ballot(e2) : 0ull;
+        const bool emit_raw = esc && act;
+        const uint64_t me = ballot(emit_raw);
         const uint32_t b1 = FULL ? prefix(m1) : popc(m1 & g.below);
         const uint32_t b2 = FULL ? prefix(m2) : popc(m2 & g.below);
+        const uint32_t be = FULL ? prefix(me) : popc(me & g.below);
         const uint32_t t1 = FULL ? popc(m1) : popc(m1 & g.segmask);
         const uint32_t t2 = FULL ? popc(m2) : popc(m2 & g.segmask);
-        wpos -= t1 + t2;
+        const uint32_t te = FULL ? popc(me) : popc(me & g.segmask);
+        constexpr uint32_t RW = 16 / R;  // raw digits of an escaped value
+        wpos -= t1 + t2 + RW * te;
+        if (emit_raw) {
+            uint32_t idx = wpos + b1 + b2 + RW * be + (e1 ? 1u : 0u) + (e2 ? 1u : 0u);
+            for (uint32_t q = 0; q < RW; ++q, ++idx) {
+                const uint32_t d = (v >> (R * (RW - 1 - q))) & ((1u << R) - 1);
+                if (idx < cap) {
+                    if (R == 16)
+                        reinterpret_cast<uint16_t*>(slot)[idx] = static_cast<uint16_t>(d);
+                    else
+                        slot[idx] = static_cast<uint8_t>(d);
+                } else {
+                    overflow = true;
+                }
+            }
+        }
         if (e1) {
-            const uint32_t idx = wpos + (a.bf ? b1 : b1 + b2);
+            const uint32_t idx = wpos + (a.bf ? b1 : b1 + b2 + RW * be);
             if (R == 16) {
                 if (idx < cap)
                     reinterpret_cast<uint16_t*>(slot)[idx] = static_cast<uint16_t>(x);

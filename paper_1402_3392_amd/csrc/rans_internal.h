@@ -57,6 +57,7 @@ struct DecodeArgs {
     uint32_t k, l;
     uint32_t alphabet;
     uint32_t bf;         // breadth-first digit order (Section 5)
+    uint32_t esc;        // escape coding with raw digits (16-bit symbols)
     const void* lut;     // fused consumer: alphabet entries of lut_w bytes (device)
     uint32_t lut_w;      // 0 (symbol output), 2 or 4
     const void* tab0;    // kPacked: dec; kTwoLevel: sym
@@ -75,6 +76,7 @@ struct EncodeArgs {
     uint32_t k, l;
     uint32_t alphabet;
     uint32_t bf;          // breadth-first digit order (Section 5)
+    uint32_t esc;         // escape coding with raw digits (16-bit symbols)
     const uint4* enc;     // alphabet + 1 entries
     uint32_t enc_bytes;   // multiple of 16
     uint8_t* slots;       // n_chunks slots, slot_stride apart

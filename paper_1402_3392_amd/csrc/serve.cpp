@@ -245,6 +245,8 @@ extern "C" int rans_server_create(const rans_server_config* cfg, rans_server** o
     int rc = check_params(&cfg->params);
     if (rc != RANS_OK)
         return rc;
+    if (cfg->params.escape)  // requests run on the batched kernels
+        return RANS_EINVAL;
     rans_server* s = new rans_server();
     s->budget = cfg->hbm_budget;
     s->params = cfg->params;

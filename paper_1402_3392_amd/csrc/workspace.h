@@ -58,7 +58,8 @@ EncodeLayout encode_layout(uint64_t n_chunks, uint32_t N, uint64_t slot_bytes);
 int check_params(const rans_params* p);
 uint32_t log2u(uint32_t v);
 uint32_t max_digits(uint32_t k, uint32_t r);
-uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r);
+uint32_t raw_digits(uint32_t r);
+uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r, bool esc = false);
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch);
 int parse_header(const uint8_t* h, uint64_t in_len, Header* out);
 bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra = 0);

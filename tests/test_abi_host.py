@@ -85,6 +85,15 @@ def test_params_check(lr):
     assert lr.rans_encode_bound(1000, p) == 0
     with pytest.raises(ValueError):
         lr.rans_params.make(15, 8, 23, 1, 64, 4096, "zz")
+    # escape coding: 16-bit symbols, depth-first only
+    assert lr.rans_params_check(lr.rans_params.make(15, 8, 23, 2, 64, 4096, "df", True)) == 0
+    assert lr.rans_params_check(lr.rans_params.make(15, 8, 23, 1, 64, 4096, "df", True)) \
+        == lr.RANS_EINVAL
+    assert lr.rans_params_check(lr.rans_params.make(15, 8, 23, 2, 64, 4096, "bf", True)) \
+        == lr.RANS_EINVAL
+    p = lr.rans_params.make(15, 8, 23, 2, 64, 4096)
+    p.escape = 2
+    assert lr.rans_params_check(p) == lr.RANS_EINVAL
 
 
 def test_encode_bound_covers_oracle(lr):
@@ -97,6 +106,16 @@ def test_encode_bound_covers_oracle(lr):
             bound = lr.rans_encode_bound(n, p)
             assert bound == oracle.encode_bound(n, k, r, N, C)
             assert oracle.encode(f, syms, k, r, l, N, C).size <= bound
+
+
+def test_encode_bound_with_escapes_covers_oracle(lr):
+    rng = np.random.default_rng(23)
+    for k, r, l, N, C in [(12, 16, 16, 64, 4096), (15, 8, 23, 32, 1000), (10, 8, 16, 4, 0)]:
+        v = rng.integers(0, 65536, 12345).astype(np.uint16)  # nearly every value escapes
+        counts = np.bincount(np.minimum(v, 99), minlength=100).astype(np.uint64)
+        f = oracle.quantize(counts, k)
+        p = lr.rans_params.make(k, r, l, 2, N, C, "df", True)
+        assert lr.rans_encode_bound(v.size, p) >= oracle.encode(f, v, k, r, l, N, C, escape=True).size
 
 
 def test_division_constants(lr):
