@@ -73,12 +73,13 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="roundtrip",
-                    choices=["roundtrip", "batched", "sweep", "serving", "dequant"],
+                    choices=["roundtrip", "batched", "sweep", "serving", "dequant", "escape"],
                     help="roundtrip: the headline line (3 x 256 MiB encode+decode); "
                          "batched: 4096 uneven streams, one persistent launch vs plain calls; "
                          "sweep: radix/precision/alphabet sweep, batched vs plain decode; "
                          "serving: Poisson request loop, p50/p99 latency; "
-                         "dequant: decode fused with a codebook lookup vs decode + gather")
+                         "dequant: decode fused with a codebook lookup vs decode + gather; "
+                         "escape: escape coding with raw digits vs the clipped stream")
     ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
     ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
@@ -485,6 +486,77 @@ def run_dequant(args):
     print(json.dumps(out), flush=True)
 
 
+def run_escape(args):
+    """Escape coding (raw digits in the interleaved stream): 64 MiB of 16-bit
+    zigzag Laplace values (scale 300), coded with a 1024-symbol table whose
+    last symbol is the escape, against the same stream without the raw
+    digits (every value clipped to the table)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1402_3392_amd as lr
+
+    K, R, L, W, N, C, T = 15, 16, 16, 2, 64, 32768, 1024
+    n = (1 << 26) // W
+    log(f"generating {n} zigzag Laplace values")
+    rng = np.random.Generator(np.random.PCG64(7001))
+    v = datagen.sample(datagen.laplace_u16_probs(300.0), n, rng, np.uint16)
+    counts = np.bincount(np.minimum(v, T - 1), minlength=T).astype(np.uint64)
+    table = lr.rans_tables_build(counts, K)
+    esc_frac = float((v >= T - 1).mean())
+    res, sizes = {}, {}
+    d_in = torch.from_numpy(v.view(np.uint8)).cuda()
+    d_clip = torch.from_numpy(np.minimum(v, T - 2).astype(np.uint16).view(np.uint8)).cuda()
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+    lens = torch.zeros(2, dtype=torch.int64, device="cuda")
+    for name, src, esc in (("escape", d_in, True), ("clipped", d_clip, False)):
+        params = lr.rans_params.make(K, R, L, W, N, C, "df", esc)
+        cap = lr.rans_encode_bound(n, params)
+        cont = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        clen = lr.rans_encode(table, params, src, n, cont, cap)
+        hdr = bytes(cont[:32].cpu().numpy().tobytes())
+        out = torch.empty(n * W, dtype=torch.uint8, device="cuda")
+        i = 0 if esc else 1
+
+        def enc():
+            lr.rans_encode_async(table, params, src, n, cont, cap, lens[i:i + 1], st[2 * i:2 * i + 1])
+
+        def dec():
+            lr.rans_decode_async(table, cont, clen, hdr, out, n, st[2 * i + 1:2 * i + 2])
+
+        for fn_name, fn in (("encode", enc), ("decode", dec)):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            torch.cuda.synchronize()
+            res[f"{name}_{fn_name}"] = timed(fn, max(5, args.steps))
+        assert int(st.abs().sum()) == 0, f"status {st.tolist()}"
+        assert torch.equal(out, src), f"{name}: decode mismatch"
+        sizes[name] = clen
+        log(f"{name}: {clen / (n * W):.4f} of input; encode {res[name + '_encode'] * 1e6:.1f} us, "
+            f"decode {res[name + '_decode'] * 1e6:.1f} us")
+    t = res["escape_decode"]
+    alg = sizes["escape"] + n * W + 4 * T
+    out = base_result("rANS escape-coded decode, GB/s of 16-bit symbols", round(n * W / t / 1e9, 2),
+                      "GB/s", args,
+                      {"workload": f"{n * W >> 20} MiB of uint16 zigzag Laplace(300) values, "
+                                   f"{T}-symbol table with escape (16 raw bits), M=2^{K}, "
+                                   f"b=L=2^16, N=64, 64 KiB chunks"})
+    out.update({
+        "escaped_fraction": round(esc_frac, 4),
+        "escape_ratio": round(sizes["escape"] / (n * W), 4),
+        "clipped_ratio": round(sizes["clipped"] / (n * W), 4),
+        "escape_encode_gbps": round(n * W / res["escape_encode"] / 1e9, 2),
+        "escape_decode_gbps": round(n * W / res["escape_decode"] / 1e9, 2),
+        "clipped_encode_gbps": round(n * W / res["clipped_encode"] / 1e9, 2),
+        "clipped_decode_gbps": round(n * W / res["clipped_decode"] / 1e9, 2),
+        "roofline": {"bound": "hbm", "kernel": "k_decode64 (escape)", "unit": "GB/s",
+                     "achieved": round(alg / t / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "frac": round(alg / t / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None},
+    })
+    print(json.dumps(out), flush=True)
+
+
 def run_serving(args):
     """Request loop: Poisson arrivals of mixed encode/decode requests under an
     8 GiB HBM budget, rates swept around the saturated throughput; p50/p99
@@ -573,7 +645,7 @@ def main():
         return
     if args.workload != "roundtrip":
         {"batched": run_batched, "sweep": run_sweep, "serving": run_serving,
-         "dequant": run_dequant}[args.workload](args)
+         "dequant": run_dequant, "escape": run_escape}[args.workload](args)
         return
 
     import numpy as np

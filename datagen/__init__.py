@@ -60,6 +60,16 @@ def gaussian_codes_probs(n: int = 256, sigma: float = 24.0) -> np.ndarray:
     return p / p.sum()
 
 
+def laplace_u16_probs(scale: float = 300.0) -> np.ndarray:
+    """Signed integers d with p(d) proportional to exp(-|d| / scale) (prediction
+    residuals, transform coefficients), stored as 16-bit values through the
+    zigzag map d >= 0 -> 2d, d < 0 -> -2d - 1: p over 0..65535."""
+    z = np.arange(65536, dtype=np.float64)
+    d = np.where(z % 2 == 0, z / 2, (z + 1) / 2)
+    p = np.exp(-d / scale)
+    return p / p.sum()
+
+
 def entropy_bits(p: np.ndarray) -> float:
     p = np.asarray(p, dtype=np.float64)
     p = p[p > 0]

@@ -510,16 +510,25 @@ constexpr uint32_t kFlushStores = 8;
 // is emitted once x < x_max; x_max >= 2^32 is stored as 2^32 - 1, which no
 // state exceeds) and bad = (f == 0), a symbol the table cannot encode.  The
 // kernel then compares against x_max - 1 directly and reads every field
-// with sub-dword operand selects.
-__device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32_t bytes, uint32_t sh)
+// with sub-dword operand selects.  esc (escape coding): the escape symbol;
+// every entry the coder cannot use directly -- frequency 0, or at or above
+// the escape (the extra last entry included) -- becomes a copy of the
+// escape's entry with bit 31 of z set, so one LDS read gives both the entry
+// to code and whether raw digits follow.
+__device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32_t bytes, uint32_t sh,
+                                          uint32_t esc = ~0u)
 {
     uint4* d = reinterpret_cast<uint4*>(lds);
     for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) {
-        const uint4 e = src[i];
+        uint4 e = src[i];
+        const bool raw = esc != ~0u && (i >= esc || (e.y & 0xFFFFu) == 0);
+        if (raw)
+            e = src[esc];
         const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16, sh1 = e.z & 0xFFu, sh2 = e.z >> 8;
         const uint64_t xm = uint64_t(f) << sh;
         d[i] = make_uint4(e.x, (f == 0 || xm > 0xFFFFFFFFull) ? 0xFFFFFFFFu : static_cast<uint32_t>(xm - 1),
-                          cum | (sh2 << 16), e.w | (f == 0 ? (1u << 23) : 0u) | (sh1 << 24));
+                          cum | (sh2 << 16) | (raw ? 1u << 31 : 0u),
+                          e.w | (f == 0 ? (1u << 23) : 0u) | (sh1 << 24));
     }
 }
 
@@ -571,7 +580,7 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
         // Granlund-Montgomery multiply-high division
         const uint32_t th = __umulhi(e.x, x);
-        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> (e.z >> 16);
+        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> ((e.z >> 16) & 31u);
         x = __umul24(q, e.w) + x + (e.z & 0xFFFFu);
     }
 }
@@ -581,17 +590,15 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
 // the escape E otherwise; an escape lane also emits 16 raw bits holding v.
 // The decoder reads them after the lane's renormalisation digits, so they
 // follow those digits in the stream (Section 3: the encoder sends raw data
-// just before it encodes the symbol they belong to).  e: the staged entry of
-// min(v, alphabet), whose bad bit marks f_v = 0; eE: the escape's entry.
+// just before it encodes the symbol they belong to).  e: the entry staged
+// for min(v, alphabet) by stage_enc with the escape, which is already the
+// escape's entry, with bit 31 of z set, when v must escape.
 template <int R>
-__device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32_t& bad, uint4 e,
-                                             const uint4& eE, uint32_t v, uint32_t E, bool act,
-                                             uint8_t* dring, uint32_t lane)
+__device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32_t& bad, const uint4& e,
+                                             uint32_t v, bool act, uint8_t* dring, uint32_t lane)
 {
     constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
-    const bool esc = act && (v >= E || ((e.w >> 23) & 1u));
-    if (esc)
-        e = eE;
+    const bool esc = act && (e.z >> 31) != 0;
     if (act)
         bad |= e.w;
     const bool e1 = act && x > e.y;
@@ -622,7 +629,7 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
     }
     if (act) {
         const uint32_t th = __umulhi(e.x, x);
-        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> (e.z >> 16);
+        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> ((e.z >> 16) & 31u);
         x = __umul24(q, e.w) + x + (e.z & 0xFFFFu);
     }
 }
@@ -639,8 +646,9 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
 // kFlushStores stores with stores to the 256 bytes after the slot.  A fixed
 // number of memory operations per block lets the compiler's wait for the
 // symbols of the next block leave the recent stores in flight.  BF: as in
-// enc_step.  ESC: escape coding, as in enc_step_esc (a 1 KiB block of 16-bit
-// symbols still emits at most 2 KiB: 4 bytes per symbol).
+// enc_step.  ESC: escape coding, as in enc_step_esc; l_enc staged with the
+// escape (a 1 KiB block of 16-bit symbols still emits at most 2 KiB: 4
+// bytes per symbol).
 template <int R, int W, int NL, bool BF = false, bool ESC = false>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
@@ -663,8 +671,6 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     const uint32_t steps = (nsym + NL - 1) / NL;
     const uint32_t nblk = nsym / (NL * SPB);  // whole blocks
     const uint32_t top = uni(static_cast<uint32_t>(slot_bytes / DB));
-    const uint32_t E = alphabet - 1;                 // the escape (ESC)
-    const uint4 eE = ESC ? l_enc[E] : make_uint4(0, 0, 0, 0);
     uint32_t x = 1u << l;
     uint32_t wpos = top;  // lowest digit written so far
     uint32_t wtop = top;  // digits from wtop up are in the slot
@@ -694,7 +700,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
         if (ESC)
-            enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], eE, s, E, act, dring, lane);
+            enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], s, act, dring, lane);
         else
             enc_step<R, BF>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
     }
@@ -728,7 +734,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
                 if (q - PF >= 0)
                     ent[q - PF] = entry(q - PF);
                 if (ESC)
-                    enc_step_esc<R>(x, wpos, bad, ent[q], eE, sy[q], E, live, dring, lane);
+                    enc_step_esc<R>(x, wpos, bad, ent[q], sy[q], live, dring, lane);
                 else
                     enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
             }

@@ -13,7 +13,7 @@ template <int R, int W, int NL, bool BF, bool ESC>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    c64::stage_enc(lds, a.enc, a.enc_bytes, a.l + R - a.k);
+    c64::stage_enc(lds, a.enc, a.enc_bytes, a.l + R - a.k, ESC ? a.alphabet - 1 : ~0u);
     __syncthreads();
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
     uint32_t t = 0;
