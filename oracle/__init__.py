@@ -86,6 +86,7 @@ def _bind(lib):
                                      u64, u64p, i32]
     lib.orc_encode_bound_raw.argtypes = [u64, u32, u32, u32, u32, u32]
     lib.orc_encode_bound_raw.restype = u64
+    lib.orc_pfx_code.argtypes = [u32p, u32, u32, u32p, u32p]
     lib.orc_decode.argtypes = [u32p, u32, u8p, u64, u8p, u64, u64p, i32]
     lib.orc_header.argtypes = [u8p, u64, u64p]
     return lib
@@ -181,12 +182,25 @@ def encode_bound(n: int, k: int, r: int, N: int, C: int) -> int:
     return int(_load().orc_encode_bound(n, k, r, N, C))
 
 
+def prefix_code(f, k: int) -> tuple[np.ndarray, np.ndarray]:
+    """(lengths, codes) of the canonical prefix code for frequencies f."""
+    f = _u32(f)
+    ln = np.zeros(len(f), np.uint32)
+    cd = np.zeros(len(f), np.uint32)
+    _check(_load().orc_pfx_code(_p(f, ct.c_uint32), len(f), k, _p(ln, ct.c_uint32),
+                                _p(cd, ct.c_uint32)), "prefix_code")
+    return ln, cd
+
+
 def encode(f, syms: np.ndarray, k: int, r: int, l: int, N: int, C: int,
-           threads: int = 1, order: str = "df", escape: bool = False) -> np.ndarray:
+           threads: int = 1, order: str = "df", escape: bool = False,
+           coder: str = "rans") -> np.ndarray:
     """Encodes a symbol array (uint8 or uint16) into a container (uint8 array).
     order: digit order of the chunk streams, 'df' depth-first or 'bf'
     breadth-first (Section 5).  escape: escape coding with raw digits
-    (uint16 symbols, depth-first; the last symbol of f is the escape).  Both
+    (uint16 symbols, depth-first; the last symbol of f is the escape).
+    coder 'prefix': the prefix-code family multiplexed by the instrumented
+    decoder (Section 4; r must be 16, l is recorded but unused).  All three
     are recorded in header byte 9."""
     f = _u32(f)
     syms = np.ascontiguousarray(syms)
@@ -196,12 +210,16 @@ def encode(f, syms: np.ndarray, k: int, r: int, l: int, N: int, C: int,
     n = syms.size
     nraw = (8 * w + r - 1) // r if escape else 0
     cap = int(_load().orc_encode_bound_raw(n, k, r, N, C, nraw))
+    if coder == "prefix":  # a word per symbol at most, plus one per coder and chunk
+        cap = encode_bound(n, 16, 16, N, C) + 2 * N * (n // max(C, 1) + 2)
+    elif coder != "rans":
+        raise ValueError("coder must be 'rans' or 'prefix'")
     out = np.zeros(cap, dtype=np.uint8)
     olen = ct.c_uint64()
     raw = syms.view(np.uint8).reshape(-1) if n else np.zeros(1, dtype=np.uint8)
     if order not in ("df", "bf"):
         raise ValueError("order must be 'df' or 'bf'")
-    flags = (1 if order == "bf" else 0) | (2 if escape else 0)
+    flags = (1 if order == "bf" else 0) | (2 if escape else 0) | (4 if coder == "prefix" else 0)
     rc = _load().orc_encode_flags(_p(f, ct.c_uint32), len(f), k, r, l, w, N, C, flags,
                                   _p(raw, ct.c_uint8), n, _p(out, ct.c_uint8), cap,
                                   ct.byref(olen), threads)
@@ -211,12 +229,13 @@ def encode(f, syms: np.ndarray, k: int, r: int, l: int, N: int, C: int,
 
 def header(container: np.ndarray) -> dict:
     buf = np.ascontiguousarray(container, dtype=np.uint8)
-    h = np.zeros(10, dtype=np.uint64)
+    h = np.zeros(11, dtype=np.uint64)
     _check(_load().orc_header(_p(buf, ct.c_uint8), buf.size, _p(h, ct.c_uint64)), "header")
-    keys = ("k", "r", "l", "w", "N", "C", "n", "n_chunks", "order", "nraw")
+    keys = ("k", "r", "l", "w", "N", "C", "n", "n_chunks", "order", "nraw", "prefix")
     d = {kk: int(v) for kk, v in zip(keys, h)}
     d["order"] = "bf" if d["order"] else "df"
     d["escape"] = d["nraw"] > 0
+    d["coder"] = "prefix" if d.pop("prefix") else "rans"
     return d
 
 

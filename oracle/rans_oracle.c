@@ -49,6 +49,13 @@
  *       v < E and f_v > 0, else as E followed by 16/r raw digits holding v
  *       (most significant first); in each coder's share of a step the raw
  *       digits follow the renormalisation digits; depth-first order only.
+ *   Q17 Section 4's multiplexer needs a second coder family, which the paper
+ *       leaves open: a canonical prefix code with lengths
+ *       max(1, ceil(log2(M/f_s))), 16-bit words, a decoder that reads one
+ *       word whenever it holds fewer than 16 bits before a symbol.  The N
+ *       coders' streams are multiplexed in the order that decoder reads
+ *       them; a chunk stream starts with the N coders' bit counts (u32, an
+ *       end check) instead of rANS states.  Header byte 9 = 4, r = 16.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -548,6 +555,229 @@ out:
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* A second coder family for Section 4's multiplexer (reading Q17): a static
+ * canonical prefix code.  Code lengths come from the quantised frequencies,
+ * len_s = max(1, ceil(log2(M / f_s))) for f_s > 0 and none for f_s = 0, so
+ * sum 2^-len_s <= sum f_s / M = 1 (Kraft) and len_s <= k.  Codes are
+ * canonical: symbols ordered by (length, index) take consecutive values, the
+ * value doubling whenever the length grows.  Bits are written most
+ * significant first into 16-bit words. */
+typedef struct {
+    uint32_t n, maxlen;
+    uint32_t *len, *code;
+    uint32_t first[17], count[17], start[17]; /* canonical decoding, per length */
+    uint32_t *sorted;                         /* symbols by (length, index)     */
+} pfx_t;
+
+static void pfx_free(pfx_t *c)
+{
+    free(c->len);
+    free(c->code);
+    free(c->sorted);
+}
+
+static int pfx_init(pfx_t *c, const uint32_t *f, uint32_t n, uint32_t k)
+{
+    uint64_t M = (uint64_t)1 << k;
+    uint32_t s, l, next = 0, m = 0;
+    memset(c, 0, sizeof(*c));
+    if (n == 0 || k < 1 || k > 16)
+        return ORC_EINVAL;
+    c->n = n;
+    c->len = (uint32_t *)calloc(n, sizeof(uint32_t));
+    c->code = (uint32_t *)calloc(n, sizeof(uint32_t));
+    c->sorted = (uint32_t *)calloc(n, sizeof(uint32_t));
+    if (!c->len || !c->code || !c->sorted) {
+        pfx_free(c);
+        return ORC_ENOMEM;
+    }
+    for (s = 0; s < n; s++) {
+        if (f[s] == 0)
+            continue;
+        l = 0;
+        while ((uint64_t)f[s] << l < M) /* smallest l with f 2^l >= M */
+            l++;
+        c->len[s] = l < 1 ? 1 : l;
+        if (c->len[s] > c->maxlen)
+            c->maxlen = c->len[s];
+    }
+    for (l = 1; l <= c->maxlen; l++) {
+        c->first[l] = next;
+        c->start[l] = m;
+        for (s = 0; s < n; s++)
+            if (c->len[s] == l) {
+                c->code[s] = next++;
+                c->sorted[m++] = s;
+                c->count[l]++;
+            }
+        next <<= 1;
+    }
+    return ORC_OK;
+}
+
+/* Bit reader of one coder's decoder: before each symbol, while fewer than
+ * 16 bits are buffered it reads one 16-bit word (one at most, since a code
+ * has at most 16 bits); the symbol is the one whose code equals the next
+ * len bits for the length len that matches (canonical decoding). */
+typedef struct {
+    uint64_t buf;
+    uint32_t nb;
+    uint64_t used; /* bits consumed */
+} bitrd_t;
+
+static int pfx_decode_symbol(const pfx_t *c, bitrd_t *d, uint32_t *s_out)
+{
+    uint32_t l;
+    for (l = 1; l <= c->maxlen && l <= d->nb; l++) {
+        uint32_t v = (uint32_t)((d->buf >> (d->nb - l)) & (((uint64_t)1 << l) - 1));
+        if (v >= c->first[l] && v - c->first[l] < c->count[l]) {
+            *s_out = c->sorted[c->start[l] + (v - c->first[l])];
+            d->nb -= l;
+            d->buf &= ((uint64_t)1 << d->nb) - 1;
+            d->used += l;
+            return ORC_OK;
+        }
+    }
+    return ORC_ECORRUPT;
+}
+
+/* Encodes one chunk with N prefix coders (symbol i -> coder i mod N), each
+ * into a stream of its own, then multiplexes them by running the
+ * instrumented decoder of Section 4: the N decoders run in the decoding
+ * order (steps, coders ascending), and every word one of them reads from its
+ * own stream is appended to the multiplexed stream at once.  bits[j] receives
+ * coder j's code bits; words[0 .. *nwords) the multiplexed stream. */
+static int encode_pfx(const pfx_t *c, uint32_t N, const uint32_t *syms, uint64_t len,
+                      uint64_t *bits, uint32_t *words, uint64_t cap, uint64_t *nwords)
+{
+    uint32_t **st = (uint32_t **)calloc(N, sizeof(uint32_t *));
+    uint64_t *nst = (uint64_t *)calloc(N, sizeof(uint64_t)), *rd = (uint64_t *)calloc(N, sizeof(uint64_t));
+    bitrd_t *dec = (bitrd_t *)calloc(N, sizeof(bitrd_t));
+    uint64_t i, m = 0, per = len / N + 2;
+    uint32_t j;
+    int rc = ORC_OK;
+    if (!st || !nst || !rd || !dec) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    /* 1. each coder writes its symbols' codes into its own stream */
+    for (j = 0; j < N; j++) {
+        uint64_t acc = 0, t;
+        uint32_t nacc = 0;
+        st[j] = (uint32_t *)calloc(per + 2, sizeof(uint32_t)); /* <= 16 bits per symbol */
+        if (!st[j]) {
+            rc = ORC_ENOMEM;
+            goto out;
+        }
+        bits[j] = 0;
+        for (t = j; t < len; t += N) {
+            uint32_t s = syms[t];
+            if (s >= c->n || c->len[s] == 0) {
+                rc = ORC_ENOSYM;
+                goto out;
+            }
+            acc = (acc << c->len[s]) | c->code[s];
+            nacc += c->len[s];
+            bits[j] += c->len[s];
+            while (nacc >= 16) {
+                st[j][nst[j]++] = (uint32_t)(acc >> (nacc - 16)) & 0xFFFF;
+                nacc -= 16;
+                acc &= ((uint64_t)1 << nacc) - 1;
+            }
+        }
+        if (nacc > 0) /* the last word, zero padded */
+            st[j][nst[j]++] = (uint32_t)(acc << (16 - nacc)) & 0xFFFF;
+        /* the decoder may read one more word than the bits fill: a word of
+         * zeros (st was zero-initialised), present as long as it is read */
+        nst[j]++;
+    }
+    /* 2. the instrumented decoder */
+    for (i = 0; i < len; i++) {
+        uint32_t s;
+        j = (uint32_t)(i % N);
+        if (dec[j].nb < 16) {
+            uint32_t w;
+            if (rd[j] >= nst[j]) {
+                rc = ORC_EINVAL;
+                goto out;
+            }
+            w = st[j][rd[j]++];
+            if (m >= cap) {
+                rc = ORC_ENOSPC;
+                goto out;
+            }
+            words[m++] = w; /* what the decoder reads, in the order it reads it */
+            dec[j].buf = (dec[j].buf << 16) | w;
+            dec[j].nb += 16;
+        }
+        rc = pfx_decode_symbol(c, &dec[j], &s);
+        if (rc != ORC_OK || s != syms[i]) {
+            rc = ORC_EINVAL;
+            goto out;
+        }
+    }
+    *nwords = m;
+out:
+    if (st)
+        for (j = 0; j < N; j++)
+            free(st[j]);
+    free(st);
+    free(nst);
+    free(rd);
+    free(dec);
+    return rc;
+}
+
+/* Decodes one chunk from the multiplexed stream: the same decoders, reading
+ * one shared stream.  End check: every coder consumed exactly bits[j] bits
+ * and the stream is exhausted. */
+static int decode_pfx(const pfx_t *c, uint32_t N, const uint64_t *bits, const uint32_t *words,
+                      uint64_t nwords, uint32_t *syms, uint64_t len)
+{
+    bitrd_t *dec = (bitrd_t *)calloc(N, sizeof(bitrd_t));
+    uint64_t i, rd = 0;
+    uint32_t j;
+    int rc = ORC_OK;
+    if (!dec)
+        return ORC_ENOMEM;
+    for (i = 0; i < len; i++) {
+        j = (uint32_t)(i % N);
+        if (dec[j].nb < 16) {
+            if (rd >= nwords) {
+                rc = ORC_ECORRUPT;
+                goto out;
+            }
+            dec[j].buf = (dec[j].buf << 16) | words[rd++];
+            dec[j].nb += 16;
+        }
+        rc = pfx_decode_symbol(c, &dec[j], &syms[i]);
+        if (rc != ORC_OK)
+            goto out;
+    }
+    for (j = 0; j < N; j++)
+        if (dec[j].used != bits[j])
+            rc = ORC_ECORRUPT;
+    if (rd != nwords)
+        rc = ORC_ECORRUPT;
+out:
+    free(dec);
+    return rc;
+}
+
+/* Code lengths and code values of the prefix code (tests). */
+int orc_pfx_code(const uint32_t *f, uint32_t n, uint32_t k, uint32_t *len, uint32_t *code)
+{
+    pfx_t c;
+    int rc = pfx_init(&c, f, n, k);
+    if (rc != ORC_OK)
+        return rc;
+    memcpy(len, c.len, sizeof(uint32_t) * n);
+    memcpy(code, c.code, sizeof(uint32_t) * n);
+    pfx_free(&c);
+    return ORC_OK;
+}
+
 /* Digit-level entry points (tests).  order: 0 = depth-first, 1 = breadth-
  * first.  digits: caller buffer of cap entries; on success the stream is
  * moved to digits[0 .. *ndigits).  trace (optional, len entries): state of
@@ -684,6 +914,7 @@ typedef struct {
     uint32_t r, w, C;
     int order;     /* 0 depth-first, 1 breadth-first */
     uint32_t nraw; /* escape coding: raw digits per escaped value; 0 = off */
+    const pfx_t *pc; /* prefix-code family (Section 4 multiplexer), or NULL */
     const uint8_t *syms;
     uint64_t nsyms, nch;
     uint8_t **chunk_bytes;
@@ -701,7 +932,7 @@ static void *encode_worker(void *arg)
     job_t *jb = (job_t *)arg;
     uint64_t c;
     uint32_t *syms = (uint32_t *)malloc(sizeof(uint32_t) * (jb->C ? jb->C : 1));
-    uint64_t cap = (max_digits_per_symbol(jb->m->k, jb->r) + jb->nraw) * jb->C + 1;
+    uint64_t cap = (max_digits_per_symbol(jb->m->k, jb->r) + jb->nraw) * jb->C + jb->g.N + 1;
     uint32_t *dig = (uint32_t *)malloc(sizeof(uint32_t) * cap);
     uint64_t *states = (uint64_t *)malloc(sizeof(uint64_t) * jb->g.N);
     jb->rc = ORC_OK;
@@ -717,7 +948,20 @@ static void *encode_worker(void *arg)
         int rc;
         for (i = 0; i < len; i++)
             syms[i] = get_sym(jb->syms, jb->w, base + i);
-        if (jb->nraw)
+        if (jb->pc) {
+            /* multiplexed words go to the front of dig: at most one per
+             * symbol plus one per coder */
+            uint64_t nw = 0;
+            if (cap < len + jb->g.N) {
+                jb->rc = ORC_EINVAL;
+                goto out;
+            }
+            rc = encode_pfx(jb->pc, jb->g.N, syms, len, states, dig, cap, &nw);
+            if (rc == ORC_OK) {
+                memmove(dig + (cap - nw), dig, sizeof(uint32_t) * nw);
+                start = cap - nw;
+            }
+        } else if (jb->nraw)
             rc = encode_esc(jb->m, &jb->g, jb->nraw, syms, len, states, dig, cap, &start);
         else if (jb->order)
             rc = encode_bf(jb->m, &jb->g, syms, len, states, dig, cap, &start, NULL);
@@ -792,18 +1036,22 @@ static uint32_t raw_digits(uint32_t w, uint32_t r) { return (8 * w + r - 1) / r;
 
 /* Encodes nsyms symbols (w bytes each, little-endian) into a container.
  * flags (header byte 9): bit 0 breadth-first digit order, bit 1 escape
- * coding (16-bit symbols, depth-first only). */
+ * coding (16-bit symbols, depth-first only), bit 2 the prefix-code family
+ * multiplexed by the instrumented decoder (r = 16; alone). */
 int orc_encode_flags(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint32_t l,
                      uint32_t w, uint32_t N, uint32_t C, int flags, const uint8_t *syms,
                      uint64_t nsyms, uint8_t *out, uint64_t cap, uint64_t *out_len, int nthreads)
 {
     model_t m;
+    pfx_t pc;
     job_t jb;
     uint64_t nch, c, off, total;
     int rc = check_container_params(k, r, l, w, N);
     if (rc != ORC_OK)
         return rc;
-    if (flags < 0 || flags > 2 || (flags == 2 && w != 2))
+    if (flags != 0 && flags != 1 && flags != 2 && flags != 4)
+        return ORC_EINVAL;
+    if ((flags == 2 && w != 2) || (flags == 4 && r != 16))
         return ORC_EINVAL;
     if (C == 0) {
         if (nsyms > 0xFFFFFFFFull)
@@ -817,6 +1065,14 @@ int orc_encode_flags(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r
     if (rc != ORC_OK)
         return rc;
     memset(&jb, 0, sizeof(jb));
+    if (flags == 4) {
+        rc = pfx_init(&pc, f, n_alpha, k);
+        if (rc != ORC_OK) {
+            model_free(&m);
+            return rc;
+        }
+        jb.pc = &pc;
+    }
     jb.m = &m;
     jb.g.b = (uint64_t)1 << r;
     jb.g.L = (uint64_t)1 << l;
@@ -877,6 +1133,8 @@ out:
             free(jb.chunk_bytes[c]);
     free(jb.chunk_bytes);
     free(jb.chunk_len);
+    if (jb.pc)
+        pfx_free(&pc);
     model_free(&m);
     return rc;
 }
@@ -903,16 +1161,18 @@ int orc_encode(const uint32_t *f, uint32_t n_alpha, uint32_t k, uint32_t r, uint
 }
 
 typedef struct {
-    uint32_t k, r, l, w, N, C, order, nraw;
+    uint32_t k, r, l, w, N, C, order, nraw, pfx;
     uint64_t n, nch;
 } hdr_t;
 
 static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
 {
-    if (in_len < 32 || get_u32(in) != ORC_MAGIC || in[4] != 1 || in[9] > 2 ||
-        (in[9] == 2 && in[8] != 2))
+    if (in_len < 32 || get_u32(in) != ORC_MAGIC || in[4] != 1 ||
+        (in[9] != 0 && in[9] != 1 && in[9] != 2 && in[9] != 4) || (in[9] == 2 && in[8] != 2) ||
+        (in[9] == 4 && in[6] != 16))
         return ORC_ECORRUPT;
     h->order = in[9] & 1;
+    h->pfx = in[9] == 4;
     h->k = in[5];
     h->r = in[6];
     h->l = in[7];
@@ -931,8 +1191,9 @@ static int parse_header(const uint8_t *in, uint64_t in_len, hdr_t *h)
     return ORC_OK;
 }
 
-/* Reads the header fields: out[0..9] = k, r, l, w, N, C, n, n_chunks, digit
- * order, raw digits per escaped value (0: no escape coding). */
+/* Reads the header fields: out[0..10] = k, r, l, w, N, C, n, n_chunks, digit
+ * order, raw digits per escaped value (0: no escape coding), prefix-code
+ * family (0/1). */
 int orc_header(const uint8_t *in, uint64_t in_len, uint64_t *out)
 {
     hdr_t h;
@@ -949,6 +1210,7 @@ int orc_header(const uint8_t *in, uint64_t in_len, uint64_t *out)
     out[7] = h.nch;
     out[8] = h.order;
     out[9] = h.nraw;
+    out[10] = h.pfx;
     return ORC_OK;
 }
 
@@ -958,7 +1220,7 @@ static void *decode_worker(void *arg)
     const hdr_t *h = (const hdr_t *)jb->hdr;
     uint64_t c;
     uint32_t *syms = (uint32_t *)malloc(sizeof(uint32_t) * (h->C ? h->C : 1));
-    uint64_t cap = (max_digits_per_symbol(h->k, h->r) + h->nraw) * h->C + 1;
+    uint64_t cap = (max_digits_per_symbol(h->k, h->r) + h->nraw) * h->C + h->N + 1;
     uint32_t *dig = (uint32_t *)malloc(sizeof(uint32_t) * cap);
     uint64_t *states = (uint64_t *)malloc(sizeof(uint64_t) * h->N);
     jb->rc = ORC_OK;
@@ -988,7 +1250,9 @@ static void *decode_worker(void *arg)
         for (i = 0; i < nd; i++)
             dig[i] = h->r == 16 ? get_u16(jb->in + off + 4ull * h->N + 2 * i)
                                 : jb->in[off + 4ull * h->N + i];
-        if (h->nraw)
+        if (h->pfx)
+            rc = decode_pfx(jb->pc, h->N, states, dig, nd, syms, nsy);
+        else if (h->nraw)
             rc = decode_esc(jb->m, &jb->g, h->nraw, states, dig, nd, syms, nsy);
         else if (h->order)
             rc = decode_bf(jb->m, &jb->g, states, dig, nd, syms, nsy, NULL);
@@ -1013,6 +1277,7 @@ int orc_decode(const uint32_t *f, uint32_t n_alpha, const uint8_t *in, uint64_t 
                uint8_t *out_syms, uint64_t cap_syms, uint64_t *nsyms, int nthreads)
 {
     model_t m;
+    pfx_t pc;
     job_t jb;
     hdr_t h;
     uint64_t s;
@@ -1031,6 +1296,14 @@ int orc_decode(const uint32_t *f, uint32_t n_alpha, const uint8_t *in, uint64_t 
     if (rc != ORC_OK)
         return rc;
     memset(&jb, 0, sizeof(jb));
+    if (h.pfx) {
+        rc = pfx_init(&pc, f, n_alpha, h.k);
+        if (rc != ORC_OK) {
+            model_free(&m);
+            return rc;
+        }
+        jb.pc = &pc;
+    }
     jb.m = &m;
     jb.g.b = (uint64_t)1 << h.r;
     jb.g.L = (uint64_t)1 << h.l;
@@ -1043,6 +1316,8 @@ int orc_decode(const uint32_t *f, uint32_t n_alpha, const uint8_t *in, uint64_t 
     jb.out_syms = out_syms;
     jb.hdr = &h;
     rc = run_workers(&jb, nthreads, decode_worker);
+    if (jb.pc)
+        pfx_free(&pc);
     model_free(&m);
     return rc;
 }

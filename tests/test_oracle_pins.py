@@ -542,3 +542,111 @@ def test_escape_flags_checked():
         oracle.encode(f1, w1, 8, 16, 16, 4, 0, escape=True)  # 16-bit symbols only
     with pytest.raises(oracle.OracleError):
         oracle.encode(f, v, 12, 16, 16, 4, 0, order="bf", escape=True)
+
+
+# ------------------------------------ prefix-code family and its multiplexer --
+
+def _pfx_case(seed, n=5000, alpha=40, k=11):
+    rng = np.random.default_rng(seed)
+    p = 1.0 / np.arange(1, alpha + 1) ** 1.3
+    syms = rng.choice(alpha, size=n, p=p / p.sum()).astype(np.uint8)
+    f = oracle.quantize(np.bincount(syms, minlength=alpha).astype(np.uint64), k)
+    return syms, f
+
+
+def test_prefix_code_is_a_valid_canonical_code():
+    """Kraft, prefix-freedom by brute force, canonical order, and the Shannon
+    bound len < log2(M/f) + 1."""
+    for seed, alpha, k in [(41, 40, 11), (42, 256, 12), (43, 3, 8), (44, 1, 9)]:
+        _, f = _pfx_case(seed, alpha=alpha, k=k)
+        ln, cd = oracle.prefix_code(f, k)
+        used = [s for s in range(len(f)) if f[s] > 0]
+        assert all(ln[s] == 0 for s in range(len(f)) if f[s] == 0)
+        assert sum(2.0 ** -int(ln[s]) for s in used) <= 1.0
+        bits = {s: format(int(cd[s]), "0%db" % int(ln[s])) for s in used}
+        for a in used:
+            for b in used:
+                if a != b:
+                    assert not bits[b].startswith(bits[a]), (a, b)
+        order = sorted(used, key=lambda s: (int(ln[s]), s))
+        vals = [int(cd[s]) << (int(ln.max()) - int(ln[s])) for s in order]
+        assert vals == sorted(vals) and len(set(vals)) == len(vals)
+        M = 1 << k
+        for s in used:
+            assert 1 <= ln[s] <= k and 2.0 ** (int(ln[s]) - 1) < max(2.0, M / f[s]) * (1 + 1e-12)
+
+
+def _lane_streams(f, k, syms, N):
+    """Each coder's own word stream, built by concatenating code strings."""
+    ln, cd = oracle.prefix_code(f, k)
+    out = []
+    for j in range(N):
+        b = "".join(format(int(cd[s]), "0%db" % int(ln[s])) for s in syms[j::N])
+        b += "0" * ((-len(b)) % 16) + "0" * 16  # zero padding and the possible extra word
+        out.append([int(b[i:i + 16], 2) for i in range(0, len(b), 16)])
+    return out, ln
+
+
+def _read_schedule(ln, syms, N):
+    """Which coder reads at each read, from code lengths alone: a coder reads
+    a word before a symbol whenever it holds fewer than 16 bits."""
+    nb = [0] * N
+    order = []
+    for i, s in enumerate(syms):
+        j = i % N
+        if nb[j] < 16:
+            order.append(j)
+            nb[j] += 16
+        nb[j] -= int(ln[s])
+    return order
+
+
+@pytest.mark.parametrize("N", [1, 3, 32, 64])
+def test_prefix_mux_is_the_decoders_read_order(N):
+    """Section 4: the multiplexed stream is every coder's own stream, merged
+    in the order the decoders read it -- derived here from the code lengths
+    alone -- and decodes back to the input."""
+    syms, f = _pfx_case(45 + N)
+    k = 11
+    buf = oracle.encode(f, syms, k, 16, 16, N, 0, coder="prefix")
+    h = oracle.header(buf)
+    assert buf[9] == 4 and h["coder"] == "prefix"
+    assert (oracle.decode(f, buf) == syms).all()
+    (states, dig), = _chunk_streams(buf)
+    words = dig.view("<u2")
+    streams, ln = _lane_streams(f, k, syms, N)
+    order = _read_schedule(ln, syms, N)
+    pos = [0] * N
+    want = []
+    for j in order:
+        want.append(streams[j][pos[j]])
+        pos[j] += 1
+    assert words.tolist() == want
+    assert states.tolist() == [int(sum(int(ln[s]) for s in syms[j::N])) for j in range(N)]
+
+
+def test_prefix_mux_roundtrip_chunks_and_checks():
+    syms, f = _pfx_case(50, n=20_000, alpha=200, k=12)
+    for N, C in [(4, 1000), (64, 4096), (32, 777)]:
+        buf = oracle.encode(f, syms, 12, 16, 16, N, C, coder="prefix", threads=2)
+        assert (oracle.decode(f, buf) == syms).all()
+        (states, dig) = _chunk_streams(buf)[1]
+        # a wrong bit count fails the end check; a flipped bit is caught or decodes wrongly
+        bad = buf.copy()
+        off = int(np.frombuffer(bad[48:56].tobytes(), "<u8")[0])
+        bad[off] ^= 1
+        with pytest.raises(oracle.OracleError):
+            oracle.decode(f, bad)
+        bad = buf.copy()
+        bad[off + 4 * N + 7] ^= 0x10
+        try:
+            assert (oracle.decode(f, bad) != syms).any()
+        except oracle.OracleError:
+            pass
+    with pytest.raises(oracle.OracleError):
+        oracle.encode(f, syms, 12, 8, 23, 4, 0, coder="prefix")  # 16-bit words only
+    for flags in (3, 5, 6, 7, 8):
+        b = oracle.encode(f, syms[:100], 12, 16, 16, 4, 0, coder="prefix")
+        b[9] = flags
+        with pytest.raises(oracle.OracleError):
+            oracle.decode(f, b)
