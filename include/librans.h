@@ -23,7 +23,8 @@
  * Stream format (container).  All fields little-endian.
  *   header, 32 bytes: u32 magic 0x534E4172 ("rANS"), u8 version 1, u8 k,
  *     u8 r, u8 l, u8 w, u8 flags (bit 0: breadth-first digit order, bit 1:
- *     escape coding; not both), u16 N, u32 C, u64 n, u32 n_chunks, u32 0
+ *     escape coding, not both; or 4 alone: the prefix-code family below),
+ *     u16 N, u32 C, u64 n, u32 n_chunks, u32 0
  *   directory: n_chunks x { u64 offset, u32 length, u32 0 }
  *   chunk streams, each at a 16-byte aligned offset, zero padding between;
  *     the first at align16(32 + 16*n_chunks); the total length is
@@ -48,6 +49,21 @@
  *     16-bit value can be coded with a table of the frequent ones.  The
  *     one-wave-per-chunk and generic kernels support it; the batched entry
  *     points, the server and rans_decode_lut reject it (RANS_EINVAL).
+ *   prefix-code family (flags 4; r = 16, l recorded as 16 and unused): the
+ *     multiplexer of Section 4 applied to a second coder family, a canonical
+ *     prefix code with lengths max(1, ceil(log2(M / f_s))) (at most k bits;
+ *     symbols ordered by (length, index) take consecutive code values).
+ *     Coder j codes symbols j, j+N, ... into its own bit sequence (codes
+ *     most significant bit first, 16-bit words); its decoder reads one word
+ *     before a symbol whenever it holds fewer than 16 bits.  The chunk
+ *     stream is the N coders' bit counts (u32, in place of the states), then
+ *     their words in the order the N decoders, stepping through the chunk's
+ *     symbols, read them -- what an instrumented decoder copying every word
+ *     it reads produces -- so the stream needs no per-coder metadata.  The
+ *     last word of a coder is zero padded, and a coder whose rule reads one
+ *     word beyond its bits reads a word of zeros.  Decoding checks that every
+ *     coder consumed exactly its bit count.  Chunks are the periodic flush
+ *     that bounds the encoder's buffering.
  *     Every coder starts encoding in state L;
  *     when a chunk's length is not a multiple of N, the last step only
  *     involves coders 0 .. (len mod N)-1.
@@ -190,6 +206,20 @@ int rans_encode_async(const rans_table *table, const rans_params *params, const 
 int rans_decode_async(const rans_table *table, const void *d_in, uint64_t in_len,
                       const void *h_header, void *d_syms, uint64_t syms_cap, int32_t *d_status,
                       void *stream);
+
+/* Encode with the prefix-code family instead of rANS (format above; the
+ * container decodes with rans_decode / rans_decode_async, which read the
+ * family from the header).  params as for rans_encode with radix_bits 16,
+ * state_lbits 16, digit_order 0, escape 0, interleave 32 or 64, chunk_syms *
+ * sym_bytes a multiple of 16 and a 16-byte aligned d_syms; the table's
+ * alphabet at most 4096.  Otherwise RANS_EINVAL.  Errors, out_len and
+ * blocking as rans_encode / rans_encode_async. */
+int rans_pfx_encode(const rans_table *table, const rans_params *params, const void *d_syms,
+                    uint64_t n_syms, void *d_out, uint64_t out_cap, uint64_t *out_len,
+                    void *stream);
+int rans_pfx_encode_async(const rans_table *table, const rans_params *params, const void *d_syms,
+                          uint64_t n_syms, void *d_out, uint64_t out_cap, uint64_t *d_out_len,
+                          int32_t *d_status, void *stream);
 
 /* Decode fused with a table-lookup consumer (Section 6: the decoder is small
  * enough to be fused into the kernel that uses its output).  Output element

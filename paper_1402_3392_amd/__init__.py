@@ -110,6 +110,10 @@ _sig = {
                                      ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "rans_decode_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_char_p,
                                      ct.c_void_p, ct.c_uint64, ct.c_void_p, ct.c_void_p]),
+    "rans_pfx_encode": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
+                                   ct.c_uint64, _u64p, ct.c_void_p]),
+    "rans_pfx_encode_async": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
+                                         ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "rans_decode_lut": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_void_p, ct.c_uint32,
                                    ct.c_void_p, ct.c_uint64, _u64p, ct.c_void_p]),
     "rans_decode_lut_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_char_p,
@@ -285,6 +289,26 @@ def rans_decode_async(table: Table, d_in, in_len: int, header: bytes, d_syms, sy
     hb = bytes(header[:32])
     _check(_lib.rans_decode_async(table.handle, _ptr(d_in), in_len, hb, _ptr(d_syms), syms_cap,
                                   _ptr(d_status), _stream(stream)), "rans_decode_async")
+
+
+def rans_pfx_encode(table: Table, params, d_syms, n_syms: int, d_out, out_cap: int,
+                    stream=None) -> int:
+    """Encodes with the prefix-code family multiplexed as Section 4 describes;
+    returns the container length (decode with rans_decode)."""
+    p = _params(params)
+    out_len = ct.c_uint64()
+    rc = _lib.rans_pfx_encode(table.handle, ct.byref(p), _ptr(d_syms), n_syms, _ptr(d_out), out_cap,
+                              ct.byref(out_len), _stream(stream))
+    _check(rc, "rans_pfx_encode")
+    return int(out_len.value)
+
+
+def rans_pfx_encode_async(table: Table, params, d_syms, n_syms: int, d_out, out_cap: int,
+                          d_out_len, d_status, stream=None):
+    p = _params(params)
+    _check(_lib.rans_pfx_encode_async(table.handle, ct.byref(p), _ptr(d_syms), n_syms, _ptr(d_out),
+                                      out_cap, _ptr(d_out_len), _ptr(d_status), _stream(stream)),
+           "rans_pfx_encode_async")
 
 
 def rans_decode_lut(table: Table, d_in, in_len: int, d_lut, lut_bytes: int, d_out, out_cap: int,

@@ -87,7 +87,7 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     std::memcpy(&C, h + 12, 4);
     std::memcpy(&n, h + 16, 8);
     std::memcpy(&nch, h + 24, 4);
-    if (magic != kMagic || h[4] != 1 || h[9] > 3)
+    if (magic != kMagic || h[4] != 1 || (h[9] > 3 && h[9] != 4))
         return RANS_ECORRUPT;
     rans_params p{};
     p.prob_bits = h[5];
@@ -95,8 +95,9 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     p.state_lbits = h[7];
     p.sym_bytes = h[8];
     p.interleave = N;
-    p.digit_order = h[9] & 1;
-    p.escape = h[9] >> 1;
+    const bool pfx = h[9] == 4;  // the prefix-code family: 16-bit words
+    p.digit_order = pfx ? 0 : h[9] & 1;
+    p.escape = pfx ? 0 : h[9] >> 1;
     p.chunk_syms = C;
     if (check_params(&p) != RANS_OK)
         return RANS_ECORRUPT;
@@ -104,6 +105,9 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
         return RANS_ECORRUPT;
     if (kHeaderBytes + uint64_t(kDirEntryBytes) * nch > in_len)
         return RANS_ECORRUPT;
+    if (pfx && p.radix_bits != 16)
+        return RANS_ECORRUPT;
+    out->pfx = pfx;
     out->p = p;
     out->n = n;
     out->n_chunks = nch;
@@ -196,10 +200,19 @@ extern "C" const char* rans_strerror(int code)
     }
 }
 
+// The one-wave-per-chunk kernels move symbols in 16-byte pieces: every chunk
+// must start 16-byte aligned in the symbol buffer.
+static bool fast64(uint32_t N, uint32_t C, uint32_t W, const void* syms)
+{
+    return (N == 32 || N == 64) && (uint64_t(C) * W) % 16 == 0 &&
+           (reinterpret_cast<uintptr_t>(syms) & 15) == 0;
+}
+
 // Validates an encode call and fills the launch arguments (host only).
+// pfx: the prefix-code family multiplexed as Section 4 describes.
 static int prepare_encode(const rans_table* table, const rans_params* params, const void* d_syms,
                           uint64_t n, void* d_out, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
-                          PlaceArgs* pa, uint64_t* ws_need)
+                          PlaceArgs* pa, uint64_t* ws_need, bool pfx = false)
 {
     if (!table || !d_out)
         return RANS_EINVAL;
@@ -222,7 +235,14 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
         return RANS_EINVAL;
     const uint32_t nch = static_cast<uint32_t>(nch64);
     const uint32_t R = p.radix_bits, N = p.interleave;
-    const uint64_t sb = slot_bytes_for(C, p.prob_bits, R, p.escape != 0);
+    // prefix-code family: 16-bit words, no rANS variants, the one-wave-per-
+    // chunk kernel only, and a table whose symbols fit its code entries
+    if (pfx && (R != 16 || p.state_lbits != 16 || p.digit_order || p.escape || !t.pfx_enc ||
+                (n && !fast64(N, C, p.sym_bytes, d_syms))))
+        return RANS_EINVAL;
+    // a prefix-coded chunk holds at most a word per symbol plus one per coder
+    const uint64_t sb = pfx ? (2 * (uint64_t(C) + 64) + 255) & ~uint64_t(255)
+                            : slot_bytes_for(C, p.prob_bits, R, p.escape != 0);
     const EncodeLayout el = encode_layout(nch, N, sb);
     *ws_need = el.total;
 
@@ -238,8 +258,8 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->alphabet = t.alphabet;
     ea->bf = p.digit_order;
     ea->esc = p.escape;
-    ea->enc = t.enc;
-    ea->enc_bytes = static_cast<uint32_t>(t.enc_bytes);
+    ea->enc = pfx ? reinterpret_cast<const uint4*>(t.pfx_enc) : t.enc;
+    ea->enc_bytes = static_cast<uint32_t>(pfx ? t.pfx_enc_bytes : t.enc_bytes);
     ea->slot_bytes = sb;
     ea->slot_stride = sb + 256;
 
@@ -249,6 +269,8 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     sa->digit_bytes = R / 8;
     sa->out = static_cast<uint8_t*>(d_out);
     make_header(sa->hdr, p, C, n, nch);
+    if (pfx)
+        sa->hdr[9] = 4;  // flags: the prefix-code family
 
     *ca = CompactArgs{};
     ca->slot_bytes = sb;
@@ -291,18 +313,22 @@ static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactA
     pa->total = sa->total;
 }
 
-// The N = 64 kernels move symbols in 16-byte pieces: every chunk must start
-// 16-byte aligned in the symbol buffer.
-static bool fast64(uint32_t N, uint32_t C, uint32_t W, const void* syms)
-{
-    return (N == 32 || N == 64) && (uint64_t(C) * W) % 16 == 0 &&
-           (reinterpret_cast<uintptr_t>(syms) & 15) == 0;
-}
-
 static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
-                                 const PlaceArgs& pa, int R, int W, hipStream_t st)
+                                 const PlaceArgs& pa, int R, int W, hipStream_t st, bool pfx = false)
 {
     hipError_t e;
+    if (pfx) {
+        if (ea.n_chunks == 0)  // the header alone: the scan kernel writes it
+            return launch_scan(sa, st);
+        e = launch_fill_u32(pa.ticket, 0, 1, st);
+        if (e == hipSuccess)
+            e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0,
+                                2 * (ea.n_chunks + (ea.n_chunks + 63) / 64), st);
+        if (e != hipSuccess)
+            return e;
+        TimingScope ts(RANS_KERNEL_ENCODE, st);
+        return launch_pfx_encode64(ea, pa, W, st);
+    }
     if (ea.n_chunks > 0 && fast64(ea.N, ea.C, W, ea.syms)) {
         // one kernel: encode and place by look-back (ticket and look-back
         // words start at zero)
@@ -339,9 +365,9 @@ static hipError_t enqueue_decode(const DecodeArgs& da, int R, int W, Layout layo
                                          : launch_decode(da, R, W, layout, st);
 }
 
-extern "C" int rans_encode_async(const rans_table* table, const rans_params* params,
-                                 const void* d_syms, uint64_t n, void* d_out, uint64_t out_cap,
-                                 uint64_t* d_out_len, int32_t* d_status, void* stream)
+static int encode_async(const rans_table* table, const rans_params* params, const void* d_syms,
+                        uint64_t n, void* d_out, uint64_t out_cap, uint64_t* d_out_len,
+                        int32_t* d_status, void* stream, bool pfx)
 {
     if (!d_status)
         return RANS_EINVAL;
@@ -350,7 +376,7 @@ extern "C" int rans_encode_async(const rans_table* table, const rans_params* par
     CompactArgs ca;
     PlaceArgs pa;
     uint64_t need = 0;
-    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &pa, &need);
+    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &pa, &need, pfx);
     if (rc != RANS_OK)
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -365,14 +391,14 @@ extern "C" int rans_encode_async(const rans_table* table, const rans_params* par
     ea.status = sa.status = d_status;
     sa.out_cap = ca.out_cap = pa.out_cap = out_cap;
     sa.total_out = pa.total_out = d_out_len;
-    return enqueue_encode(ea, sa, ca, pa, params->radix_bits, params->sym_bytes, st) == hipSuccess
+    return enqueue_encode(ea, sa, ca, pa, params->radix_bits, params->sym_bytes, st, pfx) == hipSuccess
                ? RANS_OK
                : RANS_EDEVICE;
 }
 
-extern "C" int rans_encode(const rans_table* table, const rans_params* params, const void* d_syms,
-                           uint64_t n, void* d_out, uint64_t out_cap, uint64_t* out_len,
-                           void* stream)
+static int encode_sync(const rans_table* table, const rans_params* params, const void* d_syms,
+                       uint64_t n, void* d_out, uint64_t out_cap, uint64_t* out_len, void* stream,
+                       bool pfx)
 {
     if (!out_len)
         return RANS_EINVAL;
@@ -382,7 +408,7 @@ extern "C" int rans_encode(const rans_table* table, const rans_params* params, c
     CompactArgs ca;
     PlaceArgs pa;
     uint64_t need = 0;
-    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &pa, &need);
+    int rc = prepare_encode(table, params, d_syms, n, d_out, &ea, &sa, &ca, &pa, &need, pfx);
     if (rc != RANS_OK)
         return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -401,7 +427,7 @@ extern "C" int rans_encode(const rans_table* table, const rans_params* params, c
     sa.total_out = pa.total_out = nullptr;
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(status), 0, 1, st);
     if (e == hipSuccess)
-        e = enqueue_encode(ea, sa, ca, pa, params->radix_bits, params->sym_bytes, st);
+        e = enqueue_encode(ea, sa, ca, pa, params->radix_bits, params->sym_bytes, st, pfx);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws->host, base, 16, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
@@ -414,6 +440,34 @@ extern "C" int rans_encode(const rans_table* table, const rans_params* params, c
     std::memcpy(&total, static_cast<uint8_t*>(ws->host) + 8, 8);
     *out_len = total;
     return code;
+}
+
+extern "C" int rans_encode_async(const rans_table* table, const rans_params* params,
+                                 const void* d_syms, uint64_t n, void* d_out, uint64_t out_cap,
+                                 uint64_t* d_out_len, int32_t* d_status, void* stream)
+{
+    return encode_async(table, params, d_syms, n, d_out, out_cap, d_out_len, d_status, stream, false);
+}
+
+extern "C" int rans_encode(const rans_table* table, const rans_params* params, const void* d_syms,
+                           uint64_t n, void* d_out, uint64_t out_cap, uint64_t* out_len,
+                           void* stream)
+{
+    return encode_sync(table, params, d_syms, n, d_out, out_cap, out_len, stream, false);
+}
+
+extern "C" int rans_pfx_encode_async(const rans_table* table, const rans_params* params,
+                                     const void* d_syms, uint64_t n, void* d_out, uint64_t out_cap,
+                                     uint64_t* d_out_len, int32_t* d_status, void* stream)
+{
+    return encode_async(table, params, d_syms, n, d_out, out_cap, d_out_len, d_status, stream, true);
+}
+
+extern "C" int rans_pfx_encode(const rans_table* table, const rans_params* params, const void* d_syms,
+                               uint64_t n, void* d_out, uint64_t out_cap, uint64_t* out_len,
+                               void* stream)
+{
+    return encode_sync(table, params, d_syms, n, d_out, out_cap, out_len, stream, true);
 }
 
 // Validates a decode call against a host copy of the header.  lut_w != 0:
@@ -447,6 +501,9 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
         if (h->n && (!d_syms || !fast64(h->p.interleave, h->p.chunk_syms, lut_w, d_syms)))
             return RANS_EINVAL;
     }
+    if (h->pfx && (lut_w || !t.pfx_dec ||
+                   (h->n && !fast64(h->p.interleave, h->p.chunk_syms, h->p.sym_bytes, d_syms))))
+        return RANS_EINVAL;  // the one-wave-per-chunk decoder, symbol output only
     uint32_t lds;
     if (!choose_layout(t, layout, &lds, lut_w ? lut_lds_bytes(t.alphabet, lut_w) : 0))
         return RANS_EINVAL;
@@ -467,6 +524,15 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     da->lut = d_lut;
     da->lut_w = lut_w;
     fill_decode_tables(t, *layout, da);
+    if (h->pfx) {  // its lookup table stands in for the packed layout's entries
+        da->pfx = 1;
+        da->k = t.pfx_maxlen;
+        da->tab0 = t.pfx_dec;
+        da->tab0_bytes = static_cast<uint32_t>(t.pfx_dec_bytes);
+        da->tab1 = nullptr;
+        da->tab1_bytes = 0;
+        *layout = kPacked;
+    }
     return RANS_OK;
 }
 

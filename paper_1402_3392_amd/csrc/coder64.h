@@ -131,8 +131,15 @@ __device__ __forceinline__ void stage2(uint8_t* lds, const void* a, uint32_t aby
 // (16-bit symbols, depth-first): escape coding -- the table's last symbol
 // E = alphabet - 1 is followed in its coder's share of the step by 16 / R
 // raw digits that hold the output value (Section 3's raw data mixed into
-// the stream).
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false, int LW = 0, bool ESC = false>
+// the stream).  PFX (R = 16): the chunk holds the prefix-code family
+// multiplexed as Section 4 describes -- NL bit counts at the head, then the
+// 16-bit words in the order the decoders read them; each lane reads one word
+// before a symbol whenever it holds fewer than 16 bits, then looks the
+// symbol up by its next k_ (the longest code length) bits in l_ent (u16
+// entries symbol | length << 12); the end check compares the bits each lane
+// consumed with its count.
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false, int LW = 0, bool ESC = false,
+          bool PFX = false>
 __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                              uint64_t chunk, uint32_t C, uint64_t n, void* out_base,
                                              uint32_t k_, uint32_t l, const void* l_sym_v,
@@ -141,6 +148,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
                                              uint32_t alphabet = 0)
 {
     static_assert(!ESC || (W == 2 && !BF && LW == 0), "escape coding: 16-bit symbols, depth-first");
+    static_assert(!PFX || (R == 16 && !BF && !ESC && LW == 0), "prefix-code family: 16-bit words");
     const uint32_t E = alphabet - 1;  // the escape symbol (ESC)
     using SymT = typename std::conditional<SW == 1, uint8_t, uint16_t>::type;
     using SymOutT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
@@ -251,7 +259,8 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     uint32_t x = reinterpret_cast<const uint32_t*>(obuf)[lane];
     lane_fence();  // the output block is reused for symbols
     if (!live)
-        x = L;  // idle lanes stay at L and never refill
+        x = PFX ? 0u : L;  // idle lanes stay at L and never refill (PFX: count 0)
+    uint32_t pbuf = 0, pnb = 0, pused = 0;  // PFX: bit buffer (MSB first), its bits, bits used
 
     constexpr uint32_t SPB = OB / (NL * OW);   // steps per output block
     constexpr uint32_t PIECE = OB / 64;         // bytes each lane moves per block
@@ -365,6 +374,26 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
             }
         }
     };
+    // Prefix-code step: the read (one word when fewer than 16 bits are
+    // buffered) comes before the symbol, so every lane reads at the prefix
+    // count of the reading lanes below it, then decodes from its buffer.
+    auto step_pfx = [&](bool act, auto dense, uint32_t& s) {
+        const bool n1 = act && pnb < 16;
+        const uint64_t m1 = ballot(n1);
+        if (dense || m1) {
+            const uint16_t* rp = reinterpret_cast<const uint16_t*>(ring) + (pos & DMASK);
+            const uint32_t v = rp[mbcnt(m1, 0)];
+            pbuf = select_mask(m1, pbuf, pbuf | (v << ((16u - pnb) & 31u)));
+            pnb = select_mask(m1, pnb, pnb + 16);
+            pos += __popcll(m1);
+        }
+        const uint32_t e = reinterpret_cast<const uint16_t*>(l_ent)[pbuf >> (32 - k)];
+        s = e & 0xFFFu;
+        const uint32_t len = act ? e >> 12 : 0u;
+        pbuf <<= len;
+        pnb -= len;
+        pused += len;
+    };
     auto flush = [&](uint32_t tb) {  // output block starting at step tb
         lane_fence();
         const Piece v = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
@@ -374,11 +403,15 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     };
     auto step1 = [&](OutT* dst, auto dense) {
         uint32_t s;
-        decode_one(s);
-        if (ESC)
-            refill_esc(live, dense, s);
-        else
-            refill(live, dense);
+        if (PFX) {
+            step_pfx(live, dense, s);
+        } else {
+            decode_one(s);
+            if (ESC)
+                refill_esc(live, dense, s);
+            else
+                refill(live, dense);
+        }
         if (live)
             *dst = emit(s);
     };
@@ -403,12 +436,16 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
     auto partial_step = [&]() {
         const bool act = lane < nsym - t * NL;
         uint32_t s = 0;
-        if (act)
-            decode_one(s);
-        if (ESC)
-            refill_esc(act, std::false_type{}, s);
-        else
-            refill(act, std::false_type{});
+        if (PFX) {
+            step_pfx(act, std::false_type{}, s);
+        } else {
+            if (act)
+                decode_one(s);
+            if (ESC)
+                refill_esc(act, std::false_type{}, s);
+            else
+                refill(act, std::false_type{});
+        }
         if (live)
             ob[(t & (SPB - 1)) * NL] = emit(s);
         ++t;
@@ -489,7 +526,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         }
     }
     wait_vm<0>();  // windows fetched ahead land before wave_lds is reused
-    const bool bad = x != L || pos != ndig;
+    const bool bad = (PFX ? pused != x : x != L) || pos != ndig;
     if (ballot(bad) && lane == 0)
         atomicMin(status, RANS_ECORRUPT);
 }
@@ -818,8 +855,101 @@ __device__ __forceinline__ uint64_t await_word(const uint64_t* w, bool& timeout)
     }
 }
 
-// Places encoded chunk `chunk` (NL final states in x, nd digits ending at
-// slot + slot_bytes) into the container.  Its offset is the sum of the
+// Prefix-code encoder of one chunk (the second coder family, multiplexed as
+// Section 4 describes).  Lane j codes symbols j, j + NL, ... with the
+// canonical prefix code and, step by step, applies its decoder's read rule
+// to its own bit count: the decoder reads one 16-bit word before a symbol
+// whenever it holds fewer than 16 bits.  The lanes that read in a step take
+// consecutive positions of the multiplexed stream (a ballot prefix) -- the
+// order in which the instrumented decoder would copy the words -- and each
+// word is stored at its position once the lane's bits complete it, at most
+// two reads later (the decoder holds at most 31 bits).  penc: LDS, alphabet
+// + 1 entries code | len << 16 (len 0: the symbol cannot be coded).  Words
+// go to mux[0 ..) (global); the NL bit counts to *x_out (per lane), the word
+// count to *nd_out.
+template <int W, int NL>
+__device__ __forceinline__ void encode_chunk_pfx(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
+                                                 uint32_t alphabet, const uint32_t* penc, uint16_t* mux,
+                                                 int32_t* status, uint32_t* x_out, uint32_t* nd_out)
+{
+    using InT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
+    const uint32_t lane = threadIdx.x & 63;
+    const bool live = NL == 64 || lane < NL;
+    const uint64_t first = chunk * C;
+    const uint32_t nsym = uni(static_cast<uint32_t>(n - first < C ? n - first : C));
+    const InT* in = static_cast<const InT*>(syms_base) + first;
+    const uint32_t steps = (nsym + NL - 1) / NL;
+    uint64_t acc = 0;      // code bits not yet in a word (nacc of them)
+    uint32_t nacc = 0;
+    uint32_t nbd = 0;      // bits the lane's decoder holds
+    uint32_t q0 = 0, q1 = 0, npend = 0;  // positions read, words not yet complete
+    uint32_t bits = 0, wpos = 0, bad = 0;
+    constexpr uint32_t PF = 8;  // symbols loaded this many steps ahead
+    auto load = [&](uint32_t t) -> uint32_t {
+        const uint64_t i = uint64_t(t) * NL + lane;
+        return live && i < nsym ? static_cast<uint32_t>(in[i]) : 0u;
+    };
+    uint32_t cur[PF], nxt[PF];
+#pragma unroll
+    for (uint32_t q = 0; q < PF; ++q)
+        cur[q] = load(q);
+    for (uint32_t t0 = 0; t0 < steps; t0 += PF) {
+#pragma unroll
+        for (uint32_t q = 0; q < PF; ++q)
+            nxt[q] = load(t0 + PF + q);
+#pragma unroll
+        for (uint32_t q = 0; q < PF; ++q) {
+            const uint32_t t = t0 + q;
+            const bool act = live && uint64_t(t) * NL + lane < nsym;
+            const bool rd = act && nbd < 16;
+            const uint64_t m = ballot(rd);
+            if (rd) {
+                const uint32_t pos = wpos + mbcnt(m, 0);
+                if (npend == 0)
+                    q0 = pos;
+                else
+                    q1 = pos;
+                ++npend;
+                nbd += 16;
+            }
+            wpos += __popcll(m);
+            if (act) {
+                const uint32_t e = penc[min(cur[q], alphabet)];
+                const uint32_t len = e >> 16;
+                bad |= len == 0 ? 1u : 0u;
+                acc = (acc << len) | (e & 0xFFFFu);
+                nacc += len;
+                nbd -= len;
+                bits += len;
+                if (nacc >= 16) {  // a code has at most 15 bits: one word at most
+                    nacc -= 16;
+                    mux[q0] = static_cast<uint16_t>(acc >> nacc);
+                    acc &= (1ull << nacc) - 1;
+                    q0 = q1;
+                    --npend;
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < PF; ++q)
+            cur[q] = nxt[q];
+    }
+    // the last partial word (zero padded), and a word of zeros when the
+    // decoder's rule reads one beyond the bits
+    if (live && npend > 0) {
+        mux[q0] = static_cast<uint16_t>(nacc ? acc << (16 - nacc) : 0u);
+        if (npend > 1)
+            mux[q1] = 0;
+    }
+    if (ballot(bad != 0) && lane == 0)
+        atomicMin(status, RANS_ENOSYM);
+    *x_out = live ? bits : 0u;
+    *nd_out = wpos;
+}
+
+// Places encoded chunk `chunk` (NL final states in x, nd digits starting at
+// src, a 16-byte aligned address with at least 32 readable bytes past the
+// digits) into the container.  Its offset is the sum of the
 // padded lengths of all lower chunks, found in two lane-parallel levels:
 // every chunk publishes its length; the lengths of the lower chunks of its
 // own group of 64 are read one per lane and summed; the last chunk of each
@@ -831,8 +961,7 @@ __device__ __forceinline__ uint64_t await_word(const uint64_t* w, bool& timeout)
 // all zero before the kernel.
 template <int R, int NL>
 __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32_t x, uint32_t nd,
-                                            const uint8_t* slot, uint64_t slot_bytes,
-                                            const PlaceArgs& p, int32_t* status)
+                                            const uint8_t* src, const PlaceArgs& p, int32_t* status)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t pay = nd * (R / 8);
@@ -865,9 +994,8 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
         }
         if (NL == 64 || lane < NL)
             reinterpret_cast<uint32_t*>(dst)[lane] = x;
-        const uint8_t* src = slot + slot_bytes - pay;
         const uint32_t mis = static_cast<uint32_t>(reinterpret_cast<uintptr_t>(src) & 15);
-        // reads reach at most 31 bytes past the slot: inside the 128 bytes after it
+        // reads reach at most 31 bytes past the digits
         const uint4* S = reinterpret_cast<const uint4*>(src - mis);
         uint4* D = reinterpret_cast<uint4*>(dst + 4 * NL);
         const uint32_t pieces = static_cast<uint32_t>((al - 4 * NL) / 16);

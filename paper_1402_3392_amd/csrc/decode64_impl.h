@@ -22,7 +22,7 @@ __device__ __forceinline__ void stage_lut(uint8_t* lds, const void* src, uint32_
         d[i] = s[i];
 }
 
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC, bool PFX>
 __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -48,14 +48,14 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
     const uint64_t chunk = uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave;
     if (chunk >= a.n_chunks)
         return;  // no barrier follows
-    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, LW, ESC>(
+    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, LW, ESC, PFX>(
         a.in, a.in_len, a.n_chunks, chunk, a.C, a.n, a.out, a.k, a.l, tab,
         reinterpret_cast<const uint32_t*>(tab + sym_bytes), lds + wave * c64::wave_lds_bytes(LAYOUT),
         a.status, lut, a.alphabet);
 }
 
 // Waves per block: 16 when the tables leave room for them, fewer otherwise.
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC, bool PFX = false>
 hipError_t run(const DecodeArgs& a, hipStream_t st)
 {
     const uint32_t tabs = a.tab0_bytes + a.tab1_bytes + lut_lds_bytes(a.alphabet, LW);
@@ -68,7 +68,7 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
     wpb = wpb < fit ? wpb : fit;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
     const uint32_t lds = tabs + wpb * per;
-    auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF, LW, ESC>;
+    auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF, LW, ESC, PFX>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -116,10 +116,21 @@ hipError_t run_esc(const DecodeArgs& a, Layout layout, hipStream_t st)
                             : run_l<R, 2, 1, false, 0, true>(a, layout, st);
 }
 
+// prefix-code family: 16-bit words, its lookup table staged as the packed
+// layout's entries (no symbol map)
+template <int W>
+hipError_t run_pfx(const DecodeArgs& a, hipStream_t st)
+{
+    return a.N == 32 ? run<16, W, 1, kPacked, 32, false, 0, false, true>(a, st)
+                     : run<16, W, 1, kPacked, 64, false, 0, false, true>(a, st);
+}
+
 template <int LW>
 hipError_t run_r(const DecodeArgs& a, int R, int W, Layout layout, hipStream_t st)
 {
     if constexpr (LW == 0) {
+        if (a.pfx)
+            return W == 1 ? run_pfx<1>(a, st) : run_pfx<2>(a, st);
         if (a.esc)
             return R == 16 ? run_esc<16>(a, layout, st) : run_esc<8>(a, layout, st);
     }

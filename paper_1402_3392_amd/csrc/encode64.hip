@@ -28,7 +28,10 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
                                 reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
                                 lds + a.enc_bytes + wave * c64::kEncWaveLds, nullptr, nullptr, a.status,
                                 &x, &nd);
-    c64::place_chunk<R, NL>(chunk, a.n_chunks, x, c64::uni(nd), slot, a.slot_bytes, p, a.status);
+    // the digits end at slot + slot_bytes; the 256 bytes after it absorb the
+    // copy's reads past them
+    c64::place_chunk<R, NL>(chunk, a.n_chunks, x, c64::uni(nd),
+                            slot + a.slot_bytes - uint64_t(c64::uni(nd)) * (R / 8), p, a.status);
 }
 
 template <int R, int W, int NL, bool BF, bool ESC = false>
@@ -59,7 +62,49 @@ hipError_t run_n(const EncodeArgs& a, const PlaceArgs& p, int R, int W, hipStrea
     return W == 1 ? run_place<8, 1, NL, false>(a, p, st) : run_place<8, 2, NL, false>(a, p, st);
 }
 
+// Prefix-code family (Section 4's multiplexer): one wave per chunk, code
+// entries staged in LDS, words stored at their multiplexed positions in the
+// chunk's slot, then placed like the rANS chunks (the NL bit counts take the
+// place of the states).
+template <int W, int NL>
+__global__ void __launch_bounds__(1024) k_pfx_encode64(const EncodeArgs a, const PlaceArgs p)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    c64::stage2(lds, a.enc, a.enc_bytes, nullptr, 0);
+    __syncthreads();
+    uint32_t t = 0;
+    if ((threadIdx.x & 63) == 0)
+        t = atomicAdd(p.ticket, 1u);
+    const uint32_t chunk = c64::uni(t);
+    if (chunk >= a.n_chunks)
+        return;
+    uint8_t* slot = a.slots + uint64_t(chunk) * a.slot_stride;
+    uint32_t x = 0, nd = 0;
+    c64::encode_chunk_pfx<W, NL>(a.syms, a.n, a.C, chunk, a.alphabet, reinterpret_cast<const uint32_t*>(lds),
+                                 reinterpret_cast<uint16_t*>(slot), a.status, &x, &nd);
+    c64::wait_vm<0>();  // the words are in memory before other lanes copy them
+    c64::place_chunk<16, NL>(chunk, a.n_chunks, x, c64::uni(nd), slot, p, a.status);
+}
+
+template <int W, int NL>
+hipError_t run_pfx(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
+{
+    const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
+    const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
+    hipLaunchKernelGGL((k_pfx_encode64<W, NL>), dim3(blocks), dim3(64 * wpb), a.enc_bytes, st, a, p);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_pfx_encode64(const EncodeArgs& a, const PlaceArgs& p, int W, hipStream_t stream)
+{
+    if (a.n_chunks == 0)
+        return hipSuccess;
+    if (a.N == 32)
+        return W == 1 ? run_pfx<1, 32>(a, p, stream) : run_pfx<2, 32>(a, p, stream);
+    return W == 1 ? run_pfx<1, 64>(a, p, stream) : run_pfx<2, 64>(a, p, stream);
+}
 
 hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
                                  hipStream_t stream)

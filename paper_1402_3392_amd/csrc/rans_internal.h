@@ -36,6 +36,13 @@ struct DevTable {
     uint4* enc;         // [alpha+1] encoder entries; the extra one has f = 0
     uint2* fused;       // [M]      kFused entries, or null
     uint64_t dec_bytes, sym_bytes, fc_bytes, enc_bytes, fused_bytes;  // padded to 16
+    // prefix-code family (alphabet <= 4096, else null): per symbol
+    // code | len << 16 (alphabet + 1 entries, the last one len 0), and per
+    // value of the next pfx_maxlen bits symbol | len << 12
+    uint32_t* pfx_enc;
+    uint16_t* pfx_dec;
+    uint32_t pfx_maxlen;
+    uint64_t pfx_enc_bytes, pfx_dec_bytes;
 };
 
 // Encoder entry, one per symbol (uint4):
@@ -58,6 +65,7 @@ struct DecodeArgs {
     uint32_t alphabet;
     uint32_t bf;         // breadth-first digit order (Section 5)
     uint32_t esc;        // escape coding with raw digits (16-bit symbols)
+    uint32_t pfx;        // prefix-code family (k = its longest code length)
     const void* lut;     // fused consumer: alphabet entries of lut_w bytes (device)
     uint32_t lut_w;      // 0 (symbol output), 2 or 4
     const void* tab0;    // kPacked: dec; kTwoLevel: sym
@@ -182,6 +190,9 @@ hipError_t launch_decode64(const DecodeArgs& a, int R, int W, Layout layout, hip
 // Encode with in-kernel placement (no scan / compaction kernels).
 hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R, int W,
                                  hipStream_t stream);
+// Prefix-code family encode, multiplexed and placed in-kernel; a.enc holds
+// the code entries (a.enc_bytes), a.slots one slot of a.slot_bytes per chunk.
+hipError_t launch_pfx_encode64(const EncodeArgs& a, const PlaceArgs& p, int W, hipStream_t stream);
 uint32_t decode64_lds_per_wave(Layout layout);
 // Decode fused with a table lookup: out[i] = lut[symbol i] (a.lut, a.lut_w).
 hipError_t launch_decode64_lut(const DecodeArgs& a, int R, Layout layout, hipStream_t stream);

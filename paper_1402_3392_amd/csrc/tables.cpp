@@ -93,6 +93,49 @@ static inline uint32_t gm_divide(uint32_t x, uint32_t magic, uint32_t sh1, uint3
 
 static uint64_t pad16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
 
+// Canonical prefix code for the second coder family (Section 4's
+// multiplexer): length max(1, ceil(log2(M / f_s))) for every symbol with
+// f_s > 0 (the Kraft sum is at most sum f_s / M = 1, so a prefix code with
+// these lengths exists, and no length exceeds k); codes canonical --
+// symbols ordered by (length, index) take consecutive values, doubled at
+// each length step.  enc[s] = code | len << 16 (len 0: not codable);
+// dec[v] for the 2^maxlen values v of the next maxlen bits = symbol |
+// len << 12 of the code that prefixes v (len 0 where none does).
+static void prefix_code(const std::vector<uint32_t>& f, uint32_t k, std::vector<uint32_t>& enc,
+                        std::vector<uint16_t>& dec, uint32_t* maxlen)
+{
+    const uint32_t n = static_cast<uint32_t>(f.size());
+    const uint64_t M = 1ull << k;
+    std::vector<uint32_t> len(n, 0);
+    uint32_t ml = 0;
+    for (uint32_t s = 0; s < n; ++s) {
+        if (f[s] == 0)
+            continue;
+        uint32_t l = 0;
+        while ((uint64_t(f[s]) << l) < M)
+            ++l;
+        len[s] = l < 1 ? 1 : l;
+        ml = len[s] > ml ? len[s] : ml;
+    }
+    enc.assign(n + 1, 0);
+    dec.assign(size_t(1) << ml, 0);
+    uint32_t next = 0;
+    for (uint32_t l = 1; l <= ml; ++l) {
+        for (uint32_t s = 0; s < n; ++s) {
+            if (len[s] != l)
+                continue;
+            enc[s] = next | (l << 16);
+            // every ml-bit value that starts with this code decodes to s
+            const uint32_t lo = next << (ml - l), cnt = 1u << (ml - l);
+            for (uint32_t v = 0; v < cnt; ++v)
+                dec[lo + v] = static_cast<uint16_t>(s | (l << 12));
+            ++next;
+        }
+        next <<= 1;
+    }
+    *maxlen = ml;
+}
+
 const DevTable* dev_table(const rans_table* t) { return t ? &t->dev : nullptr; }
 
 }  // namespace rans
@@ -134,6 +177,14 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
     d.enc_bytes = pad16(uint64_t(alphabet + 1) * 16);
     const bool fused = alphabet <= 256 && k <= 14;
     d.fused_bytes = fused ? uint64_t(M) * 8 : 0;
+    // the prefix-code family (symbols fit the 12-bit field of its entries)
+    std::vector<uint32_t> h_penc;
+    std::vector<uint16_t> h_pdec;
+    if (alphabet <= 4096) {
+        prefix_code(f, k, h_penc, h_pdec, &d.pfx_maxlen);
+        d.pfx_enc_bytes = pad16(h_penc.size() * 4);
+        d.pfx_dec_bytes = pad16(h_pdec.size() * 2);
+    }
 
     std::vector<uint8_t> h_dec(d.dec_bytes, 0), h_sym(d.sym_bytes, 0), h_fc(d.fc_bytes, 0),
         h_enc(d.enc_bytes, 0), h_fused(d.fused_bytes, 0);
@@ -175,7 +226,8 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
         return RANS_EDEVICE;
     }
     void* blob = nullptr;
-    const uint64_t total = d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes + d.fused_bytes;
+    const uint64_t base = d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes + d.fused_bytes;
+    const uint64_t total = base + d.pfx_enc_bytes + d.pfx_dec_bytes;
     if (hipMalloc(&blob, total) != hipSuccess) {
         delete t;
         return RANS_ENOMEM;
@@ -196,6 +248,12 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
     if (fused)
         std::memcpy(host.data() + d.dec_bytes + d.sym_bytes + d.fc_bytes + d.enc_bytes,
                     h_fused.data(), d.fused_bytes);
+    if (d.pfx_enc_bytes) {
+        d.pfx_enc = reinterpret_cast<uint32_t*>(p + base);
+        d.pfx_dec = reinterpret_cast<uint16_t*>(p + base + d.pfx_enc_bytes);
+        std::memcpy(host.data() + base, h_penc.data(), h_penc.size() * 4);
+        std::memcpy(host.data() + base + d.pfx_enc_bytes, h_pdec.data(), h_pdec.size() * 2);
+    }
     if (hipMemcpy(blob, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(blob);
         delete t;

@@ -40,6 +40,7 @@ struct Header {
     rans_params p;
     uint64_t n;
     uint32_t n_chunks;
+    bool pfx;  // the prefix-code family (header flags 4)
 };
 
 // Byte offsets inside the workspace for one encode call.
