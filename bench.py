@@ -73,13 +73,15 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workload", default="roundtrip",
-                    choices=["roundtrip", "batched", "sweep", "serving", "dequant", "escape"],
+                    choices=["roundtrip", "batched", "sweep", "serving", "dequant", "escape",
+                             "prefix"],
                     help="roundtrip: the headline line (3 x 256 MiB encode+decode); "
                          "batched: 4096 uneven streams, one persistent launch vs plain calls; "
                          "sweep: radix/precision/alphabet sweep, batched vs plain decode; "
                          "serving: Poisson request loop, p50/p99 latency; "
                          "dequant: decode fused with a codebook lookup vs decode + gather; "
-                         "escape: escape coding with raw digits vs the clipped stream")
+                         "escape: escape coding with raw digits vs the clipped stream; "
+                         "prefix: prefix-code family multiplexed by the decoder read rule vs rANS")
     ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
     ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
@@ -557,6 +559,81 @@ def run_escape(args):
     print(json.dumps(out), flush=True)
 
 
+def run_prefix(args):
+    """Section 4's multiplexer with a second coder family: the three 256 MiB
+    Zipf buffers of the round trip coded with the canonical prefix code
+    (N = 64 coder streams multiplexed in decoder read order), against rANS
+    with the same table, chunking and interleave."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1402_3392_amd as lr
+
+    n = 1 << args.size_log2
+    rows, res = [], {}
+    st = torch.zeros(4, dtype=torch.int32, device="cuda")
+    lens = torch.zeros(2, dtype=torch.int64, device="cuda")
+    tot = {"pfx_enc": 0.0, "pfx_dec": 0.0, "rans_enc": 0.0, "rans_dec": 0.0, "pfx_bytes": 0}
+    for s_ in datagen.CONFIG2_S:
+        w = datagen.config2(s_, n=n)
+        k, r, l, W, N, C = w.params.astuple()
+        table = lr.rans_tables_build(w.counts, k)
+        d_in = torch.from_numpy(w.syms).cuda()
+        out = torch.empty_like(d_in)
+        row = {"s": s_}
+        for name, pfx in (("pfx", True), ("rans", False)):
+            params = lr.rans_params.make(k, 16, 16, W, N, C)
+            cap = lr.rans_encode_bound(n, params)
+            cont = torch.empty(cap, dtype=torch.uint8, device="cuda")
+            enc_fn = lr.rans_pfx_encode if pfx else lr.rans_encode
+            clen = enc_fn(table, params, d_in, n, cont, cap)
+            hdr = bytes(cont[:32].cpu().numpy().tobytes())
+            i = 0 if pfx else 1
+            enc_async = lr.rans_pfx_encode_async if pfx else lr.rans_encode_async
+
+            def enc():
+                enc_async(table, params, d_in, n, cont, cap, lens[i:i + 1], st[2 * i:2 * i + 1])
+
+            def dec():
+                lr.rans_decode_async(table, cont, clen, hdr, out, n, st[2 * i + 1:2 * i + 2])
+
+            for fn_name, fn in (("enc", enc), ("dec", dec)):
+                for _ in range(max(1, args.warmup)):
+                    fn()
+                torch.cuda.synchronize()
+                t = timed(fn, max(5, args.steps))
+                row[f"{name}_{fn_name}_us"] = round(t * 1e6, 1)
+                tot[f"{name}_{fn_name}"] += t
+            assert int(st.abs().sum()) == 0, f"status {st.tolist()}"
+            assert torch.equal(out, d_in), f"{name}: decode mismatch"
+            row[f"{name}_ratio"] = round(clen / n, 4)
+            if pfx:
+                tot["pfx_bytes"] += clen
+        rows.append(row)
+        log(json.dumps(row))
+        table.close()
+    total = 3 * n
+    t = tot["pfx_dec"]
+    alg = tot["pfx_bytes"] + total + 3 * 2 * (1 << 14)
+    out = base_result("prefix-code family multiplexed by the decoder read rule: decode GB/s",
+                      round(total / t / 1e9, 2), "GB/s", args,
+                      {"workload": f"3 x {n >> 20} MiB uint8 Zipf(s in 0.8/1.1/1.5) over 256, "
+                                   f"canonical prefix code from M=2^14 frequencies, 16-bit words, "
+                                   f"N=64, 64 KiB chunks; rANS with the same table beside it"})
+    out.update({
+        "pfx_encode_gbps": round(total / tot["pfx_enc"] / 1e9, 2),
+        "pfx_decode_gbps": round(total / tot["pfx_dec"] / 1e9, 2),
+        "rans_encode_gbps": round(total / tot["rans_enc"] / 1e9, 2),
+        "rans_decode_gbps": round(total / tot["rans_dec"] / 1e9, 2),
+        "buffers": rows,
+        "roofline": {"bound": "hbm", "kernel": "k_decode64 (prefix-code family)", "unit": "GB/s",
+                     "achieved": round(alg / t / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "frac": round(alg / t / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None},
+    })
+    print(json.dumps(out), flush=True)
+
+
 def run_serving(args):
     """Request loop: Poisson arrivals of mixed encode/decode requests under an
     8 GiB HBM budget, rates swept around the saturated throughput; p50/p99
@@ -645,7 +722,7 @@ def main():
         return
     if args.workload != "roundtrip":
         {"batched": run_batched, "sweep": run_sweep, "serving": run_serving,
-         "dequant": run_dequant, "escape": run_escape}[args.workload](args)
+         "dequant": run_dequant, "escape": run_escape, "prefix": run_prefix}[args.workload](args)
         return
 
     import numpy as np
