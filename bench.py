@@ -196,20 +196,18 @@ def run_batched(args):
     log(f"{total / 2**30:.2f} GiB in {len(data)} streams; building tables")
     tables = [lr.rans_tables_build(datagen.counts(s, 256), K) for s, _ in data]
 
-    # chunk size and launch shape from the autotuner, on the largest stream
-    big = int(np.argmax(sizes))
-    d_big = torch.from_numpy(data[big][0]).cuda()
-    tune = lr.rans_autotune(tables[big], d_big, sizes[big], lr.rans_params.make(K, R, L, 1, N, 65536))
-    del d_big
-    C = int(tune["chunk_syms"])
-    lr.rans_batch_set_config(int(tune["waves_per_group"]), int(tune["groups_per_cu"]),
-                             int(tune["table_layout"]), 1)
-    params = lr.rans_params.make(K, R, L, 1, N, C)
-    caps = [lr.rans_encode_bound(n, params) for n in sizes]
+    # the smallest chunk size bounds every container the tuner may choose
+    caps = [lr.rans_encode_bound(n, lr.rans_params.make(K, R, L, 1, N, 4096)) for n in sizes]
     pool = DevPool(sum((n + 255) // 256 * 256 for n in sizes) * 2 + sum(caps) + 256 * len(sizes))
     d_in = [pool.take(n) for n in sizes]
     for a, (s, _) in zip(d_in, data):
         pool.view(a, s.size).copy_(torch.from_numpy(s))
+    # chunk size and launch shape from the autotuner, timed on the whole batch
+    tune_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], 0, 0, 0, 0) for i in range(len(data)))
+    log("autotuning on the batch")
+    tune = lr.rans_autotune_batch(tune_jobs, len(data), lr.rans_params.make(K, R, L, 1, N, 65536))
+    C = int(tune["chunk_syms"])
+    params = lr.rans_params.make(K, R, L, 1, N, C)
     d_cont = [pool.take(c) for c in caps]
     d_dec = [pool.take(n) for n in sizes]
     lens = torch.zeros(len(data), dtype=torch.int64, device="cuda")

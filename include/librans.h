@@ -319,6 +319,15 @@ typedef struct rans_tune_result {
 int rans_autotune(const rans_table *table, const void *d_syms, uint64_t n_syms,
                   const rans_params *base, const char *cache_path, rans_tune_result *out);
 
+/* The same search on a whole batch: jobs are encode jobs as for
+ * rans_encode_batch (symbols in `in`, each with its table; their out,
+ * d_out_len and d_status are not touched -- the tuner encodes into memory of
+ * its own).  Every candidate is timed on all of the jobs together, so launch
+ * shapes that suit many short streams win where they should.  The cache key
+ * adds the number of streams (power-of-two class). */
+int rans_autotune_batch(const rans_job *jobs, uint32_t njobs, const rans_params *base,
+                        const char *cache_path, rans_tune_result *out);
+
 /* ---------------------------------------------------------------- serving --
  * Continuous-batching request server.  Requests (encode or decode of one
  * device-resident buffer, each with its own table) are admitted first come

@@ -125,6 +125,8 @@ _sig = {
     "rans_batch_set_config": (ct.c_int, [ct.POINTER(rans_batch_config)]),
     "rans_autotune": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, _P, ct.c_char_p,
                                  ct.POINTER(rans_tune_result)]),
+    "rans_autotune_batch": (ct.c_int, [ct.POINTER(rans_job), ct.c_uint32, _P, ct.c_char_p,
+                                       ct.POINTER(rans_tune_result)]),
     "rans_server_create": (ct.c_int, [ct.POINTER(rans_server_config), ct.POINTER(ct.c_void_p)]),
     "rans_server_destroy": (None, [ct.c_void_p]),
     "rans_server_submit": (ct.c_int, [ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_uint64,
@@ -371,6 +373,15 @@ def rans_autotune(table: Table, d_syms, n_syms: int, params, cache_path: str | N
     cp = cache_path.encode() if cache_path else None
     _check(_lib.rans_autotune(table.handle, _ptr(d_syms), n_syms, ct.byref(p), cp, ct.byref(r)),
            "rans_autotune")
+    return {f: getattr(r, f) for f, _ in r._fields_}
+
+
+def rans_autotune_batch(jobs, njobs: int, params, cache_path: str | None = None):
+    """Tunes on a whole batch of encode jobs (make_jobs); returns a dict."""
+    p = _params(params)
+    r = rans_tune_result()
+    cp = cache_path.encode() if cache_path else None
+    _check(_lib.rans_autotune_batch(jobs, njobs, ct.byref(p), cp, ct.byref(r)), "rans_autotune_batch")
     return {f: getattr(r, f) for f, _ in r._fields_}
 
 

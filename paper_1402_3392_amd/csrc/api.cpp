@@ -13,10 +13,19 @@ namespace rans {
 
 int max_lds_bytes()
 {
+    // per device, asked once (every launch needs it)
+    static std::mutex mu;
+    static std::map<int, int> known;
     int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    if (hipGetDevice(&dev) != hipSuccess)
         return 65536;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = known.find(dev);
+    if (it != known.end())
+        return it->second;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    known[dev] = v;
     return v;
 }
 

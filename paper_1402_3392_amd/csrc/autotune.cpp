@@ -109,6 +109,140 @@ double time_ms(hipStream_t st, int reps, F fn, int* rc)
     return ts[ts.size() / 2];
 }
 
+// One stream of a tuning sample: symbols on the device, coded with table.
+struct Sample {
+    const rans_table* table;
+    const void* d_syms;
+    uint64_t n;  // symbols
+};
+
+// The search shared by both entry points: every chunk size, then every
+// decode shape for its containers, each timed on the whole sample with the
+// batched kernels; finally graph replay against direct launches for the
+// best shape.  Applies the winner as the process-wide batch config.
+int tune(const std::vector<Sample>& smp, const rans_params& p, const std::string& key,
+         const char* cache_path, rans_tune_result* out)
+{
+    const uint32_t w = p.sym_bytes;
+    const uint32_t nj = static_cast<uint32_t>(smp.size());
+    // one tuning stream per process (its library workspace stays cached)
+    static hipStream_t st = nullptr;
+    if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+        return RANS_EDEVICE;
+    rans_params small = p;
+    small.chunk_syms = 4096;  // the smallest candidate bounds every container
+    std::vector<uint64_t> cap(nj), coff(nj), doff(nj);
+    uint64_t ctot = 0, dtot = 0, total = 0;
+    for (uint32_t j = 0; j < nj; ++j) {
+        cap[j] = rans_encode_bound(smp[j].n, &small);
+        coff[j] = ctot;
+        ctot += (cap[j] + 255) & ~uint64_t(255);
+        doff[j] = dtot;
+        dtot += (smp[j].n * w + 255) & ~uint64_t(255);
+        total += smp[j].n * w;
+    }
+    DevBuf cont, dec, meta;
+    if (!cont.alloc(ctot) || !dec.alloc(dtot) || !meta.alloc(16ull * nj))
+        return RANS_ENOMEM;
+    uint64_t* d_len = static_cast<uint64_t*>(meta.p);
+    int32_t* d_status = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(meta.p) + 8ull * nj);
+    std::vector<rans_job> ej(nj), dj(nj);
+    for (uint32_t j = 0; j < nj; ++j) {
+        ej[j] = rans_job{smp[j].table, smp[j].d_syms, smp[j].n * w,
+                         static_cast<uint8_t*>(cont.p) + coff[j], cap[j], d_len + j, d_status + j};
+        dj[j] = rans_job{smp[j].table, static_cast<uint8_t*>(cont.p) + coff[j], 0,
+                         static_cast<uint8_t*>(dec.p) + doff[j], smp[j].n * w, d_len + j, d_status + j};
+    }
+    std::vector<uint64_t> clen(nj);
+    std::vector<int32_t> cst(nj);
+    auto statuses_ok = [&](bool lengths) {
+        (void)hipMemcpy(cst.data(), d_status, 4ull * nj, hipMemcpyDeviceToHost);
+        for (int32_t v : cst)
+            if (v != RANS_OK)
+                return false;
+        if (lengths)
+            (void)hipMemcpy(clen.data(), d_len, 8ull * nj, hipMemcpyDeviceToHost);
+        return true;
+    };
+
+    rans_batch_config base_cfg = batch_config();
+    base_cfg.use_graph = 1;
+    double best_score = 1e30, ref_bytes = 0;
+    rans_tune_result best{};
+    const uint32_t chunk_sizes[] = {65536, 32768, 16384, 8192, 4096};
+    for (uint32_t C : chunk_sizes) {
+        if ((uint64_t(C) * w) % 16 != 0)
+            continue;
+        rans_params pc = p;
+        pc.chunk_syms = C;
+        int e = RANS_OK;
+        const double enc_ms = time_ms(st, 5, [&] {
+            return run_batch(ej.data(), nj, &pc, st, false, &base_cfg);
+        }, &e);
+        if (e != RANS_OK || !statuses_ok(true))
+            continue;
+        double bytes = 0;
+        for (uint32_t j = 0; j < nj; ++j) {
+            dj[j].in_len = clen[j];
+            bytes += double(clen[j]);
+        }
+        if (ref_bytes == 0)
+            ref_bytes = bytes;
+        // decode shapes for these containers
+        for (uint32_t G : {16u, 8u, 4u}) {
+            for (uint32_t gpc : {1u, 2u, 4u}) {
+                for (uint32_t lay : {3u, 1u, 2u}) {
+                    rans_batch_config cfg{G, gpc, lay, 1};
+                    int de = RANS_OK;
+                    const double dec_ms = time_ms(st, 5, [&] {
+                        return run_batch(dj.data(), nj, &pc, st, true, &cfg);
+                    }, &de);
+                    if (de != RANS_OK || !statuses_ok(false))
+                        continue;  // e.g. the layout does not fit LDS with G waves
+                    // size overhead beyond 1% over the largest chunks counts as time
+                    const double over = std::max(0.0, bytes / ref_bytes - 1.01);
+                    const double score = (enc_ms + dec_ms) * (1.0 + 10.0 * over);
+                    if (score < best_score) {
+                        best_score = score;
+                        best.chunk_syms = C;
+                        best.waves_per_group = G;
+                        best.groups_per_cu = gpc;
+                        best.table_layout = lay;
+                        best.encode_gbps = double(total) / (enc_ms * 1e6);
+                        best.decode_gbps = double(total) / (dec_ms * 1e6);
+                    }
+                }
+            }
+        }
+    }
+    if (best.chunk_syms == 0)
+        return RANS_EDEVICE;
+    // graph replay against direct launches, for the best shape
+    {
+        rans_params pc = p;
+        pc.chunk_syms = best.chunk_syms;
+        double t[2] = {0, 0};
+        for (uint32_t g = 0; g < 2; ++g) {
+            rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, g};
+            int e = RANS_OK;
+            t[g] = time_ms(st, 5, [&] { return run_batch(ej.data(), nj, &pc, st, false, &cfg); }, &e);
+            if (e == RANS_OK && statuses_ok(true)) {
+                for (uint32_t j = 0; j < nj; ++j)
+                    dj[j].in_len = clen[j];
+                t[g] += time_ms(st, 5, [&] { return run_batch(dj.data(), nj, &pc, st, true, &cfg); }, &e);
+            }
+            if (e != RANS_OK)
+                t[g] = 1e30;
+        }
+        best.use_graph = t[1] <= t[0] ? 1u : 0u;
+    }
+    (void)hipStreamSynchronize(st);
+    *out = best;
+    cache_store(cache_path, key, best);
+    rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, best.use_graph};
+    return rans_batch_set_config(&cfg);
+}
+
 }  // namespace
 }  // namespace rans
 
@@ -128,105 +262,52 @@ extern "C" int rans_autotune(const rans_table* table, const void* d_syms, uint64
     const DevTable* t = dev_table(table);
     if (t->k != p.prob_bits)
         return RANS_EINVAL;
-    const uint32_t w = p.sym_bytes;
-    const std::string key = cache_key(p, t->alphabet, n_syms * w);
+    const std::string key = cache_key(p, t->alphabet, n_syms * p.sym_bytes);
     if (cache_lookup(cache_path, key, out)) {
         rans_batch_config cfg{out->waves_per_group, out->groups_per_cu, out->table_layout, out->use_graph};
         return rans_batch_set_config(&cfg);
     }
     if (n_syms == 0)
         return RANS_EINVAL;
+    return tune({Sample{table, d_syms, n_syms}}, p, key, cache_path, out);
+}
 
-    // one tuning stream per process (its library workspace stays cached)
-    static hipStream_t st = nullptr;
-    if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
-        return RANS_EDEVICE;
-    DevBuf cont, dec, meta;
-    rans_params big = p;
-    big.chunk_syms = 1024;  // the smallest candidate bounds every container
-    const uint64_t cap = rans_encode_bound(n_syms, &big);
-    if (!cont.alloc(cap) || !dec.alloc(n_syms * w) || !meta.alloc(64))
-        return RANS_ENOMEM;
-    uint64_t* d_len = static_cast<uint64_t*>(meta.p);
-    int32_t* d_status = reinterpret_cast<int32_t*>(static_cast<uint8_t*>(meta.p) + 16);
-
-    rans_batch_config base_cfg = batch_config();
-    base_cfg.use_graph = 1;
-    double best_score = 1e30, ref_bytes = 0;
-    rans_tune_result best{};
-    const uint32_t chunk_sizes[] = {65536, 32768, 16384, 8192, 4096};
-    for (uint32_t C : chunk_sizes) {
-        if ((uint64_t(C) * w) % 16 != 0)
+extern "C" int rans_autotune_batch(const rans_job* jobs, uint32_t njobs, const rans_params* base,
+                                   const char* cache_path, rans_tune_result* out)
+{
+    if (!jobs || njobs == 0 || !base || !out)
+        return RANS_EINVAL;
+    rans_params p = *base;
+    p.interleave = 64;
+    p.chunk_syms = 65536;
+    int rc = check_params(&p);
+    if (rc != RANS_OK)
+        return rc;
+    std::vector<Sample> smp;
+    uint64_t total = 0;
+    uint32_t alpha = 0;
+    for (uint32_t j = 0; j < njobs; ++j) {
+        const rans_job& jb = jobs[j];
+        const DevTable* t = dev_table(jb.table);
+        if (!t || t->k != p.prob_bits || (jb.in_len % p.sym_bytes) != 0 ||
+            (jb.in_len && !jb.in) || (reinterpret_cast<uintptr_t>(jb.in) & 15))
+            return RANS_EINVAL;
+        if (jb.in_len == 0)
             continue;
-        rans_params pc = p;
-        pc.chunk_syms = C;
-        rans_job ej{table, d_syms, n_syms * w, cont.p, cap, d_len, d_status};
-        int e = RANS_OK;
-        const double enc_ms = time_ms(st, 5, [&] {
-            return run_batch(&ej, 1, &pc, st, false, &base_cfg);
-        }, &e);
-        uint64_t clen = 0;
-        int32_t cst = 0;
-        (void)hipMemcpy(&clen, d_len, 8, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(&cst, d_status, 4, hipMemcpyDeviceToHost);
-        if (e != RANS_OK || cst != RANS_OK)
-            continue;
-        if (ref_bytes == 0)
-            ref_bytes = double(clen);
-        // decode shapes for this container
-        for (uint32_t G : {16u, 8u, 4u}) {
-            for (uint32_t gpc : {1u, 2u}) {
-                for (uint32_t lay : {3u, 1u, 2u}) {
-                    rans_batch_config cfg{G, gpc, lay, 1};
-                    rans_job dj{table, cont.p, clen, dec.p, n_syms * w, d_len, d_status};
-                    int de = RANS_OK;
-                    const double dec_ms = time_ms(st, 5, [&] {
-                        return run_batch(&dj, 1, &pc, st, true, &cfg);
-                    }, &de);
-                    int32_t dst = 0;
-                    (void)hipMemcpy(&dst, d_status, 4, hipMemcpyDeviceToHost);
-                    if (de != RANS_OK || dst != RANS_OK)
-                        continue;  // e.g. the layout does not fit LDS with G waves
-                    // size overhead beyond 1% over the largest chunk counts as time
-                    const double over = std::max(0.0, double(clen) / ref_bytes - 1.01);
-                    const double score = (enc_ms + dec_ms) * (1.0 + 10.0 * over);
-                    if (score < best_score) {
-                        best_score = score;
-                        best.chunk_syms = C;
-                        best.waves_per_group = G;
-                        best.groups_per_cu = gpc;
-                        best.table_layout = lay;
-                        best.encode_gbps = double(n_syms * w) / (enc_ms * 1e6);
-                        best.decode_gbps = double(n_syms * w) / (dec_ms * 1e6);
-                    }
-                }
-            }
-        }
+        smp.push_back(Sample{jb.table, jb.in, jb.in_len / p.sym_bytes});
+        total += jb.in_len;
+        alpha = std::max(alpha, t->alphabet);
     }
-    if (best.chunk_syms == 0)
-        return RANS_EDEVICE;
-    // graph replay against direct launches, for the best shape
-    {
-        rans_params pc = p;
-        pc.chunk_syms = best.chunk_syms;
-        double t[2] = {0, 0};
-        for (uint32_t g = 0; g < 2; ++g) {
-            rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, g};
-            rans_job ej{table, d_syms, n_syms * w, cont.p, cap, d_len, d_status};
-            int e = RANS_OK;
-            t[g] = time_ms(st, 5, [&] { return run_batch(&ej, 1, &pc, st, false, &cfg); }, &e);
-            uint64_t clen = 0;
-            (void)hipMemcpy(&clen, d_len, 8, hipMemcpyDeviceToHost);
-            rans_job dj{table, cont.p, clen, dec.p, n_syms * w, d_len, d_status};
-            t[g] += time_ms(st, 5, [&] { return run_batch(&dj, 1, &pc, st, true, &cfg); }, &e);
-            if (e != RANS_OK)
-                t[g] = 1e30;
-        }
-        best.use_graph = t[1] <= t[0] ? 1u : 0u;
+    if (smp.empty())
+        return RANS_EINVAL;
+    // the key adds the number of streams (its power-of-two class)
+    uint32_t nclass = 0;
+    while ((1u << (nclass + 1)) <= smp.size())
+        ++nclass;
+    const std::string key = cache_key(p, alpha, total) + "|j" + std::to_string(nclass);
+    if (cache_lookup(cache_path, key, out)) {
+        rans_batch_config cfg{out->waves_per_group, out->groups_per_cu, out->table_layout, out->use_graph};
+        return rans_batch_set_config(&cfg);
     }
-    (void)hipStreamSynchronize(st);
-    *out = best;
-    cache_store(cache_path, key, best);
-    rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, best.use_graph};
-    return rans_batch_set_config(&cfg);
+    return tune(smp, p, key, cache_path, out);
 }

@@ -235,7 +235,7 @@ def test_autotune_result_is_valid_applied_and_cached(lr, tmp_path):
     base = lr.rans_params.make(k, r, l, 1, 64, 65536)
     res = lr.rans_autotune(table, d, s.size, base, cache)
     assert res["chunk_syms"] in (65536, 32768, 16384, 8192, 4096)
-    assert res["waves_per_group"] in (16, 8, 4) and res["groups_per_cu"] in (1, 2)
+    assert res["waves_per_group"] in (16, 8, 4) and res["groups_per_cu"] in (1, 2, 4)
     assert res["table_layout"] in (1, 2, 3) and res["use_graph"] in (0, 1)
     assert res["encode_gbps"] > 0 and res["decode_gbps"] > 0
     cfg = lr.rans_batch_get_config()
@@ -255,3 +255,43 @@ def test_autotune_result_is_valid_applied_and_cached(lr, tmp_path):
     dec, st2, _ = run_decode_batch(lr, tables, outs, [s.size], k, r, l)
     assert (st2 == 0).all() and (dec[0] == s).all()
     lr.rans_batch_set_config(16, 1, 0, 1)
+
+
+def test_batch_autotune_on_the_batch(lr, tmp_path):
+    """The tuner times candidates on the whole batch; its choice is applied,
+    cached, and codes the batch bit-exactly."""
+    import torch
+    k, r, l = 14, 16, 16
+    data = streams(24, seed=4700, lo=10, hi=16)
+    tables = [lr.rans_tables_build(datagen.counts(s, 256), k) for s, _ in data]
+    pool = Pool(sum(s.size + 256 for s, _ in data))
+    ins = []
+    for s, _ in data:
+        a = pool.take(s.size)
+        pool.put(a, s)
+        ins.append(a)
+    jobs = lr.make_jobs((tables[i], ins[i], data[i][0].size, 0, 0, 0, 0) for i in range(len(data)))
+    cache = str(tmp_path / "tune.txt")
+    base = lr.rans_params.make(k, r, l, 1, 64, 65536)
+    res = lr.rans_autotune_batch(jobs, len(data), base, cache)
+    assert res["chunk_syms"] in (65536, 32768, 16384, 8192, 4096)
+    assert res["waves_per_group"] in (16, 8, 4) and res["groups_per_cu"] in (1, 2, 4)
+    assert res["table_layout"] in (1, 2, 3) and res["decode_gbps"] > 0
+    cfg = lr.rans_batch_get_config()
+    assert (cfg["waves_per_group"], cfg["groups_per_cu"], cfg["table_layout"]) == \
+        (res["waves_per_group"], res["groups_per_cu"], res["table_layout"])
+    assert len(open(cache).read().splitlines()) == 1
+    again = lr.rans_autotune_batch(jobs, len(data), base, cache)
+    assert again["chunk_syms"] == res["chunk_syms"] and len(open(cache).read().splitlines()) == 1
+    try:
+        C = res["chunk_syms"]
+        tabs, outs, st, _ = run_encode_batch(lr, data, k, r, l, C)
+        assert (st == 0).all()
+        for i, (s, _) in enumerate(data):
+            ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+            assert (outs[i] == ref).all(), i
+        dec, st2, _ = run_decode_batch(lr, tabs, outs, [s.size for s, _ in data], k, r, l)
+        assert (st2 == 0).all() and all((dec[i] == s).all() for i, (s, _) in enumerate(data))
+    finally:
+        lr.rans_batch_set_config(16, 1, 0, 1)
+    torch.cuda.synchronize()
