@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--streams", type=int, default=4096, help="batched: number of streams")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests per rate")
     ap.add_argument("--points", default="", help="sweep: comma-separated point indices")
+    ap.add_argument("--grouped", action="store_true",
+                    help="sweep: batch the points sharing (k, r, l, w, N) into one launch each")
     ap.add_argument("--chunk-syms", type=int, default=0,
                     help="sweep: fixed chunk size in symbols (0: autotune per point)")
     ap.add_argument("--order", default="df", choices=["df", "bf"],
@@ -486,6 +488,119 @@ def run_dequant(args):
     print(json.dumps(out), flush=True)
 
 
+def run_sweep_grouped(args):
+    """The sweep's points as batches: the points that share (k, r, l, w, N)
+    -- the three distributions of every alphabet with the same symbol width --
+    go through one persistent batched launch, each with its own table, tuned
+    on that batch; against one plain launch per point.  Every container is
+    compared with the oracle's."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    import paper_1402_3392_amd as lr
+
+    pts = [p for p in datagen.config3_points() if p["feasible"]]
+    if args.points:
+        keep = {int(x) for x in args.points.split(",") if x}
+        pts = [p for i, p in enumerate(datagen.config3_points()) if i in keep and p["feasible"]]
+    groups = {}
+    for p in pts:
+        groups.setdefault((p["k"], p["r"], p["l"], p["w"], p["N"]), []).append(p)
+    threads = min(16, os.cpu_count() or 1)
+    rows = []
+    cache = {}
+    for (k, r, l, w, N), gp in sorted(groups.items()):
+        data = []
+        for p in gp:
+            key = (p["alphabet"], p["dist"])
+            if key not in cache:
+                if len(cache) > 12:
+                    cache.clear()
+                cache[key] = datagen.config3_data(p["alphabet"], p["dist"])[0]
+            data.append((p, cache[key]))
+        sizes = [int(s.size) * w for _, s in data]
+        total = sum(sizes)
+        tables = [lr.rans_tables_build(datagen.counts(s, p["alphabet"]), k) for p, s in data]
+        cap_params = lr.rans_params.make(k, r, l, w, N, 4096 // w)
+        caps = [lr.rans_encode_bound(s.size, cap_params) for _, s in data]
+        pool = DevPool(sum((n + 255) // 256 * 256 for n in sizes) * 2 + sum(caps) + 256 * len(data))
+        d_in = [pool.take(n) for n in sizes]
+        for a, (_, s) in zip(d_in, data):
+            pool.view(a, s.nbytes).copy_(torch.from_numpy(s.view(np.uint8)))
+        d_cont = [pool.take(c) for c in caps]
+        d_dec = [pool.take(n) for n in sizes]
+        lens = torch.zeros(len(data), dtype=torch.int64, device="cuda")
+        st = torch.zeros(len(data), dtype=torch.int32, device="cuda")
+        tune_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], 0, 0, 0, 0) for i in range(len(data)))
+        tune = lr.rans_autotune_batch(tune_jobs, len(data), lr.rans_params.make(k, r, l, w, 64, 65536 // w))
+        C = int(tune["chunk_syms"])
+        params = lr.rans_params.make(k, r, l, w, N, C)
+        enc_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], d_cont[i], caps[i],
+                                 int(lens.data_ptr()) + 8 * i, int(st.data_ptr()) + 4 * i)
+                                for i in range(len(data)))
+        lr.rans_encode_batch(enc_jobs, len(data), params)
+        torch.cuda.synchronize()
+        assert int(st.abs().sum()) == 0, f"batched encode status {st.tolist()}"
+        clen = [int(v) for v in lens.cpu().tolist()]
+        exact = True
+        for i, (p, s) in enumerate(data):
+            f = oracle.quantize(datagen.counts(s, p["alphabet"]), k)
+            ref = oracle.encode(f, s, k, r, l, N, C, threads=threads)
+            exact &= clen[i] == ref.size and np.array_equal(pool.view(d_cont[i], clen[i]).cpu().numpy(), ref)
+        headers = [bytes(pool.view(d_cont[i], 32).cpu().numpy().tobytes()) for i in range(len(data))]
+        dec_jobs = lr.make_jobs((tables[i], d_cont[i], clen[i], d_dec[i], sizes[i],
+                                 int(lens.data_ptr()) + 8 * i, int(st.data_ptr()) + 4 * i)
+                                for i in range(len(data)))
+
+        def batched():
+            lr.rans_decode_batch(dec_jobs, len(data), params)
+
+        def plain():
+            for i in range(len(data)):
+                lr.rans_decode_async(tables[i], pool.view(d_cont[i], clen[i]), clen[i], headers[i],
+                                     pool.view(d_dec[i], sizes[i]), sizes[i] // w, st[i:i + 1])
+
+        res = {}
+        for name, fn in (("batched", batched), ("plain", plain)):
+            fn()
+            torch.cuda.synchronize()
+            st.zero_()
+            res[name] = timed(fn, max(5, args.steps))
+            torch.cuda.synchronize()
+            assert int(st.abs().sum()) == 0, name
+            for i in range(len(data)):
+                assert torch.equal(pool.view(d_dec[i], sizes[i]), pool.view(d_in[i], sizes[i])), name
+        alg = sum(clen) + total + sum(4 * p["alphabet"] for p, _ in data)
+        row = {"k": k, "r": r, "l": l, "w": w, "N": N, "points": len(data), "bytes": total, "C": C,
+               "G": tune["waves_per_group"], "gpc": tune["groups_per_cu"], "layout": tune["table_layout"],
+               "bit_exact": bool(exact),
+               "batched_decode_gbps": round(total / res["batched"] / 1e9, 1),
+               "plain_decode_gbps": round(total / res["plain"] / 1e9, 1),
+               "speedup": round(res["plain"] / res["batched"], 2),
+               "ratio": round(sum(clen) / total, 4),
+               "batched_roofline_frac": round(alg / res["batched"] / 1e9 / HBM_PEAK_GBPS, 4)}
+        rows.append(row)
+        log(json.dumps(row))
+        for t in tables:
+            t.close()
+        del pool
+        torch.cuda.empty_cache()
+    best = max(rows, key=lambda r_: r_["batched_roofline_frac"])
+    out = base_result("rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
+                      best["batched_decode_gbps"], "GB/s", args,
+                      {"workload": "sweep points batched by (k, r, l, w, N): 64 MiB of symbol bytes "
+                                   "per point, each with its own table; batched decode vs one plain "
+                                   "launch per point"})
+    out["groups"] = rows
+    out["roofline"] = {"bound": "hbm", "kernel": "k_batch_decode64", "unit": "GB/s",
+                       "achieved": round(best["batched_roofline_frac"] * HBM_PEAK_GBPS, 1),
+                       "peak": HBM_PEAK_GBPS, "frac": best["batched_roofline_frac"], "traffic": None,
+                       "note": f"best group: k={best['k']} r={best['r']} w={best['w']} N={best['N']}"}
+    print(json.dumps(out), flush=True)
+
+
 def run_escape(args):
     """Escape coding (raw digits in the interleaved stream): 64 MiB of 16-bit
     zigzag Laplace values (scale 300), coded with a 1024-symbol table whose
@@ -719,6 +834,9 @@ def main():
         copy_probe()
         return
     if args.workload != "roundtrip":
+        if args.workload == "sweep" and args.grouped:
+            run_sweep_grouped(args)
+            return
         {"batched": run_batched, "sweep": run_sweep, "serving": run_serving,
          "dequant": run_dequant, "escape": run_escape, "prefix": run_prefix}[args.workload](args)
         return
