@@ -25,8 +25,10 @@ hipEvent_t get_event()
         g_pool.pop_back();
         return e;
     }
+    // a device-scope release: a system-scope one (the default) writes the
+    // caches back between the kernels being timed and slows the stream down
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess)
+    if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess)
         return nullptr;
     return e;
 }
