@@ -192,7 +192,7 @@ def run_batched(args):
 
     K, R, L, N = 14, 16, 16, 64
     log(f"generating {args.streams} streams")
-    data = datagen.config4_streams(nstreams=args.streams)
+    data = datagen.dirichlet_streams(nstreams=args.streams)
     sizes = [int(s.size) for s, _ in data]
     total = sum(sizes)
     log(f"{total / 2**30:.2f} GiB in {len(data)} streams; building tables")
@@ -297,7 +297,7 @@ def run_sweep(args):
     import oracle
     import paper_1402_3392_amd as lr
 
-    pts = datagen.config3_points()
+    pts = datagen.sweep_points()
     sel = [int(x) for x in args.points.split(",") if x] if args.points else range(len(pts))
     threads = min(16, os.cpu_count() or 1)
     cache = {}
@@ -307,7 +307,7 @@ def run_sweep(args):
         key = (p["alphabet"], p["dist"])
         if key not in cache:
             cache.clear()
-            cache[key] = datagen.config3_data(p["alphabet"], p["dist"])[0]
+            cache[key] = datagen.sweep_data(p["alphabet"], p["dist"])[0]
         syms = cache[key]
         w = 1 if p["alphabet"] <= 256 else 2
         row = {"idx": idx, "alphabet": p["alphabet"], "dist": p["dist"], "k": p["k"], "r": p["r"],
@@ -501,10 +501,10 @@ def run_sweep_grouped(args):
     import oracle
     import paper_1402_3392_amd as lr
 
-    pts = [p for p in datagen.config3_points() if p["feasible"]]
+    pts = [p for p in datagen.sweep_points() if p["feasible"]]
     if args.points:
         keep = {int(x) for x in args.points.split(",") if x}
-        pts = [p for i, p in enumerate(datagen.config3_points()) if i in keep and p["feasible"]]
+        pts = [p for i, p in enumerate(datagen.sweep_points()) if i in keep and p["feasible"]]
     groups = {}
     for p in pts:
         groups.setdefault((p["k"], p["r"], p["l"], p["w"], p["N"]), []).append(p)
@@ -518,7 +518,7 @@ def run_sweep_grouped(args):
             if key not in cache:
                 if len(cache) > 12:
                     cache.clear()
-                cache[key] = datagen.config3_data(p["alphabet"], p["dist"])[0]
+                cache[key] = datagen.sweep_data(p["alphabet"], p["dist"])[0]
             data.append((p, cache[key]))
         sizes = [int(s.size) * w for _, s in data]
         total = sum(sizes)
@@ -688,8 +688,8 @@ def run_prefix(args):
     st = torch.zeros(4, dtype=torch.int32, device="cuda")
     lens = torch.zeros(2, dtype=torch.int64, device="cuda")
     tot = {"pfx_enc": 0.0, "pfx_dec": 0.0, "rans_enc": 0.0, "rans_dec": 0.0, "pfx_bytes": 0}
-    for s_ in datagen.CONFIG2_S:
-        w = datagen.config2(s_, n=n)
+    for s_ in datagen.ZIPF_S:
+        w = datagen.zipf_buffer(s_, n=n)
         k, r, l, W, N, C = w.params.astuple()
         table = lr.rans_tables_build(w.counts, k)
         d_in = torch.from_numpy(w.syms).cuda()
@@ -759,7 +759,7 @@ def run_serving(args):
 
     K, R, L, W, N, C = 14, 16, 16, 1, 64, 65536
     params = lr.rans_params.make(K, R, L, W, N, C)
-    reqs = datagen.config5_requests(nreq=args.requests)
+    reqs = datagen.serving_requests(nreq=args.requests)
     log(f"{len(reqs)} requests, {sum(q['size'] for q in reqs) / 2**30:.2f} GiB; staging")
     staged = []
     for q in reqs:
@@ -853,8 +853,8 @@ def main():
 
     log(f"generating 3 x {n >> 20} MiB Zipf buffers")
     work = []
-    for s in datagen.CONFIG2_S:
-        w = datagen.config2(s, n=n)
+    for s in datagen.ZIPF_S:
+        w = datagen.zipf_buffer(s, n=n)
         work.append(w)
     params = [lr.rans_params.make(*w.params.astuple()) for w in work]
     tables = [lr.rans_tables_build(w.counts, w.params.k) for w in work]

@@ -165,7 +165,7 @@ class Workload:
         return int(self.syms.nbytes)
 
 
-def config1(n: int = 1 << 20) -> Workload:
+def tiny_zipf(n: int = 1 << 20) -> Workload:
     """1 MiB of uint8, Zipf(1.1) over 256, M=2^12, b=L=2^16, 4 coders, one chunk."""
     rng = np.random.Generator(np.random.PCG64(1001))
     p = zipf_probs(256, 1.1)
@@ -173,29 +173,29 @@ def config1(n: int = 1 << 20) -> Workload:
                     Params(12, 16, 16, 1, 4, 0), p)
 
 
-CONFIG2_S = (0.8, 1.1, 1.5)
+ZIPF_S = (0.8, 1.1, 1.5)
 
 
-def config2(s: float, n: int = 1 << 28) -> Workload:
+def zipf_buffer(s: float, n: int = 1 << 28) -> Workload:
     """256 MiB of uint8, Zipf(s) over 256, M=2^14, b=L=2^16, 64 KiB chunks, 64 coders."""
-    idx = CONFIG2_S.index(s)
+    idx = ZIPF_S.index(s)
     rng = np.random.Generator(np.random.PCG64(2001 + idx))
     p = zipf_probs(256, s)
     return Workload(f"zipf{s}-a256-{n >> 20}MiB-N64-C64K", sample(p, n, rng), 256,
                     Params(14, 16, 16, 1, 64, 65536), p)
 
 
-CONFIG3_ALPHABETS = (2, 16, 256, 4096)
-CONFIG3_K = (11, 15)
-CONFIG3_DISTS = ("dominant", "zipf1.1", "near_uniform")
-CONFIG3_RADIX = ((8, 23), (16, 16))
-CONFIG3_N = (32, 64)
+SWEEP_ALPHABETS = (2, 16, 256, 4096)
+SWEEP_K = (11, 15)
+SWEEP_DISTS = ("dominant", "zipf1.1", "near_uniform")
+SWEEP_RADIX = ((8, 23), (16, 16))
+SWEEP_N = (32, 64)
 
 
-def config3_data(alphabet: int, dist: str, nbytes: int = 64 << 20):
+def sweep_data(alphabet: int, dist: str, nbytes: int = 64 << 20):
     """64 MiB of symbol bytes (uint16 symbols for alphabets above 256)."""
-    di = CONFIG3_DISTS.index(dist)
-    ai = CONFIG3_ALPHABETS.index(alphabet)
+    di = SWEEP_DISTS.index(dist)
+    ai = SWEEP_ALPHABETS.index(alphabet)
     rng = np.random.Generator(np.random.PCG64(3000 + 3 * ai + di))
     if dist == "dominant":
         p = dominant_probs(alphabet, 0.995)
@@ -208,22 +208,22 @@ def config3_data(alphabet: int, dist: str, nbytes: int = 64 << 20):
     return sample(p, n, rng, dt), p
 
 
-def config3_points():
+def sweep_points():
     """The radix/precision sweep: 96 combinations, 12 of them infeasible
     (alphabet 4096 cannot be represented with M = 2^11)."""
     pts = []
-    for a in CONFIG3_ALPHABETS:
-        for k in CONFIG3_K:
-            for dist in CONFIG3_DISTS:
-                for (r, l) in CONFIG3_RADIX:
-                    for N in CONFIG3_N:
+    for a in SWEEP_ALPHABETS:
+        for k in SWEEP_K:
+            for dist in SWEEP_DISTS:
+                for (r, l) in SWEEP_RADIX:
+                    for N in SWEEP_N:
                         pts.append(dict(alphabet=a, k=k, dist=dist, r=r, l=l, N=N,
                                         w=1 if a <= 256 else 2,
                                         feasible=a <= (1 << k)))
     return pts
 
 
-def config4_streams(nstreams: int = 4096, lo_log2: float = 10.0, hi_log2: float = 22.0,
+def dirichlet_streams(nstreams: int = 4096, lo_log2: float = 10.0, hi_log2: float = 22.0,
                     seed: int = 4001, alphabet: int = 256):
     """Independent uint8 streams with log-uniform lengths and per-stream
     Dirichlet(alpha) distributions, alpha log-uniform in [0.05, 5]."""
@@ -241,7 +241,7 @@ def config4_streams(nstreams: int = 4096, lo_log2: float = 10.0, hi_log2: float 
     return out
 
 
-def config5_requests(nreq: int = 1000, seed: int = 5001, lo_log2: float = 12.0,
+def serving_requests(nreq: int = 1000, seed: int = 5001, lo_log2: float = 12.0,
                      hi_log2: float = 26.0):
     """Serving requests: sizes 2^U(12,26) bytes, encode/decode 50/50, per-request
     Zipf(s ~ U(0.7, 1.5)) over 256.  Returns a list of dicts with the data."""

@@ -51,13 +51,13 @@ def test_quantizer_matches_oracle(lr):
 
 
 def test_quantizer_on_workload_histograms(lr):
-    w = datagen.config1(n=1 << 18)
+    w = datagen.tiny_zipf(n=1 << 18)
     assert (lr.rans_quantize(w.counts, 12) == oracle.quantize(w.counts, 12)).all()
-    for a in datagen.CONFIG3_ALPHABETS:
-        for dist in datagen.CONFIG3_DISTS:
-            syms, _ = datagen.config3_data(a, dist, nbytes=1 << 18)
+    for a in datagen.SWEEP_ALPHABETS:
+        for dist in datagen.SWEEP_DISTS:
+            syms, _ = datagen.sweep_data(a, dist, nbytes=1 << 18)
             c = datagen.counts(syms, a)
-            for k in datagen.CONFIG3_K:
+            for k in datagen.SWEEP_K:
                 if int((c > 0).sum()) > (1 << k):
                     with pytest.raises(lr.RansError) as e:
                         lr.rans_quantize(c, k)

@@ -25,7 +25,7 @@ def lr():
 
 def streams(nstreams, seed, lo=10, hi=17):
     """Uint8 streams of log-uniform length with Dirichlet(alpha) tables."""
-    return datagen.config4_streams(nstreams=nstreams, lo_log2=lo, hi_log2=hi, seed=seed)
+    return datagen.dirichlet_streams(nstreams=nstreams, lo_log2=lo, hi_log2=hi, seed=seed)
 
 
 class Pool:

@@ -41,13 +41,13 @@ def check_roundtrip(lr, syms, alphabet, k, r, l, N, C):
 
 
 def test_one_chunk_four_coders_1MiB(lr):
-    w = datagen.config1()
+    w = datagen.tiny_zipf()
     check_roundtrip(lr, w.syms, 256, *w.params.astuple()[:3], w.params.N, w.params.C)
 
 
-@pytest.mark.parametrize("s", datagen.CONFIG2_S)
+@pytest.mark.parametrize("s", datagen.ZIPF_S)
 def test_256MiB_zipf(lr, s):
-    w = datagen.config2(s)
+    w = datagen.zipf_buffer(s)
     k, r, l, _, N, C = w.params.astuple()
     check_roundtrip(lr, w.syms, 256, k, r, l, N, C)
 
@@ -63,7 +63,7 @@ SWEEP = [(2, "dominant", 11, (8, 23), 64), (16, "zipf1.1", 15, (16, 16), 32),
 def test_sweep_point_64MiB_plain_and_batched(lr, pt):
     import torch
     alphabet, dist, k, (r, l), N = pt
-    syms = datagen.config3_data(alphabet, dist)[0]
+    syms = datagen.sweep_data(alphabet, dist)[0]
     w = syms.dtype.itemsize
     C = 16384 // w
     table, ref = check_roundtrip(lr, syms, alphabet, k, r, l, N, C)
@@ -86,7 +86,7 @@ def test_uneven_streams_one_batched_launch(lr):
     Dirichlet tables), encoded and decoded in one batched call each."""
     import torch
     from test_gpu_batch import run_decode_batch, run_encode_batch
-    data = datagen.config4_streams(nstreams=192, seed=4001)
+    data = datagen.dirichlet_streams(nstreams=192, seed=4001)
     k, r, l, C = 14, 16, 16, 8192
     tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C)
     assert (st == 0).all()
@@ -109,7 +109,7 @@ def test_serving_requests_at_full_size_range(lr):
     from test_gpu_serve import device_bytes
     K, R, L, W, N, C = 14, 16, 16, 1, 64, 65536
     params = lr.rans_params.make(K, R, L, W, N, C)
-    reqs = datagen.config5_requests(nreq=40, seed=5201)
+    reqs = datagen.serving_requests(nreq=40, seed=5201)
     staged, want = [], []
     for q in reqs:
         syms = datagen.request_data(q, seed=5201)

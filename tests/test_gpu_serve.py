@@ -27,7 +27,7 @@ def lr():
 def make_requests(lr, nreq, seed, lo=12, hi=20):
     """Small mixed requests: payloads staged in device memory beforehand."""
     import torch
-    reqs = datagen.config5_requests(nreq=nreq, seed=seed, lo_log2=lo, hi_log2=hi)
+    reqs = datagen.serving_requests(nreq=nreq, seed=seed, lo_log2=lo, hi_log2=hi)
     params = lr.rans_params.make(K, R, L, W, N, C)
     out = []
     for q in reqs:
