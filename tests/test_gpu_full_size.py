@@ -137,3 +137,60 @@ def test_serving_requests_at_full_size_range(lr):
             lr.rans_server_release(srv, c.id)
     finally:
         lr.rans_server_destroy(srv)
+
+
+@pytest.mark.parametrize("s", datagen.ZIPF_S)
+def test_prefix_family_256MiB(lr, s):
+    """The prefix-code family at the round-trip size: the GPU container equals
+    the oracle's (its instrumented-decoder multiplexer) and decodes back."""
+    import torch
+    from rans_util import dev
+    w = datagen.zipf_buffer(s)
+    k, _, _, W, N, C = w.params.astuple()
+    f = oracle.quantize(w.counts, k)
+    table = lr.rans_tables_build(w.counts, k)
+    ref = oracle.encode(f, w.syms, k, 16, 16, N, C, threads=THREADS, coder="prefix")
+    p = lr.rans_params.make(k, 16, 16, W, N, C)
+    cap = lr.rans_encode_bound(w.syms.size, p) + 4096
+    d_out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    olen = lr.rans_pfx_encode(table, p, dev(w.syms), w.syms.size, d_out, cap)
+    got = d_out[:olen].cpu().numpy()
+    assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
+    dec = gpu_decode(lr, table, ref, w.syms.size, 1)
+    assert (dec == w.syms).all()
+
+
+def test_escape_64MiB_laplace(lr):
+    """Escape coding at the escape workload's size: 2^25 zigzag Laplace
+    values, 1024-symbol table, about 18% escaped."""
+    rng = np.random.Generator(np.random.PCG64(7001))
+    v = datagen.sample(datagen.laplace_u16_probs(300.0), 1 << 25, rng, np.uint16)
+    T = 1024
+    counts = np.bincount(np.minimum(v, T - 1), minlength=T).astype(np.uint64)
+    f = oracle.quantize(counts, 15)
+    table = lr.rans_tables_build(counts, 15)
+    for r, l in [(16, 16), (8, 23)]:
+        ref = oracle.encode(f, v, 15, r, l, 64, 32768, threads=THREADS, escape=True)
+        got = gpu_encode(lr, table, (15, r, l, 2, 64, 32768, "df", True), v)
+        assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
+        assert (gpu_decode(lr, table, ref, v.size, 2) == v).all()
+
+
+def test_lookup_decode_256MiB(lr):
+    """The fused lookup decode at the dequantisation workload's size: every
+    output element equals lut[the oracle's decoded symbol]."""
+    import torch
+    from rans_util import dev
+    rng = np.random.Generator(np.random.PCG64(6001))
+    syms = datagen.sample(datagen.gaussian_codes_probs(256, 24.0), 1 << 28, rng)
+    counts = datagen.counts(syms, 256)
+    f = oracle.quantize(counts, 14)
+    table = lr.rans_tables_build(counts, 14)
+    ref = oracle.encode(f, syms, 14, 16, 16, 64, 65536, threads=THREADS)
+    lut = ((np.arange(256, dtype=np.int64) - 128) * 977 % 65536).astype(np.uint16)
+    want = lut[oracle.decode(f, ref, threads=THREADS)]
+    d_out = torch.empty(syms.size * 2, dtype=torch.uint8, device="cuda")
+    n = lr.rans_decode_lut(table, dev(ref), ref.size, dev(lut), 2, d_out, syms.size)
+    assert n == syms.size
+    got = d_out.cpu().numpy().view(np.uint16)
+    assert (got == want).all(), first_diff(got.view(np.uint8), want.view(np.uint8))
