@@ -999,8 +999,8 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
         const uint4* S = reinterpret_cast<const uint4*>(src - mis);
         uint4* D = reinterpret_cast<uint4*>(dst + 4 * NL);
         const uint32_t pieces = static_cast<uint32_t>((al - 4 * NL) / 16);
-        for (uint32_t q = lane; q < pieces; q += 64) {
-            uint4 v = funnel16(S[q], S[q + 1], mis);
+        auto piece = [&](uint32_t q, const uint4& lo, const uint4& hi) {
+            uint4 v = funnel16(lo, hi, mis);
             const uint32_t have = pay - 16 * q;  // > 0 for every piece
             if (have < 16) {
                 const uint32_t keep[4] = {have >= 4 ? 4u : have, have >= 8 ? 4u : (have > 4 ? have - 4 : 0u),
@@ -1010,7 +1010,24 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
                 v = make_uint4(m(v.x, keep[0]), m(v.y, keep[1]), m(v.z, keep[2]), m(v.w, keep[3]));
             }
             D[q] = v;
+        };
+        // KU rounds of loads in flight before their stores: one round at a
+        // time would wait a full memory latency per KiB
+        constexpr uint32_t KU = 8;
+        uint32_t q0 = lane;
+        for (; q0 + 64 * (KU - 1) < pieces; q0 += 64 * KU) {
+            uint4 lo[KU], hi[KU];
+#pragma unroll
+            for (uint32_t u = 0; u < KU; ++u) {
+                lo[u] = S[q0 + 64 * u];
+                hi[u] = S[q0 + 64 * u + 1];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < KU; ++u)
+                piece(q0 + 64 * u, lo[u], hi[u]);
         }
+        for (uint32_t q = q0; q < pieces; q += 64)
+            piece(q, S[q], S[q + 1]);
     } else if (lane == 0) {
         atomicMin(status, timeout ? RANS_EINVAL : RANS_ENOSPC);
     }
