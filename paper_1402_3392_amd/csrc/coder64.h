@@ -884,7 +884,7 @@ __device__ __forceinline__ void encode_chunk_pfx(const void* syms_base, uint64_t
     uint32_t nbd = 0;      // bits the lane's decoder holds
     uint32_t q0 = 0, q1 = 0, npend = 0;  // positions read, words not yet complete
     uint32_t bits = 0, wpos = 0, bad = 0;
-    constexpr uint32_t PF = 8;  // symbols loaded this many steps ahead
+    constexpr uint32_t PF = 16;  // symbols loaded this many steps ahead
     auto load = [&](uint32_t t) -> uint32_t {
         const uint64_t i = uint64_t(t) * NL + lane;
         return live && i < nsym ? static_cast<uint32_t>(in[i]) : 0u;
@@ -897,6 +897,12 @@ __device__ __forceinline__ void encode_chunk_pfx(const void* syms_base, uint64_t
 #pragma unroll
         for (uint32_t q = 0; q < PF; ++q)
             nxt[q] = load(t0 + PF + q);
+        // the block's code entries, read before its steps: the LDS latency
+        // stays off the steps' chain
+        uint32_t ent[PF];
+#pragma unroll
+        for (uint32_t q = 0; q < PF; ++q)
+            ent[q] = penc[min(cur[q], alphabet)];
 #pragma unroll
         for (uint32_t q = 0; q < PF; ++q) {
             const uint32_t t = t0 + q;
@@ -914,7 +920,7 @@ __device__ __forceinline__ void encode_chunk_pfx(const void* syms_base, uint64_t
             }
             wpos += __popcll(m);
             if (act) {
-                const uint32_t e = penc[min(cur[q], alphabet)];
+                const uint32_t e = ent[q];
                 const uint32_t len = e >> 16;
                 bad |= len == 0 ? 1u : 0u;
                 acc = (acc << len) | (e & 0xFFFFu);
