@@ -414,7 +414,7 @@ int rans_server_replay(rans_server *server, const rans_server_request *reqs, uin
 #define RANS_KERNEL_COMPACT 3      /* chunk compaction into the container    */
 #define RANS_KERNEL_BATCH_DECODE 4 /* persistent batched decoder             */
 #define RANS_KERNEL_BATCH_ENCODE 5 /* persistent batched encoder             */
-#define RANS_KERNEL_BATCH_PLAN 6   /* batch planning / scans / compaction    */
+#define RANS_KERNEL_BATCH_PLAN 6   /* batch planning (headers, work items)   */
 int rans_timing_enable(int on);
 int rans_timing_reset(void);
 int rans_timing_read(int kind, uint64_t *launches, double *total_ms);

@@ -3,18 +3,20 @@
 // description on the device (a decode job's chunk count lives in its
 // container header), turns chunk counts into work items of G chunks and maps
 // items to jobs; a persistent grid then pulls work items from an atomic
-// counter.  A block restages its LDS table
-// whenever the next work item belongs to another job; each of its G waves
-// codes one chunk with the same N = 32 or 64 chunk coder as the single-buffer
-// kernels.  Encode jobs then get their container laid out per job (scan of
-// chunk lengths, header, directory) and compacted.  No kernel waits on
-// another block: every block leaves when the counter passes the last item.
+// counter.  A block restages its LDS table whenever the next work item
+// belongs to another job; each of its G waves codes one chunk with the same
+// N = 32 or 64 chunk coder as the single-buffer kernels.  An encoded chunk
+// places itself in its job's container at once, by the same look-back over
+// the job's lower chunks as the single-buffer encoder; encode work items are
+// therefore taken strictly in start order (a ticket from the counter), so
+// every chunk a wave waits on belongs to a block that is already running,
+// and the copy overlaps the coding of other items.  Every block leaves when
+// the counter passes the last item.
 #include "coder64.h"
 
 namespace rans {
 namespace {
 
-__device__ __forceinline__ uint64_t align16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
 
 // Completes job j's description: chunk size, symbol count and chunk count
 // (a decode job's come from its container header, which is checked).
@@ -78,66 +80,96 @@ constexpr uint32_t kPrepThreads = 1024;
 constexpr uint32_t kBigJobs = 256;
 constexpr uint32_t kSmallEntries = 32;
 
+// Header words of an encode job's container.
+__device__ __forceinline__ void job_header(const BatchArgs& a, const BatchJob& jb, uint32_t nch, uint32_t* h)
+{
+    h[0] = kMagic;
+    h[1] = 1u | (a.k << 8) | (a.r << 16) | (a.l << 24);
+    h[2] = a.w | (a.bf << 8) | (a.N << 16);
+    h[3] = jb.C;
+    h[4] = static_cast<uint32_t>(jb.n);
+    h[5] = static_cast<uint32_t>(jb.n >> 32);
+    h[6] = nch;
+    h[7] = 0;
+}
+
 __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, bool decode)
 {
-    __shared__ uint32_t part_i[kPrepThreads], part_c[kPrepThreads];
-    __shared__ uint32_t big[kBigJobs];
+    __shared__ uint32_t part_i[kPrepThreads], part_c[kPrepThreads], part_l[kPrepThreads];
+    // jobs whose map entries the whole block writes: job, item base, items,
+    // chunk base, chunks (kept here so the block's loop over them reads no
+    // global memory)
+    __shared__ uint32_t big[kBigJobs][3];
     __shared__ uint32_t nbig;
     const uint32_t T = blockDim.x, tid = threadIdx.x;
     if (tid == 0) {
-        a.counter[0] = a.grid;  // items below grid are taken by block index
+        // decode: items below grid are taken by block index; encode: every
+        // item by ticket, in start order
+        a.counter[0] = decode ? a.grid : 0u;
         nbig = 0;
     }
     // contiguous job ranges per thread, so the scan below is ordered
     const uint32_t per = (a.njobs + T - 1) / T;
     const uint32_t lo = min(a.njobs, tid * per), hi = min(a.njobs, lo + per);
-    uint32_t si = 0, sc = 0;
+    uint32_t si = 0, sc = 0, sl = 0;
     for (uint32_t j = lo; j < hi; ++j) {
         plan_job(a, j, decode);
-        si += (a.jobs[j].nch + a.G - 1) / a.G;
-        sc += a.jobs[j].nch;
+        const uint32_t nch = a.jobs[j].nch;
+        si += (nch + a.G - 1) / a.G;
+        sc += nch;
+        sl += nch + (nch + 63) / 64;  // chunk words and group words
     }
     part_i[tid] = si;
     part_c[tid] = sc;
+    part_l[tid] = sl;
     __syncthreads();
     for (uint32_t o = 1; o < T; o <<= 1) {
-        const uint32_t vi = tid >= o ? part_i[tid - o] : 0, vc = tid >= o ? part_c[tid - o] : 0;
+        const uint32_t vi = tid >= o ? part_i[tid - o] : 0, vc = tid >= o ? part_c[tid - o] : 0,
+                       vl = tid >= o ? part_l[tid - o] : 0;
         __syncthreads();
         part_i[tid] += vi;
         part_c[tid] += vc;
+        part_l[tid] += vl;
         __syncthreads();
     }
-    uint32_t bi = tid ? part_i[tid - 1] : 0, bc = tid ? part_c[tid - 1] : 0;
+    uint32_t bi = tid ? part_i[tid - 1] : 0, bc = tid ? part_c[tid - 1] : 0, bl = tid ? part_l[tid - 1] : 0;
     for (uint32_t j = lo; j < hi; ++j) {
         BatchJob& jb = a.jobs[j];
         jb.item_base = bi;
         jb.chunk_base = bc;
+        jb.lb_base = bl;
         const uint32_t items = (jb.nch + a.G - 1) / a.G;
-        if (items <= kSmallEntries && (decode || jb.nch <= kSmallEntries)) {
-            // the host sized the maps from the jobs' lengths; never exceed them
+        if (items <= kSmallEntries) {
+            // the host sized the map from the jobs' lengths; never exceed it
             for (uint32_t i = 0; i < items; ++i)
                 if (bi + i < a.max_items)
                     a.item_job[bi + i] = j;
-            if (!decode)
-                for (uint32_t c = 0; c < jb.nch; ++c)
-                    if (bc + c < a.max_chunks)
-                        a.chunk_job[bc + c] = j;
         } else {
             const uint32_t slot = atomicAdd(&nbig, 1u);
             if (slot < kBigJobs) {
-                big[slot] = j;
+                big[slot][0] = j;
+                big[slot][1] = bi;
+                big[slot][2] = items;
             } else {
                 for (uint32_t i = 0; i < items; ++i)
                     if (bi + i < a.max_items)
                         a.item_job[bi + i] = j;
-                if (!decode)
-                    for (uint32_t c = 0; c < jb.nch; ++c)
-                        if (bc + c < a.max_chunks)
-                            a.chunk_job[bc + c] = j;
+            }
+        }
+        if (!decode && jb.nch == 0) {  // no chunk will place it: the header-only container
+            *jb.d_out_len = kHeaderBytes;
+            if (jb.out_cap >= kHeaderBytes) {
+                uint32_t h[8];
+                job_header(a, jb, 0, h);
+                for (int q = 0; q < 8; ++q)
+                    reinterpret_cast<uint32_t*>(jb.out)[q] = h[q];
+            } else {
+                *jb.d_status = RANS_ENOSPC;
             }
         }
         bi += items;
         bc += jb.nch;
+        bl += jb.nch + (jb.nch + 63) / 64;
     }
     if (tid == T - 1) {
         a.totals[0] = min(part_i[T - 1], a.max_items);
@@ -146,16 +178,15 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
     __syncthreads();
     const uint32_t nb = min(nbig, kBigJobs);
     for (uint32_t b = 0; b < nb; ++b) {
-        const uint32_t j = big[b];
-        const BatchJob& jb = a.jobs[j];
-        const uint32_t items = (jb.nch + a.G - 1) / a.G;
+        const uint32_t j = big[b][0], ib = big[b][1], items = big[b][2];
         for (uint32_t i = tid; i < items; i += T)
-            if (jb.item_base + i < a.max_items)
-                a.item_job[jb.item_base + i] = j;
-        if (!decode)
-            for (uint32_t c = tid; c < jb.nch; c += T)
-                if (jb.chunk_base + c < a.max_chunks)
-                    a.chunk_job[jb.chunk_base + c] = j;
+            if (ib + i < a.max_items)
+                a.item_job[ib + i] = j;
+    }
+    if (!decode) {  // the placement words start at zero
+        const uint64_t nl = min(uint64_t(part_l[T - 1]), a.max_lookback);
+        for (uint64_t i = tid; i < nl; i += T)
+            a.lookback[i] = 0;
     }
 }
 
@@ -220,11 +251,11 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
     uint8_t* sbuf = lds + a.tab_lds + wave * c64::kEncWaveLds;
     int cur = -1;
     uint32_t item;
-    for (bool first = true;; first = false) {
-        const int j = next_item(a, s_slot, &item, first);
+    for (;;) {
+        const int j = next_item(a, s_slot, &item, false);  // tickets only: start order
         if (j < 0)
             break;
-        const BatchJob& jb = a.jobs[j];
+        BatchJob& jb = a.jobs[j];
         if (j != cur) {
             c64::stage_enc(lds, jb.enc, jb.enc_bytes, a.l + R - a.k);
             __syncthreads();
@@ -232,107 +263,34 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
         }
         const uint32_t nch = c64::uni(jb.nch);
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
-        if (c < nch) {
+        // the job's slots and placement words lie inside what the host sized
+        const bool room = uint64_t(jb.chunk_base) + nch <= a.max_chunks &&
+                          uint64_t(jb.lb_base) + nch + (nch + 63) / 64 <= a.max_lookback;
+        if (!room && c == 0 && (threadIdx.x & 63) == 0)
+            atomicMin(jb.d_status, RANS_EINVAL);
+        if (room && c < nch) {
             const uint64_t g = c64::uni(jb.chunk_base) + uint64_t(c);
+            uint8_t* slot = a.slots + g * a.slot_stride;
+            uint32_t x = 0, nd = 0;
             c64::encode_chunk<R, W, NL, BF>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
-                                    reinterpret_cast<const uint4*>(lds), a.slots + g * a.slot_stride,
-                                    a.slot_bytes, sbuf, a.states + g * 64, a.ndig + g, jb.d_status);
-        }
-    }
-}
-
-// Block per encode job: chunk offsets, directory, header, container length.
-__global__ void __launch_bounds__(256) k_batch_cscan(BatchArgs a)
-{
-    __shared__ uint64_t part[256];
-    const uint32_t j = blockIdx.x;
-    if (j >= a.njobs)
-        return;
-    BatchJob& jb = a.jobs[j];
-    const uint32_t T = blockDim.x, tid = threadIdx.x, nch = jb.nch, db = a.r / 8;
-    const uint32_t per = (nch + T - 1) / T;
-    const uint32_t lo = min(nch, tid * per), hi = min(nch, lo + per);
-    uint64_t sum = 0;
-    for (uint32_t c = lo; c < hi; ++c)
-        sum += align16(4ull * a.N + uint64_t(a.ndig[jb.chunk_base + c]) * db);
-    part[tid] = sum;
-    __syncthreads();
-    for (uint32_t o = 1; o < T; o <<= 1) {
-        const uint64_t v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    const uint64_t base = align16(kHeaderBytes + uint64_t(kDirEntryBytes) * nch);
-    const uint64_t total = nch ? base + part[T - 1] : kHeaderBytes;
-    const bool fits = total <= jb.out_cap;
-    uint64_t off = base + (tid ? part[tid - 1] : 0);
-    for (uint32_t c = lo; c < hi; ++c) {
-        const uint32_t len = 4 * a.N + a.ndig[jb.chunk_base + c] * db;
-        a.chunk_off[jb.chunk_base + c] = off;
-        if (fits) {
-            uint8_t* de = jb.out + kHeaderBytes + uint64_t(kDirEntryBytes) * c;
-            *reinterpret_cast<uint64_t*>(de) = off;
-            reinterpret_cast<uint32_t*>(de)[2] = len;
-            reinterpret_cast<uint32_t*>(de)[3] = 0;
-        }
-        off += align16(len);
-    }
-    if (tid == 0) {
-        jb.total = total;
-        *jb.d_out_len = total;
-        if (fits) {
-            uint32_t* h = reinterpret_cast<uint32_t*>(jb.out);
-            h[0] = kMagic;
-            h[1] = 1u | (a.k << 8) | (a.r << 16) | (a.l << 24);
-            h[2] = a.w | (a.bf << 8) | (a.N << 16);
-            h[3] = jb.C;
-            h[4] = static_cast<uint32_t>(jb.n);
-            h[5] = static_cast<uint32_t>(jb.n >> 32);
-            h[6] = nch;
-            h[7] = 0;
-        } else {
-            atomicMin(jb.d_status, RANS_ENOSPC);
-        }
-    }
-}
-
-// Grid-stride over all chunks of the batch: move each chunk (states + digits
-// from the end of its slot) to its directory offset, zero padding.
-__global__ void __launch_bounds__(256) k_batch_compact(BatchArgs a)
-{
-    const uint32_t nchunks = a.totals[1];
-    for (uint32_t g = blockIdx.x; g < nchunks; g += gridDim.x) {
-        const BatchJob& jb = a.jobs[a.chunk_job[g]];
-        if (jb.total > jb.out_cap)
-            continue;
-        const uint32_t db = a.r / 8, N = a.N;
-        const uint64_t off = a.chunk_off[g];
-        const uint32_t pay = a.ndig[g] * db;
-        const uint32_t words = static_cast<uint32_t>(align16(4ull * N + pay) / 4);
-        const uint8_t* slot_end = a.slots + uint64_t(g) * a.slot_stride + a.slot_bytes;
-        const uint8_t* src = slot_end - pay;
-        uint32_t* dst = reinterpret_cast<uint32_t*>(jb.out + off);
-        for (uint32_t q = threadIdx.x; q < words; q += blockDim.x) {
-            uint32_t v = 0;
-            if (q < N) {
-                v = a.states[uint64_t(g) * 64 + q];
-            } else {
-                const uint32_t p = (q - N) * 4;
-                if (p < pay) {
-                    const uintptr_t ad = reinterpret_cast<uintptr_t>(src + p);
-                    const uintptr_t al = ad & ~uintptr_t(3);
-                    const uint32_t lo = *reinterpret_cast<const uint32_t*>(al);
-                    const uint32_t hi = al + 4 < reinterpret_cast<uintptr_t>(slot_end)
-                                            ? *reinterpret_cast<const uint32_t*>(al + 4)
-                                            : 0u;
-                    v = static_cast<uint32_t>(((uint64_t(hi) << 32) | lo) >> ((ad & 3) * 8));
-                    const uint32_t rem = pay - p;
-                    if (rem < 4)
-                        v &= (1u << (8 * rem)) - 1;
-                }
-            }
-            dst[q] = v;
+                                            reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes, sbuf,
+                                            nullptr, nullptr, jb.d_status, &x, &nd);
+            PlaceArgs pa;
+            pa.ticket = nullptr;
+            pa.lookback = a.lookback + c64::uni(jb.lb_base);
+            pa.out = jb.out;
+            pa.out_cap = jb.out_cap;
+            pa.total = &jb.total;
+            pa.total_out = jb.d_out_len;
+            uint32_t h[8];
+            job_header(a, jb, nch, h);
+            for (int q = 0; q < 8; ++q)
+                reinterpret_cast<uint32_t*>(pa.hdr)[q] = h[q];
+            // the digits end at the slot's end; the stride leaves 256 bytes
+            // after it for the copy's reads past them
+            nd = c64::uni(nd);
+            c64::place_chunk<R, NL>(c, nch, x, nd, slot + a.slot_bytes - uint64_t(nd) * (R / 8), pa,
+                                    jb.d_status);
         }
     }
 }
@@ -427,11 +385,7 @@ hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, L
         e = persistent_encode_w<8, true>(a, W, grid, st);
     else
         e = persistent_encode_w<8, false>(a, W, grid, st);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_batch_cscan, dim3(a.njobs), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(k_batch_compact, dim3(4096), dim3(256), 0, st, a);
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace rans

@@ -29,21 +29,19 @@ int num_cus()
 }
 
 struct Region {
-    uint64_t ctrl, jobs, item_job, chunk_job, slots, states, ndig, chunk_off, total;
+    uint64_t ctrl, jobs, item_job, slots, lookback, total;
 };
 
-Region layout_for(uint32_t njobs, uint64_t max_items, uint64_t max_chunks, uint64_t slot_stride)
+Region layout_for(uint32_t njobs, uint64_t max_items, uint64_t max_chunks, uint64_t slot_stride,
+                  uint64_t max_lookback)
 {
     Region r{};
     r.ctrl = 0;  // counter + totals
     r.jobs = 256;
     r.item_job = up256(r.jobs + sizeof(BatchJob) * uint64_t(njobs));
-    r.chunk_job = up256(r.item_job + 4 * max_items);
-    r.slots = up256(r.chunk_job + 4 * max_chunks);
-    r.states = up256(r.slots + slot_stride * max_chunks);
-    r.ndig = up256(r.states + 256 * max_chunks);
-    r.chunk_off = up256(r.ndig + 4 * max_chunks);
-    r.total = up256(r.chunk_off + 8 * max_chunks);
+    r.slots = up256(r.item_job + 4 * max_items);
+    r.lookback = up256(r.slots + slot_stride * max_chunks);
+    r.total = up256(r.lookback + 8 * max_lookback);
     return r;
 }
 
@@ -79,7 +77,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     const uint32_t G = cfg.waves_per_group;
 
     // host checks of every descriptor and the launch shape they imply
-    uint64_t max_items = 0, max_chunks = 0;
+    uint64_t max_items = 0, max_chunks = 0, max_lookback = 0;
     uint32_t tab_lds = 0, sw = 0;
     Layout layout = kPacked;
     std::vector<BatchJob> hj(njobs);
@@ -120,6 +118,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             if (nch > 0xFFFFFFFFull)
                 return RANS_EINVAL;
             max_chunks += nch;
+            max_lookback += nch + (nch + 63) / 64;
             max_items += (nch + G - 1) / G;
             tab_lds = tab_lds > b.enc_bytes ? tab_lds : b.enc_bytes;
         }
@@ -175,7 +174,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             tab_lds = tab_lds > b.sym_bytes + b.ent_bytes ? tab_lds : b.sym_bytes + b.ent_bytes;
         }
     }
-    if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull)
+    if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull || max_lookback > 0xFFFFFFF0ull)
         return RANS_EINVAL;
     const uint32_t per_wave = decode ? decode64_lds_per_wave(layout) : kEncWaveLdsBytes;
     if (uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
@@ -183,7 +182,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
 
     const uint64_t slot_bytes = decode ? 0 : slot_bytes_for(p.chunk_syms, p.prob_bits, R);
     const uint64_t slot_stride = decode ? 0 : slot_bytes + 256;
-    const Region rg = layout_for(njobs, max_items ? max_items : 1, max_chunks, slot_stride);
+    const Region rg = layout_for(njobs, max_items ? max_items : 1, max_chunks, slot_stride, max_lookback);
 
     Workspace* ws = workspace_for(st);
     if (!ws)
@@ -210,15 +209,13 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     a.counter = reinterpret_cast<uint32_t*>(base + rg.ctrl);
     a.totals = a.counter + 4;
     a.item_job = reinterpret_cast<uint32_t*>(base + rg.item_job);
-    a.chunk_job = reinterpret_cast<uint32_t*>(base + rg.chunk_job);
     a.max_items = static_cast<uint32_t>(max_items ? max_items : 1);
     a.max_chunks = static_cast<uint32_t>(max_chunks);
     a.slots = base + rg.slots;
     a.slot_bytes = slot_bytes;
     a.slot_stride = slot_stride;
-    a.states = reinterpret_cast<uint32_t*>(base + rg.states);
-    a.ndig = reinterpret_cast<uint32_t*>(base + rg.ndig);
-    a.chunk_off = reinterpret_cast<uint64_t*>(base + rg.chunk_off);
+    a.lookback = reinterpret_cast<uint64_t*>(base + rg.lookback);
+    a.max_lookback = max_lookback;
     a.tab_lds = (tab_lds + 15) & ~15u;
     const uint32_t grid = static_cast<uint32_t>(num_cus()) * cfg.groups_per_cu;
     a.grid = grid;

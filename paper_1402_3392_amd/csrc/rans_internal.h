@@ -158,6 +158,7 @@ struct BatchJob {
     uint32_t C, nch;       // symbols per chunk, chunks (0 when the job failed)
     uint32_t item_base;    // first work item
     uint32_t chunk_base;   // first global chunk (encode slots)
+    uint32_t lb_base;      // encode: the job's placement words (nch chunk words, then its groups')
 };
 
 struct BatchArgs {
@@ -166,18 +167,16 @@ struct BatchArgs {
     uint32_t k, r, l, w, N, C;  // C: encode chunk size (0 = whole input)
     uint32_t bf;                // breadth-first digit order (Section 5)
     uint32_t G;                 // chunks per work item = waves per block
-    uint32_t* counter;          // work-queue head, zeroed before the pass
+    uint32_t* counter;          // work-queue head, set by the planning kernel
     uint32_t* totals;           // [0] work items, [1] chunks
     uint32_t* item_job;         // work item -> job
-    uint32_t* chunk_job;        // global chunk -> job (encode)
     uint32_t max_items, max_chunks;
     uint8_t* slots;             // encode: one slot per global chunk
     uint64_t slot_bytes, slot_stride;
-    uint32_t* states;           // encode: 64 per global chunk
-    uint32_t* ndig;
-    uint64_t* chunk_off;
+    uint64_t* lookback;         // encode: placement words of every job, zeroed by the planning kernel
+    uint64_t max_lookback;      // their count (bounds the zeroing)
     uint32_t tab_lds;           // LDS bytes reserved for the largest table
-    uint32_t grid;              // persistent blocks; block b starts with work item b
+    uint32_t grid;              // persistent blocks; decode: block b starts with work item b
 };
 
 // Launchers (kernels.hip).  All asynchronous on `stream`.

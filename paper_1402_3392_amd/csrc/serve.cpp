@@ -130,7 +130,7 @@ namespace {
 uint64_t request_cost(const rans_server* s, int op, uint64_t in_len, uint64_t out_cap)
 {
     // encode also holds its digit slots (up to 2 bytes per symbol plus the
-    // per-chunk states) in the stream's workspace while it runs
+    // per-chunk placement words) in the stream's workspace while it runs
     const uint64_t scratch = op == RANS_OP_ENCODE ? 2 * in_len + in_len / 64 + 4096 : 0;
     (void)s;
     return ((in_len + 255) & ~uint64_t(255)) + ((out_cap + 255) & ~uint64_t(255)) + scratch;
