@@ -541,8 +541,9 @@ static_assert(kEncWaveLds == 1024 + kEncRing + 128, "encoder LDS layout");
 constexpr uint32_t kFlushStores = 8;
 
 // Stages the encoder entries of a table into LDS for one parameter set,
-// sh = l + r - k.  Table entry {magic, f | cum << 16, sh1 | sh2 << 8, M - f}
-// becomes {magic, x_max - 1, cum | sh2 << 16, (M - f) | bad << 23 | sh1 << 24}
+// sh = l + r - k.  Table entry {m, f | cum << 16, inc | dsh << 8, M - f}
+// (q = x / f = mulhi(x + inc, m) >> dsh) becomes
+// {m, x_max - 1, cum | dsh << 16, (M - f) | bad << 23 | inc << 24}
 // with x_max = f * 2^sh the bound of Algorithm 1's renormalisation (no digit
 // is emitted once x < x_max; x_max >= 2^32 is stored as 2^32 - 1, which no
 // state exceeds) and bad = (f == 0), a symbol the table cannot encode.  The
@@ -561,11 +562,11 @@ __device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32
         const bool raw = esc != ~0u && (i >= esc || (e.y & 0xFFFFu) == 0);
         if (raw)
             e = src[esc];
-        const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16, sh1 = e.z & 0xFFu, sh2 = e.z >> 8;
+        const uint32_t f = e.y & 0xFFFFu, cum = e.y >> 16, inc = e.z & 0xFFu, dsh = e.z >> 8;
         const uint64_t xm = uint64_t(f) << sh;
         d[i] = make_uint4(e.x, (f == 0 || xm > 0xFFFFFFFFull) ? 0xFFFFFFFFu : static_cast<uint32_t>(xm - 1),
-                          cum | (sh2 << 16) | (raw ? 1u << 31 : 0u),
-                          e.w | (f == 0 ? (1u << 23) : 0u) | (sh1 << 24));
+                          cum | (dsh << 16) | (raw ? 1u << 31 : 0u),
+                          e.w | (f == 0 ? (1u << 23) : 0u) | (inc << 24));
     }
 }
 
@@ -614,11 +615,11 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     if (act) {
-        // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
-        // Granlund-Montgomery multiply-high division
-        const uint32_t th = __umulhi(e.x, x);
-        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> ((e.z >> 16) & 31u);
-        x = __umul24(q, e.w) + x + (e.z & 0xFFFFu);
+        // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f
+        // by one multiply-high (the entry's m, inc and shift); the 24-bit
+        // multiply reads M - f (bit 23 is set only on entries that are errors)
+        const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
+        x = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
     }
 }
 
@@ -665,9 +666,8 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     if (act) {
-        const uint32_t th = __umulhi(e.x, x);
-        const uint32_t q = (th + ((x - th) >> (e.w >> 24))) >> ((e.z >> 16) & 31u);
-        x = __umul24(q, e.w) + x + (e.z & 0xFFFFu);
+        const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
+        x = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
     }
 }
 

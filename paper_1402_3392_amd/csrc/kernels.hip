@@ -321,8 +321,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_encode(const EncodeArgs a)
             }
         }
         if (act) {
-            const uint32_t th = __umulhi(e.x, x);
-            const uint32_t q = (th + ((x - th) >> (e.z & 0xFFu))) >> (e.z >> 8);
+            const uint32_t q = __umulhi(e.x, x + (e.z & 0xFFu)) >> (e.z >> 8);
             x = x + __umul24(q, e.w) + cum;
         }
     }

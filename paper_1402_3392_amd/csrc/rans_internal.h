@@ -46,11 +46,11 @@ struct DevTable {
 };
 
 // Encoder entry, one per symbol (uint4):
-//   x = GM magic m'      (Granlund & Montgomery, "Division by invariant
-//                         integers using multiplication", PLDI 1994, Fig. 4.1)
+//   x = m                (q = x / f = mulhi(x + inc, m) >> sh: Robison,
+//                         "N-bit unsigned division via N-bit multiply-add")
 //   y = f | cum << 16
-//   z = sh1 | sh2 << 8   (the two shifts of that method)
-//   w = M - f            (C(s,x) = x + q*(M - f) + cum with q = x / f)
+//   z = inc | sh << 8
+//   w = M - f            (C(s,x) = x + q*(M - f) + cum)
 
 struct DecodeArgs {
     const uint8_t* in;

@@ -70,25 +70,43 @@ int quantize(const uint64_t* counts, uint32_t alphabet, uint32_t k, uint32_t* f)
     return RANS_OK;
 }
 
-// Granlund-Montgomery constants for dividing a 32-bit x by f (1 <= f < 2^31):
-// l = ceil(log2 f), m' = floor(2^32 (2^l - f) / f) + 1, sh1 = min(l,1),
-// sh2 = max(l-1,0); then q = (t + ((x - t) >> sh1)) >> sh2 with
-// t = mulhi(m', x) equals floor(x / f) for every x < 2^32.
-static void gm_constants(uint32_t f, uint32_t* magic, uint32_t* sh1, uint32_t* sh2)
+// Division constants for q = floor(x / f) with one 32-bit multiply-high
+// (A. D. Robison, "N-bit unsigned division via N-bit multiply-add", ARITH
+// 2005): q = mulhi(x + inc, m) >> sh.  For f = 2^t, t >= 1: m = 2^31,
+// sh = t - 1, inc = 0 (exact for every 32-bit x).  f = 1: m = 2^32 - 1,
+// inc = 1, sh = 0.  Otherwise, with t = floor(log2 f), m0 = floor(2^(32+t)
+// / f) and r = 2^(32+t) - m0 f: the rounded-up multiplier m0 + 1 is exact
+// when f - r <= 2^t, else the rounded-down m0 with the increment is (then
+// r < 2^t); both for every x < 2^32 - 1.  The encoder's states stay below
+// f 2^(l+r-k) <= 2^32, so only f = M = 2^k (a power of two >= 2) meets
+// x = 2^32 - 1.
+static void div_constants(uint32_t f, uint32_t* magic, uint32_t* inc, uint32_t* sh)
 {
-    uint32_t l = 0;
-    while ((1ull << l) < f)
-        ++l;
-    const uint64_t m = ((1ull << 32) * ((1ull << l) - f)) / f + 1;
-    *magic = static_cast<uint32_t>(m);
-    *sh1 = l < 1 ? l : 1;
-    *sh2 = l > 1 ? l - 1 : 0;
+    uint32_t t = 0;
+    while ((2ull << t) <= f)
+        ++t;
+    if (f == 1) {
+        *magic = 0xFFFFFFFFu;
+        *inc = 1;
+        *sh = 0;
+    } else if ((f & (f - 1)) == 0) {
+        *magic = 1u << 31;
+        *inc = 0;
+        *sh = t - 1;
+    } else {
+        const uint64_t p = 1ull << (32 + t);
+        const uint64_t m0 = p / f, r = p - m0 * f;
+        const bool up = f - r <= (1ull << t);
+        *magic = static_cast<uint32_t>(up ? m0 + 1 : m0);
+        *inc = up ? 0 : 1;
+        *sh = t;
+    }
 }
 
-static inline uint32_t gm_divide(uint32_t x, uint32_t magic, uint32_t sh1, uint32_t sh2)
+static inline uint32_t div_apply(uint32_t x, uint32_t magic, uint32_t inc, uint32_t sh)
 {
-    const uint32_t t = static_cast<uint32_t>((static_cast<uint64_t>(magic) * x) >> 32);
-    return (t + ((x - t) >> sh1)) >> sh2;
+    const uint32_t xi = x + inc;  // 32-bit, as on the device
+    return static_cast<uint32_t>((static_cast<uint64_t>(magic) * xi) >> 32) >> sh;
 }
 
 static uint64_t pad16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
@@ -207,12 +225,12 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
             }
         }
         fc[s] = f[s] | (cum[s] << 16);
-        uint32_t magic = 0, sh1 = 0, sh2 = 0;
+        uint32_t magic = 0, inc = 0, sh = 0;
         if (f[s] != 0)
-            gm_constants(f[s], &magic, &sh1, &sh2);
+            div_constants(f[s], &magic, &inc, &sh);
         enc[4 * s + 0] = magic;
         enc[4 * s + 1] = f[s] | (cum[s] << 16);
-        enc[4 * s + 2] = sh1 | (sh2 << 8);
+        enc[4 * s + 2] = inc | (sh << 8);
         enc[4 * s + 3] = M - f[s];
     }
     // entry `alphabet` stays all-zero: f = 0 marks "not encodable"
@@ -295,19 +313,25 @@ extern "C" void rans_table_destroy(rans_table* table)
 }
 
 // Host-side check of the division constants (not part of the C ABI header):
-// for every f in [1, fmax] compares the Granlund-Montgomery quotient with
-// x / f at the bounds, at multiples of f and at `samples` pseudo-random x.
-// Returns the number of mismatches.
+// for every f in [1, fmax] compares mulhi(x + inc, m) >> sh with x / f at
+// the ends of the domain (x = 2^32 - 1 only for powers of two >= 2), around
+// multiples of f and at `samples` pseudo-random x.  Returns the number of
+// mismatches.
 extern "C" uint64_t rans_internal_check_division(uint32_t fmax, uint32_t samples)
 {
     uint64_t bad = 0, seed = 0x9E3779B97F4A7C15ull;
     for (uint32_t f = 1; f <= fmax; ++f) {
-        uint32_t magic, sh1, sh2;
-        gm_constants(f, &magic, &sh1, &sh2);
-        auto chk = [&](uint32_t x) { bad += gm_divide(x, magic, sh1, sh2) != x / f; };
+        uint32_t magic, inc, sh;
+        div_constants(f, &magic, &inc, &sh);
+        const bool full = f >= 2 && (f & (f - 1)) == 0;
+        auto chk = [&](uint32_t x) {
+            if (x != 0xFFFFFFFFu || full)
+                bad += div_apply(x, magic, inc, sh) != x / f;
+        };
         chk(0);
         chk(0xFFFFFFFFu);
-        chk(0xFFFFFFFFu - f);
+        chk(0xFFFFFFFEu);
+        chk(0xFFFFFFFEu - f);
         for (uint64_t m = f; m < (1ull << 32); m += (uint64_t(f) << 12) + f) {
             chk(static_cast<uint32_t>(m));
             chk(static_cast<uint32_t>(m - 1));
