@@ -531,6 +531,9 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         atomicMin(status, RANS_ECORRUPT);
 }
 
+// Four dwords as the compiler's vector type (for the non-temporal builtins).
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
 // Per-wave LDS of the encoder: a 1 KiB symbol block, a 4 KiB digit ring,
 // then 128 bytes where lanes with nothing to emit write.
 constexpr uint32_t kEncRing = 4096;
@@ -744,9 +747,13 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     flush();  // the tail is shorter than a block: at most 8 windows
 
     if (nblk > 0) {
-        // block b = symbols [b*NL*SPB, (b+1)*NL*SPB); lane loads 16 bytes
+        // block b = symbols [b*NL*SPB, (b+1)*NL*SPB); lane loads 16 bytes,
+        // marked non-temporal (each symbol is read once)
         const uint4* blk = reinterpret_cast<const uint4*>(in) + lane;
-        auto load_blk = [&](int64_t b) { return blk[(b < 0 ? 0 : b) * 64]; };
+        auto load_blk = [&](int64_t b) {
+            const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(blk + (b < 0 ? 0 : b) * 64));
+            return make_uint4(v.x, v.y, v.z, v.w);
+        };
         // The block's symbols are read from LDS up front and each step's
         // entry PF steps ahead, in program order before the steps' digit
         // writes: the reads stay off the state's dependency chain.
@@ -1015,7 +1022,12 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
                 auto m = [](uint32_t w, uint32_t nb) { return nb >= 4 ? w : (nb ? w & ((1u << (8 * nb)) - 1) : 0u); };
                 v = make_uint4(m(v.x, keep[0]), m(v.y, keep[1]), m(v.z, keep[2]), m(v.w, keep[3]));
             }
-            D[q] = v;
+            v4u t;  // the container is not read again here: a non-temporal store
+            t.x = v.x;
+            t.y = v.y;
+            t.z = v.z;
+            t.w = v.w;
+            __builtin_nontemporal_store(t, reinterpret_cast<v4u*>(D + q));
         };
         // KU rounds of loads in flight before their stores: one round at a
         // time would wait a full memory latency per KiB
