@@ -587,8 +587,9 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
                                          bool act, uint8_t* dring, uint32_t lane)
 {
     constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
-    if (act)
-        bad |= e.w;
+    // idle lanes keep their state through selects, not branches (an
+    // exec-mask branch per step splits the unrolled loop into blocks)
+    bad |= act ? e.w : 0u;
     const bool e1 = act && x > e.y;
     // every lane writes (lanes with nothing to emit into the area after the
     // ring), the address picked by a select on the ballot mask: no exec-mask
@@ -617,13 +618,12 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         dring[o2] = static_cast<uint8_t>(x);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
-    if (act) {
-        // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f
-        // by one multiply-high (the entry's m, inc and shift); the 24-bit
-        // multiply reads M - f (bit 23 is set only on entries that are errors)
-        const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
-        x = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
-    }
+    // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
+    // one multiply-high (the entry's m, inc and shift); the 24-bit multiply
+    // reads M - f (bit 23 is set only on entries that are errors)
+    const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
+    const uint32_t xn = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
+    x = act ? xn : x;
 }
 
 // Encoder step with escape coding (16-bit symbols, depth-first).  The value
@@ -640,8 +640,7 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
 {
     constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
     const bool esc = act && (e.z >> 31) != 0;
-    if (act)
-        bad |= e.w;
+    bad |= act ? e.w : 0u;
     const bool e1 = act && x > e.y;
     const uint64_t m1 = ballot(e1), me = ballot(esc);
     if (R == 16) {
@@ -668,10 +667,9 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
         dring[o4] = static_cast<uint8_t>(v);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
-    if (act) {
-        const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
-        x = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
-    }
+    const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
+    const uint32_t xn = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
+    x = act ? xn : x;
 }
 
 // Encodes chunk `chunk` of syms_base (n symbols, C per chunk, NL = 32 or 64
@@ -757,30 +755,40 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         // The block's symbols are read from LDS up front and each step's
         // entry PF steps ahead, in program order before the steps' digit
         // writes: the reads stay off the state's dependency chain.
+        // A block of 32 steps (8-bit symbols, N = 32) runs as two halves of
+        // 16, so that its symbols fit in registers next to the rest.
         constexpr int PF = 3;
+        constexpr int HB = SPB > 16 ? 16 : int(SPB);
         auto run_blk = [&](uint4 v) {
             lane_fence();
             *reinterpret_cast<uint4*>(sbuf + 16 * lane) = v;
             lane_fence();
             const InT* sb = reinterpret_cast<const InT*>(sbuf) + lane;
-            uint32_t sy[SPB];  // entry index (ESC: the value itself)
 #pragma unroll
-            for (int q = 0; q < int(SPB); ++q)
-                sy[q] = ESC ? static_cast<uint32_t>(sb[q * NL]) : min(static_cast<uint32_t>(sb[q * NL]), alphabet);
-            lane_fence();  // the symbols are in registers before the ring writes
-            auto entry = [&](int q) { return l_enc[ESC ? min(sy[q], alphabet) : sy[q]]; };
-            uint4 ent[SPB];
+            for (int h = int(SPB) / HB - 1; h >= 0; --h) {
+                uint32_t sy[HB];  // entry index (ESC: the value itself)
+                if (h + 1 < int(SPB) / HB)
+                    lane_fence();  // read after the first half's steps
 #pragma unroll
-            for (int q = SPB - 1; q >= int(SPB) - PF && q >= 0; --q)
-                ent[q] = entry(q);
+                for (int q = 0; q < HB; ++q) {
+                    const uint32_t v0 = static_cast<uint32_t>(sb[(h * HB + q) * NL]);
+                    sy[q] = ESC ? v0 : min(v0, alphabet);
+                }
+                lane_fence();  // the symbols are in registers before the ring writes
+                auto entry = [&](int q) { return l_enc[ESC ? min(sy[q], alphabet) : sy[q]]; };
+                uint4 ent[HB];
 #pragma unroll
-            for (int q = SPB - 1; q >= 0; --q) {
-                if (q - PF >= 0)
-                    ent[q - PF] = entry(q - PF);
-                if (ESC)
-                    enc_step_esc<R>(x, wpos, bad, ent[q], sy[q], live, dring, lane);
-                else
-                    enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
+                for (int q = HB - 1; q >= HB - PF && q >= 0; --q)
+                    ent[q] = entry(q);
+#pragma unroll
+                for (int q = HB - 1; q >= 0; --q) {
+                    if (q - PF >= 0)
+                        ent[q - PF] = entry(q - PF);
+                    if (ESC)
+                        enc_step_esc<R>(x, wpos, bad, ent[q], sy[q], live, dring, lane);
+                    else
+                        enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
+                }
             }
             flush();
         };
