@@ -60,12 +60,12 @@ uint32_t max_digits(uint32_t k, uint32_t r) { return (k + r - 1) / r; }
 // Raw digits an escaped 16-bit value adds (escape coding).
 uint32_t raw_digits(uint32_t r) { return 16 / r; }
 
-// Digit slot of one chunk: room for its largest stream, rounded to 256 bytes
-// (the encoder writes whole 256-byte windows, aligned to the slot).
+// Digit slot of one chunk: room for its largest stream, rounded to whole
+// encoder windows (kSlotAlign bytes, aligned to the slot's end).
 uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r, bool esc)
 {
     const uint64_t per = max_digits(k, r) + (esc ? raw_digits(r) : 0);
-    return (uint64_t(C) * per * (r / 8) + 255) & ~uint64_t(255);
+    return (uint64_t(C) * per * (r / 8) + kSlotAlign - 1) & ~(kSlotAlign - 1);
 }
 
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch)
@@ -270,7 +270,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     ea->enc = pfx ? reinterpret_cast<const uint4*>(t.pfx_enc) : t.enc;
     ea->enc_bytes = static_cast<uint32_t>(pfx ? t.pfx_enc_bytes : t.enc_bytes);
     ea->slot_bytes = sb;
-    ea->slot_stride = sb + 256;
+    ea->slot_stride = sb + kSlotPad;
 
     *sa = ScanArgs{};
     sa->n_chunks = nch;
@@ -283,7 +283,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
 
     *ca = CompactArgs{};
     ca->slot_bytes = sb;
-    ca->slot_stride = sb + 256;
+    ca->slot_stride = sb + kSlotPad;
     ca->n_chunks = nch;
     ca->N = N;
     ca->digit_bytes = R / 8;

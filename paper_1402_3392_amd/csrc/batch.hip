@@ -286,8 +286,8 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
             job_header(a, jb, nch, h);
             for (int q = 0; q < 8; ++q)
                 reinterpret_cast<uint32_t*>(pa.hdr)[q] = h[q];
-            // the digits end at the slot's end; the stride leaves 256 bytes
-            // after it for the copy's reads past them
+            // the digits end at the slot's end; the stride leaves room after
+            // it for the copy's reads past them
             nd = c64::uni(nd);
             c64::place_chunk<R, NL>(c, nch, x, nd, slot + a.slot_bytes - uint64_t(nd) * (R / 8), pa,
                                     jb.d_status);

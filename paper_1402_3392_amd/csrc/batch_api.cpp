@@ -181,7 +181,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         return RANS_EINVAL;
 
     const uint64_t slot_bytes = decode ? 0 : slot_bytes_for(p.chunk_syms, p.prob_bits, R);
-    const uint64_t slot_stride = decode ? 0 : slot_bytes + 256;
+    const uint64_t slot_stride = decode ? 0 : slot_bytes + kSlotPad;
     const Region rg = layout_for(njobs, max_items ? max_items : 1, max_chunks, slot_stride, max_lookback);
 
     Workspace* ws = workspace_for(st);

@@ -14,7 +14,7 @@
 //  * symbols arrive in 1 KiB blocks, one 16-byte load per lane issued a block
 //    ahead and transposed through LDS;
 //  * digits go to a per-wave LDS ring at positions from a ballot prefix and
-//    reach HBM a 256-byte window at a time, one coalesced 4-byte store per
+//    reach HBM a 1 KiB window at a time, one coalesced 16-byte store per
 //    lane, instead of a scattered 2-byte store per lane and step.
 #pragma once
 
@@ -539,9 +539,15 @@ typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 constexpr uint32_t kEncRing = 4096;
 constexpr uint32_t kEncWaveLds = kEncWaveLdsBytes;
 static_assert(kEncWaveLds == 1024 + kEncRing + 128, "encoder LDS layout");
-// Window stores per flush: a block of symbols (1 KiB) emits at most 2 KiB
-// of digits, i.e. completes at most 8 windows of 256 bytes.
-constexpr uint32_t kFlushStores = 8;
+// Digits leave the ring in windows of kEncWindow bytes, aligned to
+// multiples of it in the slot (slot sizes are multiples of it), one 16-byte
+// store per lane.  Window stores per flush: after a flush fewer than
+// kEncWindow bytes stay pending, and a block of symbols (1 KiB) adds at
+// most 2 KiB of digits, so a flush completes at most 2 windows.
+constexpr uint32_t kEncWindow = 1024;
+constexpr uint32_t kFlushStores = 2;
+static_assert(kEncWindow == kSlotAlign && kSlotPad >= kEncWindow && kEncRing % kEncWindow == 0,
+              "encoder windows, slots and ring");
 
 // Stages the encoder entries of a table into LDS for one parameter set,
 // sh = l + r - k.  Table entry {m, f | cum << 16, inc | dsh << 8, M - f}
@@ -674,14 +680,14 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
 
 // Encodes chunk `chunk` of syms_base (n symbols, C per chunk, NL = 32 or 64
 // interleaved coders) into the digit slot `slot` (digits end at slot +
-// slot_bytes, a multiple of 256; 256 more bytes follow), writes the NL final
+// slot_bytes, a multiple of kEncWindow; kSlotPad more bytes follow), writes the NL final
 // states to states_out and the digit count to *ndig_out (or to the
 // caller's x_out / nd_out).  l_enc: LDS encoder entries staged by stage_enc
 // (alphabet + 1);
 // wave_lds: this wave's kEncWaveLds bytes.  Digits reach the slot from the
-// LDS ring a 256-byte window at a time, one 4-byte store per lane: after
-// every block of symbols, the windows the stream has grown past, padded to
-// kFlushStores stores with stores to the 256 bytes after the slot.  A fixed
+// LDS ring a window at a time, one 16-byte store per lane: after every block
+// of symbols, the windows the stream has grown past, padded to kFlushStores
+// stores with stores to the kSlotPad bytes after the slot.  A fixed
 // number of memory operations per block lets the compiler's wait for the
 // symbols of the next block leave the recent stores in flight.  BF: as in
 // enc_step.  ESC: escape coding, as in enc_step_esc; l_enc staged with the
@@ -698,7 +704,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     static_assert(!ESC || (W == 2 && !BF), "escape coding: 16-bit symbols, depth-first");
     using InT = typename std::conditional<W == 1, uint8_t, uint16_t>::type;
     constexpr uint32_t SPB = 1024 / (W * NL);  // steps per 1 KiB symbol block
-    constexpr uint32_t DB = R / 8, WD = 256 / DB;  // bytes per digit, digits per window
+    constexpr uint32_t DB = R / 8, WD = kEncWindow / DB;  // bytes per digit, digits per window
     const uint32_t lane = threadIdx.x & 63;
     const bool live = NL == 64 || lane < NL;
     uint8_t* sbuf = wave_lds;
@@ -714,19 +720,19 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     uint32_t wtop = top;  // digits from wtop up are in the slot
     uint32_t bad = 0;
 
-    auto ring_word = [&](uint32_t lo) {  // this lane's word of the ring window of digits [lo, lo + WD)
-        return reinterpret_cast<const uint32_t*>(dring + ((lo * DB) & (kEncRing - 1)))[lane];
+    auto ring_word = [&](uint32_t lo) {  // this lane's 16 bytes of the ring window of digits [lo, lo + WD)
+        return reinterpret_cast<const uint4*>(dring + ((lo * DB) & (kEncRing - 1)))[lane];
     };
     auto flush = [&]() {
         const uint32_t wc = (wpos + WD - 1) / WD * WD;  // lowest window boundary at or above wpos
-        const uint32_t cnt = (wtop - wc) / WD;          // complete windows not yet stored (<= 8)
+        const uint32_t cnt = (wtop - wc) / WD;          // complete windows not yet stored (<= 2)
         lane_fence();
 #pragma unroll
         for (uint32_t j = 0; j < kFlushStores; ++j) {
             const uint32_t lo = wtop - (j + 1) * WD;
             uint8_t* dst = j < cnt ? slot + uint64_t(lo) * DB : slot + slot_bytes;
-            const uint32_t v = ring_word(lo);
-            reinterpret_cast<uint32_t*>(dst)[lane] = v;
+            const uint4 v = ring_word(lo);
+            reinterpret_cast<uint4*>(dst)[lane] = v;
         }
         lane_fence();
         wtop = wc;
@@ -742,7 +748,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         else
             enc_step<R, BF>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
     }
-    flush();  // the tail is shorter than a block: at most 8 windows
+    flush();  // the tail is shorter than a block: at most 2 windows
 
     if (nblk > 0) {
         // block b = symbols [b*NL*SPB, (b+1)*NL*SPB); lane loads 16 bytes,
@@ -810,8 +816,8 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     }
     if (wpos < wtop) {  // the window holding the stream's first digits
         lane_fence();
-        const uint32_t v = ring_word(wtop - WD);
-        reinterpret_cast<uint32_t*>(slot + uint64_t(wtop - WD) * DB)[lane] = v;
+        const uint4 v = ring_word(wtop - WD);
+        reinterpret_cast<uint4*>(slot + uint64_t(wtop - WD) * DB)[lane] = v;
     }
     if (states_out && live)
         states_out[lane] = x;

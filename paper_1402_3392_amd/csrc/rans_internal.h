@@ -200,6 +200,12 @@ inline uint32_t lut_lds_bytes(uint32_t alphabet, int lw) { return (alphabet * ui
 // LDS per wave of the one-wave-per-chunk encoder: 1 KiB symbol block, 4 KiB
 // digit ring, 128 bytes for the writes of lanes with nothing to emit.
 constexpr uint32_t kEncWaveLdsBytes = 5248;
+// Encoder digit slots: sizes are multiples of kSlotAlign (the encoder
+// writes whole windows of that size, aligned to multiples of it), and
+// kSlotPad bytes follow every slot (stores that pad a block's window count,
+// and reads just past a chunk's digits).
+constexpr uint64_t kSlotAlign = 1024;
+constexpr uint64_t kSlotPad = 1024;
 
 // Batched pass (batch.hip).  `decode` selects the direction.
 hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, Layout layout,
