@@ -579,6 +579,20 @@ __device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32
     }
 }
 
+// x + cum + q (M - f) from a staged entry (cum in the low half of z, M - f in
+// the low 24 bits of w): one add reading z's low half in place and one
+// 24-bit multiply-add, where the compiler otherwise masks, multiplies and
+// adds three operands.
+__device__ __forceinline__ uint32_t c_update(uint32_t x, uint32_t q, uint32_t z, uint32_t w)
+{
+    uint32_t xc, xn;
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(xc)
+        : "v"(x), "v"(z));
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(xn) : "v"(q), "v"(w), "v"(xc));
+    return xn;
+}
+
 // One encoder step (Algorithm 1's Encode with rANS's C) for every lane:
 // emits the digits the renormalisation drops into the wave's LDS digit ring
 // (at their slot positions modulo the ring; positions from a ballot prefix,
@@ -628,8 +642,7 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
     // one multiply-high (the entry's m, inc and shift); the 24-bit multiply
     // reads M - f (bit 23 is set only on entries that are errors)
     const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
-    const uint32_t xn = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
-    x = act ? xn : x;
+    x = act ? c_update(x, q, e.z, e.w) : x;
 }
 
 // Encoder step with escape coding (16-bit symbols, depth-first).  The value
@@ -674,8 +687,7 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
-    const uint32_t xn = __umul24(q, e.w) + (x + (e.z & 0xFFFFu));
-    x = act ? xn : x;
+    x = act ? c_update(x, q, e.z, e.w) : x;
 }
 
 // Encodes chunk `chunk` of syms_base (n symbols, C per chunk, NL = 32 or 64
