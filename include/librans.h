@@ -245,7 +245,8 @@ int rans_decode_lut_async(const rans_table *table, const void *d_in, uint64_t in
 /* One stream of a batch.  `table` is a host handle; every other pointer is
  * device memory.  Encode: in = symbols, in_len = their count in BYTES
  * (a multiple of sym_bytes), out = container buffer of out_cap bytes,
- * *d_out_len = container length.  Decode: in = container of in_len bytes,
+ * *d_out_len = container length (with RANS_ENOSPC: the length the container
+ * needs).  Decode: in = container of in_len bytes,
  * out = symbol buffer of out_cap BYTES, *d_out_len = symbols decoded.
  * *d_status = RANS_OK or the job's RANS_E* code.  A failing job never
  * affects another job's output. */

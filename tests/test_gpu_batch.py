@@ -54,7 +54,7 @@ class Pool:
         return self.buf[o:o + nbytes].cpu().numpy()
 
 
-def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64, order="df"):
+def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64, order="df", counts=None):
     import torch
     params = lr.rans_params.make(k, r, l, 1, N, C, order)
     tables, specs = [], []
@@ -63,7 +63,7 @@ def run_encode_batch(lr, data, k, r, l, C, cap_override=None, N=64, order="df"):
     lens = torch.zeros(len(data), dtype=torch.int64, device="cuda")
     st = torch.full((len(data),), 99, dtype=torch.int32, device="cuda")
     for i, (s, _) in enumerate(data):
-        t = lr.rans_tables_build(datagen.counts(s, 256), k)
+        t = lr.rans_tables_build(datagen.counts(s, 256) if counts is None else counts[i], k)
         tables.append(t)
         din = pool.take(s.size)
         pool.put(din, s)
@@ -119,6 +119,44 @@ def test_batch_encode_decode_match_oracle(lr, k, r, l, C, N):
     for i, (s, _) in enumerate(data):
         assert n2[i] == s.size
         assert (dec[i] == s).all(), i
+
+
+def _zipf_stream(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return datagen.sample(datagen.zipf_probs(256, 1.1), n, rng, np.uint8)
+
+
+@pytest.mark.parametrize("N", [64, 32])
+def test_batch_edge_jobs(lr, N):
+    """Jobs the batched encoder places specially: empty (a header-only
+    container written by the planning kernel), one symbol, exactly 64 and 65
+    chunks (the look-back's group level), a ragged last chunk; then the same
+    batch with one job 16 bytes short of its container and an empty job
+    with room for less than a header (RANS_ENOSPC for those two alone, the
+    needed length reported)."""
+    k, r, l, C = 12, 16, 16, 1024
+    sizes = [0, 1, 64 * C, 65 * C, 3 * C + 17, 0, 5 * C]
+    data = [(_zipf_stream(n, 4700 + i), None) for i, n in enumerate(sizes)]
+    counts = []
+    for s, _ in data:
+        c = datagen.counts(s, 256)
+        c[0] += 1  # a non-empty histogram for the empty jobs
+        counts.append(c)
+    refs = [oracle.encode(oracle.quantize(c, k), s, k, r, l, N, C) for c, (s, _) in zip(counts, data)]
+    assert refs[0].size == 32 and refs[5].size == 32
+    tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C, N=N, counts=counts)
+    assert (st == 0).all(), st
+    for i in range(len(sizes)):
+        assert lens[i] == refs[i].size and (outs[i] == refs[i]).all(), (i, first_diff(outs[i], refs[i]))
+    dec, st2, n2 = run_decode_batch(lr, tables, refs, sizes, k, r, l, N=N)
+    assert (st2 == 0).all(), st2
+    for i, (s, _) in enumerate(data):
+        assert n2[i] == s.size and (dec[i][:s.size] == s).all(), i
+    short = {3: refs[3].size - 16, 5: 16}
+    _, _, st3, lens3 = run_encode_batch(lr, data, k, r, l, C, cap_override=short, N=N, counts=counts)
+    assert st3[3] == lr.RANS_ENOSPC and st3[5] == lr.RANS_ENOSPC, st3
+    assert lens3[3] == refs[3].size and lens3[5] == 32
+    assert (np.delete(st3, [3, 5]) == 0).all(), st3
 
 
 @pytest.mark.parametrize("N,C,layout", [(64, 8192, 1), (64, 2048, 2), (32, 4096, 3), (32, 1024, 0)])
