@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
             break;
         BatchJob& jb = a.jobs[j];
         if (j != cur) {
-            c64::stage_enc(lds, jb.enc, jb.enc_bytes, a.l + R - a.k);
+            c64::stage_enc(lds, jb.enc, jb.enc_bytes, a.l + R - a.k, ~0u, W == 1 ? 256u : 0u);
             __syncthreads();
             cur = j;
         }

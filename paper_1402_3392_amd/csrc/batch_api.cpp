@@ -120,7 +120,8 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             max_chunks += nch;
             max_lookback += nch + (nch + 63) / 64;
             max_items += (nch + G - 1) / G;
-            tab_lds = tab_lds > b.enc_bytes ? tab_lds : b.enc_bytes;
+            const uint32_t el = enc_lds_bytes(b.enc_bytes, w);
+            tab_lds = tab_lds > el ? tab_lds : el;
         }
     }
     if (decode) {

@@ -561,13 +561,15 @@ static_assert(kEncWindow == kSlotAlign && kSlotPad >= kEncWindow && kEncRing % k
 // every entry the coder cannot use directly -- frequency 0, or at or above
 // the escape (the extra last entry included) -- becomes a copy of the
 // escape's entry with bit 31 of z set, so one LDS read gives both the entry
-// to code and whether raw digits follow.
+// to code and whether raw digits follow.  pad_to: entries staged at least
+// (those past the table get frequency 0: not encodable).
 __device__ __forceinline__ void stage_enc(uint8_t* lds, const uint4* src, uint32_t bytes, uint32_t sh,
-                                          uint32_t esc = ~0u)
+                                          uint32_t esc = ~0u, uint32_t pad_to = 0)
 {
     uint4* d = reinterpret_cast<uint4*>(lds);
-    for (uint32_t i = threadIdx.x; i < bytes / 16; i += blockDim.x) {
-        uint4 e = src[i];
+    const uint32_t n = bytes / 16, nn = n > pad_to ? n : pad_to;
+    for (uint32_t i = threadIdx.x; i < nn; i += blockDim.x) {
+        uint4 e = i < n ? src[i] : make_uint4(0, 0, 0, 0);  // padding: frequency 0
         const bool raw = esc != ~0u && (i >= esc || (e.y & 0xFFFFu) == 0);
         if (raw)
             e = src[esc];
@@ -695,7 +697,7 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
 // slot_bytes, a multiple of kEncWindow; kSlotPad more bytes follow), writes the NL final
 // states to states_out and the digit count to *ndig_out (or to the
 // caller's x_out / nd_out).  l_enc: LDS encoder entries staged by stage_enc
-// (alphabet + 1);
+// (alphabet + 1 entries; 256 with 8-bit symbols, which index it unclamped);
 // wave_lds: this wave's kEncWaveLds bytes.  Digits reach the slot from the
 // LDS ring a window at a time, one 16-byte store per lane: after every block
 // of symbols, the windows the stream has grown past, padded to kFlushStores
@@ -758,7 +760,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         if (ESC)
             enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], s, act, dring, lane);
         else
-            enc_step<R, BF>(x, wpos, bad, l_enc[min(s, alphabet)], act, dring, lane);
+            enc_step<R, BF>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], act, dring, lane);
     }
     flush();  // the tail is shorter than a block: at most 2 windows
 
@@ -790,7 +792,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
 #pragma unroll
                 for (int q = 0; q < HB; ++q) {
                     const uint32_t v0 = static_cast<uint32_t>(sb[(h * HB + q) * NL]);
-                    sy[q] = ESC ? v0 : min(v0, alphabet);
+                    sy[q] = ESC || W == 1 ? v0 : min(v0, alphabet);
                 }
                 lane_fence();  // the symbols are in registers before the ring writes
                 auto entry = [&](int q) { return l_enc[ESC ? min(sy[q], alphabet) : sy[q]]; };

@@ -13,7 +13,8 @@ template <int R, int W, int NL, bool BF, bool ESC>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    c64::stage_enc(lds, a.enc, a.enc_bytes, a.l + R - a.k, ESC ? a.alphabet - 1 : ~0u);
+    const uint32_t tab = enc_lds_bytes(a.enc_bytes, W);
+    c64::stage_enc(lds, a.enc, a.enc_bytes, a.l + R - a.k, ESC ? a.alphabet - 1 : ~0u, tab / 16);
     __syncthreads();
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
     uint32_t t = 0;
@@ -26,10 +27,10 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
     uint32_t x = 0, nd = 0;
     c64::encode_chunk<R, W, NL, BF, ESC>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
                                 reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
-                                lds + a.enc_bytes + wave * c64::kEncWaveLds, nullptr, nullptr, a.status,
+                                lds + tab + wave * c64::kEncWaveLds, nullptr, nullptr, a.status,
                                 &x, &nd);
-    // the digits end at slot + slot_bytes; the 256 bytes after it absorb the
-    // copy's reads past them
+    // the digits end at slot + slot_bytes; the slot padding after it absorbs
+    // the copy's reads past them
     c64::place_chunk<R, NL>(chunk, a.n_chunks, x, c64::uni(nd),
                             slot + a.slot_bytes - uint64_t(c64::uni(nd)) * (R / 8), p, a.status);
 }
@@ -39,7 +40,7 @@ hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 {
     const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
     const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
-    const uint32_t lds = a.enc_bytes + wpb * c64::kEncWaveLds;
+    const uint32_t lds = enc_lds_bytes(a.enc_bytes, W) + wpb * c64::kEncWaveLds;
     auto kern = k_encode64_place<R, W, NL, BF, ESC>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -206,6 +206,13 @@ constexpr uint32_t kEncWaveLdsBytes = 5248;
 // and reads just past a chunk's digits).
 constexpr uint64_t kSlotAlign = 1024;
 constexpr uint64_t kSlotPad = 1024;
+// LDS bytes of an encoder table staged for w-byte symbols: with 8-bit
+// symbols all 256 entries are staged (those at or above the alphabet mark
+// the symbol as not encodable), so a symbol indexes the table unclamped.
+__host__ __device__ inline uint32_t enc_lds_bytes(uint32_t enc_bytes, uint32_t w)
+{
+    return w == 1 && enc_bytes < 256 * 16 ? 256 * 16 : enc_bytes;
+}
 
 // Batched pass (batch.hip).  `decode` selects the direction.
 hipError_t launch_batch(const BatchArgs& a, bool decode, int R, int W, int SW, Layout layout,
