@@ -295,7 +295,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     sa->chunk_off = reinterpret_cast<uint64_t*>(el.chunk_off);
     sa->total = reinterpret_cast<uint64_t*>(el.flags + 8);
     *pa = PlaceArgs{};
-    pa->ticket = reinterpret_cast<uint32_t*>(el.flags + 16);
+    pa->ticket = reinterpret_cast<uint32_t*>(el.lookback + 8 * (nch + (uint64_t(nch) + 63) / 64));
     pa->lookback = reinterpret_cast<uint64_t*>(el.lookback);
     pa->out = sa->out;
     std::memcpy(pa->hdr, sa->hdr, 32);
@@ -329,22 +329,19 @@ static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const
     if (pfx) {
         if (ea.n_chunks == 0)  // the header alone: the scan kernel writes it
             return launch_scan(sa, st);
-        e = launch_fill_u32(pa.ticket, 0, 1, st);
-        if (e == hipSuccess)
-            e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0,
-                                2 * (ea.n_chunks + (ea.n_chunks + 63) / 64), st);
+        // the look-back words and the ticket after them start at zero
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0,
+                            2 * (ea.n_chunks + (ea.n_chunks + 63) / 64 + 1), st);
         if (e != hipSuccess)
             return e;
         TimingScope ts(RANS_KERNEL_ENCODE, st);
         return launch_pfx_encode64(ea, pa, W, st);
     }
     if (ea.n_chunks > 0 && fast64(ea.N, ea.C, W, ea.syms)) {
-        // one kernel: encode and place by look-back (ticket and look-back
-        // words start at zero)
-        e = launch_fill_u32(pa.ticket, 0, 1, st);
-        if (e == hipSuccess)
-            e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0,
-                                2 * (ea.n_chunks + (ea.n_chunks + 63) / 64), st);
+        // one kernel: encode and place by look-back (the look-back words and
+        // the ticket after them start at zero: one fill)
+        e = launch_fill_u32(reinterpret_cast<uint32_t*>(pa.lookback), 0,
+                            2 * (ea.n_chunks + (ea.n_chunks + 63) / 64 + 1), st);
         if (e != hipSuccess)
             return e;
         TimingScope ts(RANS_KERNEL_ENCODE, st);

@@ -97,7 +97,7 @@ EncodeLayout encode_layout(uint64_t n_chunks, uint32_t N, uint64_t slot_bytes)
     l.states = up256(l.chunk_off + 8 * n_chunks);
     l.slots = up256(l.states + 4ull * N * n_chunks);
     l.lookback = up256(l.slots + (slot_bytes + kSlotPad) * n_chunks);
-    l.total = up256(l.lookback + 8 * (n_chunks + (n_chunks + 63) / 64));
+    l.total = up256(l.lookback + 8 * (n_chunks + (n_chunks + 63) / 64 + 1));
     return l;
 }
 

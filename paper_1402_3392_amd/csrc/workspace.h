@@ -45,12 +45,13 @@ struct Header {
 
 // Byte offsets inside the workspace for one encode call.
 struct EncodeLayout {
-    uint64_t flags;      // 32 B: i32 status, pad, u64 container length, u32 ticket
+    uint64_t flags;      // 32 B: i32 status, pad, u64 container length
     uint64_t ndig;       // n_chunks u32
     uint64_t chunk_off;  // n_chunks u64
     uint64_t states;     // n_chunks * N u32
     uint64_t slots;      // n_chunks * slot_stride
-    uint64_t lookback;   // n_chunks + ceil(n_chunks / 64) u64 (in-kernel placement)
+    uint64_t lookback;   // n_chunks + ceil(n_chunks / 64) u64 (in-kernel placement), then the
+                         // u64 whose low half is the start ticket (one fill clears all)
     uint64_t total;
 };
 
