@@ -244,6 +244,34 @@ def test_other_chunks_still_decode_after_corruption(lr):
     assert (out[2 * 8192:] == syms[2 * 8192:]).all()
 
 
+@pytest.mark.parametrize("N", [64, 32, 4])
+def test_symbol_beyond_small_alphabet(lr, N):
+    """8-bit symbols coded with a 16-symbol table: a value at or above the
+    alphabet has no entry (the one-wave kernels stage all 256 entries, those
+    past the table marked not encodable) and fails with RANS_ENOSYM, planted
+    inside a chunk's whole symbol blocks and in the ragged tail; the clean
+    input matches the oracle."""
+    import torch
+    from rans_util import dev
+    syms = make_syms(16, "zipf", 50_001, 31)
+    counts = datagen.counts(syms, 16)
+    f = oracle.quantize(counts, 11)
+    table = lr.rans_tables_build(counts, 11)
+    p = lr.rans_params.make(11, 16, 16, 1, N, 4096)
+    cap = lr.rans_encode_bound(syms.size, p)
+    d_out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    n = lr.rans_encode(table, p, dev(syms), syms.size, d_out, cap)
+    ref = oracle.encode(f, syms, 11, 16, 16, N, 4096)
+    got = d_out[:n].cpu().numpy()
+    assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
+    for pos, v in ((5000, 16), (5001, 17), (syms.size - 3, 255)):
+        bad = syms.copy()
+        bad[pos] = v
+        with pytest.raises(lr.RansError) as e:
+            lr.rans_encode(table, p, dev(bad), bad.size, d_out, cap)
+        assert e.value.code == lr.RANS_ENOSYM, (pos, v)
+
+
 def test_encode_errors(lr):
     import torch
     from rans_util import dev
