@@ -378,7 +378,7 @@ static int encode_bf(const model_t *m, const geom_t *g, const uint32_t *syms, ui
             if (lane_nd[j] > maxd)
                 maxd = lane_nd[j];
         }
-        /* Decoder read order for this round: q = 0, 1, ...; coders ascending;
+        /* Decoder read order for this step: q = 0, 1, ...; coders ascending;
          * coder j's q-th read is its (nd-1-q)-th emitted digit.  Prepend the
          * block in reverse read order. */
         for (q = maxd; q-- > 0;) {
