@@ -128,3 +128,15 @@ def test_division_constants(lr):
 def test_strerror(lr):
     for code in range(0, -8, -1):
         assert lr.rans_strerror(code)
+
+
+def test_quantizer_hand_computed_cases(lr):
+    """The library's own quantiser on the hand-computed tie, forced-symbol and
+    excess cases (independent of the oracle)."""
+    from conftest import load_golden
+    g = load_golden("quantizer_ties.txt")
+    for key in g:
+        if key.startswith("counts_"):
+            nm = key[len("counts_"):]
+            got = lr.rans_quantize(np.array(g[key], dtype=np.uint64), g["k_" + nm][0])
+            assert [int(v) for v in got] == g["expect_" + nm], nm

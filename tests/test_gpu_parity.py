@@ -297,3 +297,24 @@ def test_encode_errors(lr):
     with pytest.raises(lr.RansError) as e:
         lr.rans_tables_build(np.ones(4096, dtype=np.uint64), 11)
     assert e.value.code == lr.RANS_EPREC
+
+
+@pytest.mark.parametrize("name", ["digit_order_two_coders.txt", "digit_order_packed_load.txt"])
+def test_digit_orders_equal_hand_derived_streams(lr, name):
+    """The GPU coder on Section 5's hand-derived digit-order messages: both
+    orders' states and digits equal the fixtures (not the oracle's output),
+    and both containers decode back to the message."""
+    from conftest import load_golden
+    g = load_golden(name)
+    k, r, l, N = g["k"][0], g["radix_bits"][0], g["L_bits"][0], g["N"][0]
+    msg = np.array(g["message"], dtype=np.uint8)
+    table = lr.rans_tables_build(np.array(g["freq"], dtype=np.uint64), k)
+    assert [int(v) for v in lr.rans_table_freqs(table)] == g["freq"]
+    off = 32 + 16  # one chunk: header, one directory entry, 16-byte aligned stream
+    for order, key in (("df", "depth_first"), ("bf", "breadth_first")):
+        print(f"[golden-order] {name} {order}", flush=True)
+        got = gpu_encode(lr, table, (k, r, l, 1, N, 0, order), msg)
+        states = got[off:off + 4 * N].view("<u4")
+        assert [int(v) for v in states] == g["states"], order
+        assert [int(v) for v in got[off + 4 * N:]] == g[key], order
+        assert (gpu_decode(lr, table, got, msg.size, 1) == msg).all(), order

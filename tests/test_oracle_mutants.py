@@ -31,6 +31,24 @@ MUTANTS = [
      "buf[--*pos] = (uint32_t)(*x / g->b % g->b);", 1),
     ("raw digit weight", "v = v * g->b + dig[rd++];", "v = v + g->b * dig[rd++];", 1),
     ("escape ignores zero frequency", "if (v >= E || m->f[v] == 0) {", "if (v >= E) {", 1),
+    ("quantiser deficit ties to the higher index", "return i < j ? -1 : (i > j ? 1 : 0);",
+     "return i > j ? -1 : (i < j ? 1 : 0);", 1),
+    ("quantiser excess ties to the higher index", "if (f[s] > 1 && (best == n || f[s] > f[best]))",
+     "if (f[s] > 1 && (best == n || f[s] >= f[best]))", 1),
+    ("quantiser deficit to forced symbols too", "if (counts[s] > 0 && !forced[s])",
+     "if (counts[s] > 0)", 1),
+    # breadth-first rounds after the first taken in descending lane order,
+    # consistently in the encoder and the decoder (round trips still pass)
+    ("breadth-first later rounds lanes descending", [
+        ("            for (j = active; j-- > 0;) {\n                if (q < lane_nd[j]) {",
+         "            for (uint32_t jj = 0; jj < active; jj++) {\n                j = q ? jj : active - 1 - jj;\n"
+         "                if (q < lane_nd[j]) {", 1),
+        ("        do {\n            any = 0;\n            for (j = 0; j < active; j++) {\n"
+         "                if (x[j] < g->L) {",
+         "        int round_no = -1;\n        do {\n            any = 0;\n            round_no++;\n"
+         "            for (uint32_t jj = 0; jj < active; jj++) {\n"
+         "                j = round_no ? active - 1 - jj : jj;\n                if (x[j] < g->L) {", 1),
+    ], None, None),
 ]
 
 
@@ -46,14 +64,21 @@ def _checks(golden):
         lambda: pins.test_interleaved_stream_equals_instrumented_mux(3),
         lambda: pins.test_escape_with_one_symbol_table_is_raw_storage(16, 16),
         lambda: pins.test_escape_roundtrip_and_states_equal_token_stream(8, 23, 4, 1000),
+        lambda: pins.test_digit_orders_equal_hand_derived_streams("digit_order_two_coders.txt"),
+        lambda: pins.test_digit_orders_equal_hand_derived_streams("digit_order_packed_load.txt"),
+        lambda: pins.test_breadth_first_rounds_read_lanes_ascending(),
+        lambda: pins.test_quantizer_hand_computed_ties_and_excess(),
     ]
 
 
 @pytest.mark.parametrize("name,old,new,count", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_mutant_fails_a_pin(tmp_path, name, old, new, count):
     src = open(SRC).read()
-    assert src.count(old) == count, name
-    mutated = src.replace(old, new)
+    edits = old if isinstance(old, list) else [(old, new, count)]
+    mutated = src
+    for o, n_, c in edits:
+        assert mutated.count(o) == c, (name, o)
+        mutated = mutated.replace(o, n_)
     cfile = tmp_path / "mutant.c"
     cfile.write_text(mutated)
     so = tmp_path / "mutant.so"

@@ -258,6 +258,56 @@ def test_depth_first_and_breadth_first_differ_when_b_lt_M():
     assert differ > 0
 
 
+def _digit_order_case(name):
+    from conftest import load_golden
+    g = load_golden(name)
+    return (g["freq"], g["k"][0], g["radix_bits"][0], g["L_bits"][0], g["N"][0], g["message"],
+            g["states"], g["depth_first"], g["breadth_first"], g)
+
+
+@pytest.mark.parametrize("name", ["digit_order_two_coders.txt", "digit_order_packed_load.txt"])
+def test_digit_orders_equal_hand_derived_streams(name):
+    """Section 5's two orders on hand-derived messages: the two-coder case the
+    paper describes in words (coder 0 reads two bytes, coder 1 one) and the
+    paper's packed-load mask {1, 0, 1, 1} followed by a second round with
+    two coders, ascending in both rounds; the last step is ragged."""
+    f, k, r, l, N, msg, states, df, bf, _ = _digit_order_case(name)
+    for order, want in (("df", df), ("bf", bf)):
+        st, dig, _ = oracle.encode_digits(f, k, r, l, N, msg, order=order)
+        assert [int(v) for v in st] == states, order
+        assert [int(v) for v in dig] == want, order
+        assert [int(v) for v in oracle.decode_digits(f, k, r, l, N, states, want, len(msg),
+                                                     order=order)] == msg, order
+    # read in the other order the streams fail the end check (same digits,
+    # other coders)
+    for order, other in (("df", bf), ("bf", df)):
+        with pytest.raises(oracle.OracleError):
+            oracle.decode_digits(f, k, r, l, N, states, other, len(msg), order=order)
+
+
+def test_breadth_first_rounds_read_lanes_ascending():
+    """After step 0 of the packed-load message, the coders hold the states
+    the hand derivation gives: round 1 feeds coders 0, 2, 3 the bytes at
+    ptr[0], ptr[1], ptr[2]; round 2 feeds coders 0, 3 the next two."""
+    f, k, r, l, N, msg, states, _, bf, g = _digit_order_case("digit_order_packed_load.txt")
+    _, tr = oracle.decode_digits(f, k, r, l, N, states, bf, len(msg), order="bf", trace=True)
+    assert [int(v) for v in tr[:N]] == g["after_step0"]
+
+
+def test_quantizer_hand_computed_ties_and_excess():
+    """The quantiser rule on hand-computed cases: deficits by remainder with
+    ties to the lower index, forced symbols left out of the deficit, absent
+    symbols at 0, an excess taken from the largest f with ties to the lower
+    index."""
+    from conftest import load_golden
+    g = load_golden("quantizer_ties.txt")
+    names = [key[len("counts_"):] for key in g if key.startswith("counts_")]
+    assert len(names) >= 7
+    for nm in names:
+        c = np.array(g["counts_" + nm], dtype=np.uint64)
+        assert [int(v) for v in oracle.quantize(c, g["k_" + nm][0])] == g["expect_" + nm], nm
+
+
 # ------------------------------------------------------------------ sizes --
 
 def test_size_close_to_cross_entropy():
