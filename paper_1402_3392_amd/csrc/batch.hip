@@ -135,10 +135,22 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
     uint32_t bi = tid ? part_i[tid - 1] : 0, bc = tid ? part_c[tid - 1] : 0, bl = tid ? part_l[tid - 1] : 0;
     for (uint32_t j = lo; j < hi; ++j) {
         BatchJob& jb = a.jobs[j];
+        // a job whose work items would run past the map the host sized (or
+        // whose chunks would run past its slots and placement words) fails as
+        // a whole instead of being coded in part: its items keep their place
+        // in the scan, but with no chunks every wave that takes one skips it
+        const uint32_t nch_j = jb.nch, items = (nch_j + a.G - 1) / a.G;
+        const bool over = uint64_t(bi) + items > a.max_items ||
+                          (!decode && (uint64_t(bc) + nch_j > a.max_chunks ||
+                                       uint64_t(bl) + nch_j + (nch_j + 63) / 64 > a.max_lookback));
+        if (over) {
+            *jb.d_status = RANS_EINVAL;
+            *jb.d_out_len = 0;
+            jb.nch = 0;
+        }
         jb.item_base = bi;
         jb.chunk_base = bc;
         jb.lb_base = bl;
-        const uint32_t items = (jb.nch + a.G - 1) / a.G;
         if (items <= kSmallEntries) {
             // the host sized the map from the jobs' lengths; never exceed it
             for (uint32_t i = 0; i < items; ++i)
@@ -156,7 +168,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
                         a.item_job[bi + i] = j;
             }
         }
-        if (!decode && jb.nch == 0) {  // no chunk will place it: the header-only container
+        if (!decode && !over && nch_j == 0) {  // no chunk will place it: the header-only container
             *jb.d_out_len = kHeaderBytes;
             if (jb.out_cap >= kHeaderBytes) {
                 uint32_t h[8];
@@ -168,8 +180,8 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
             }
         }
         bi += items;
-        bc += jb.nch;
-        bl += jb.nch + (jb.nch + 63) / 64;
+        bc += nch_j;
+        bl += nch_j + (nch_j + 63) / 64;
     }
     if (tid == T - 1) {
         a.totals[0] = min(part_i[T - 1], a.max_items);

@@ -107,8 +107,11 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         b.enc = t->enc;
         b.enc_bytes = static_cast<uint32_t>(t->enc_bytes);
         if (decode) {
-            // chunks cost at least a directory entry and 64 states
-            const uint64_t nch = jb.in_len >= kHeaderBytes ? (jb.in_len - kHeaderBytes) / (16 + 256) : 0;
+            // a chunk costs at least a directory entry and N states: the same
+            // bound the device's header check enforces, so no accepted job can
+            // have more chunks than this
+            const uint64_t per_chunk = uint64_t(kDirEntryBytes) + 4ull * p.interleave;
+            const uint64_t nch = jb.in_len >= kHeaderBytes ? (jb.in_len - kHeaderBytes) / per_chunk : 0;
             max_items += (nch + G - 1) / G;
         } else {
             if (jb.in_len % w)
