@@ -330,17 +330,27 @@ int rans_autotune_batch(const rans_job *jobs, uint32_t njobs, const rans_params 
                         const char *cache_path, rans_tune_result *out);
 
 /* ---------------------------------------------------------------- serving --
- * Continuous-batching request server.  Requests (encode or decode of one
+ * Continuous-batching request server (not in the paper: the serving shape
+ * around Section 3's independent coders).  Requests (encode or decode of one
  * device-resident buffer, each with its own table) are admitted first come
- * first served while the sum of their costs (input + output capacity +
- * encode scratch of about 2 bytes per symbol) fits hbm_budget; admitted
+ * first served while the sum of their costs fits hbm_budget; admitted
  * requests are launched as batched persistent kernels on whichever of the
  * server's `streams` is idle, up to max_batch per launch, so requests that
- * arrive while others run are launched alongside them.  Outputs live in a
- * device arena of hbm_budget bytes allocated once by rans_server_create; the
- * serving loop itself allocates no device memory.  All requests use
- * config->params (decode: the containers must carry those parameters;
- * interleave 32 or 64).  The calls are thread-safe. */
+ * arrive while others run are launched alongside them.
+ * Memory: rans_server_create makes ONE device allocation of exactly
+ * hbm_budget bytes.  Its first part holds every stream's control region
+ * (job descriptors, work-item map, status words; sized at creation for
+ * max_batch requests whose inputs fit the budget, and reported as `fixed`);
+ * the rest is an arena holding each admitted request's output capacity and,
+ * to encode, its digit slots and placement words (about ceil(k/r)*r/8
+ * bytes per symbol plus 1 KiB per chunk).  A request's cost is its input
+ * length (caller memory, counted all the same) plus those arena bytes; the
+ * sum of admitted costs plus `fixed` never exceeds hbm_budget.  Polling,
+ * admission and launches allocate no device memory and wait for no stream.
+ * The launch shape (rans_batch_config) in force at creation is kept for
+ * the server's life.  All requests use config->params (decode: the
+ * containers must carry those parameters; interleave 32 or 64).  The calls
+ * are thread-safe. */
 #define RANS_OP_ENCODE 0
 #define RANS_OP_DECODE 1
 
@@ -369,9 +379,18 @@ typedef struct rans_completion {
     double queue_us;
 } rans_completion;
 
+/* budget: hbm_budget; fixed: the control regions' bytes; used / peak: fixed
+ * plus the costs of the admitted requests (now / at most so far); waiting,
+ * ready: requests queued for admission / admitted but not launched;
+ * busy_streams: streams with a launch in flight now, peak_busy_streams: at
+ * most at once so far; launches: batched launches so far, of which
+ * multi_request_launches held more than one request; max_launch_requests:
+ * the most requests one launch held. */
 typedef struct rans_server_stats_t {
     uint64_t budget, used, peak;
-    uint32_t waiting, ready, busy_streams, reserved;
+    uint32_t waiting, ready, busy_streams, peak_busy_streams;
+    uint64_t launches, multi_request_launches, fixed;
+    uint32_t max_launch_requests, reserved;
 } rans_server_stats_t;
 
 /* A request of an arrival schedule for rans_server_replay. */
@@ -419,6 +438,14 @@ int rans_server_replay(rans_server *server, const rans_server_request *reqs, uin
 int rans_timing_enable(int on);
 int rans_timing_reset(void);
 int rans_timing_read(int kind, uint64_t *launches, double *total_ms);
+
+/* Frees the device workspace, pinned staging and cached graphs the library
+ * keeps for `stream` on the current device (they are created on the first
+ * call that needs them and grow on demand).  Waits for the stream first.
+ * Call it before destroying a stream the library was used on; it must not
+ * overlap another call on the same stream.  A later call on the stream
+ * creates a new workspace. */
+int rans_workspace_release(void *stream);
 
 /* Static description of an error code. */
 const char *rans_strerror(int code);

@@ -79,7 +79,9 @@ class rans_completion(ct.Structure):
 class rans_server_stats_t(ct.Structure):
     _fields_ = [("budget", ct.c_uint64), ("used", ct.c_uint64), ("peak", ct.c_uint64),
                 ("waiting", ct.c_uint32), ("ready", ct.c_uint32), ("busy_streams", ct.c_uint32),
-                ("reserved", ct.c_uint32)]
+                ("peak_busy_streams", ct.c_uint32), ("launches", ct.c_uint64),
+                ("multi_request_launches", ct.c_uint64), ("fixed", ct.c_uint64),
+                ("max_launch_requests", ct.c_uint32), ("reserved", ct.c_uint32)]
 
 
 class rans_server_request(ct.Structure):
@@ -139,6 +141,7 @@ _sig = {
                                       ct.c_int, ct.POINTER(rans_completion),
                                       ct.POINTER(ct.c_double)]),
     "rans_batch_get_config": (ct.c_int, [ct.POINTER(rans_batch_config)]),
+    "rans_workspace_release": (ct.c_int, [ct.c_void_p]),
     "rans_timing_enable": (ct.c_int, [ct.c_int]),
     "rans_timing_reset": (ct.c_int, []),
     "rans_timing_read": (ct.c_int, [ct.c_int, _u64p, ct.POINTER(ct.c_double)]),
@@ -441,6 +444,10 @@ def rans_server_replay(server, requests, keep_outputs: bool = False):
 
 RANS_KERNEL_DECODE, RANS_KERNEL_ENCODE, RANS_KERNEL_SCAN, RANS_KERNEL_COMPACT = 0, 1, 2, 3
 RANS_KERNEL_BATCH_DECODE, RANS_KERNEL_BATCH_ENCODE, RANS_KERNEL_BATCH_PLAN = 4, 5, 6
+
+
+def rans_workspace_release(stream=None):
+    _check(_lib.rans_workspace_release(_stream(stream)), "rans_workspace_release")
 
 
 def rans_timing_enable(on: bool = True):

@@ -95,10 +95,10 @@ __device__ __forceinline__ void job_header(const BatchArgs& a, const BatchJob& j
 
 __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, bool decode)
 {
-    __shared__ uint32_t part_i[kPrepThreads], part_c[kPrepThreads], part_l[kPrepThreads];
-    // jobs whose map entries the whole block writes: job, item base, items,
-    // chunk base, chunks (kept here so the block's loop over them reads no
-    // global memory)
+    __shared__ uint32_t part_i[kPrepThreads];
+    // jobs whose map entries (and, to encode, placement words) the whole
+    // block writes: job, item base, items (kept here so the block's loop over
+    // them reads no global memory)
     __shared__ uint32_t big[kBigJobs][3];
     __shared__ uint32_t nbig;
     const uint32_t T = blockDim.x, tid = threadIdx.x;
@@ -111,51 +111,42 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
     // contiguous job ranges per thread, so the scan below is ordered
     const uint32_t per = (a.njobs + T - 1) / T;
     const uint32_t lo = min(a.njobs, tid * per), hi = min(a.njobs, lo + per);
-    uint32_t si = 0, sc = 0, sl = 0;
+    uint32_t si = 0;
     for (uint32_t j = lo; j < hi; ++j) {
         plan_job(a, j, decode);
-        const uint32_t nch = a.jobs[j].nch;
-        si += (nch + a.G - 1) / a.G;
-        sc += nch;
-        sl += nch + (nch + 63) / 64;  // chunk words and group words
+        si += (a.jobs[j].nch + a.G - 1) / a.G;
     }
     part_i[tid] = si;
-    part_c[tid] = sc;
-    part_l[tid] = sl;
     __syncthreads();
     for (uint32_t o = 1; o < T; o <<= 1) {
-        const uint32_t vi = tid >= o ? part_i[tid - o] : 0, vc = tid >= o ? part_c[tid - o] : 0,
-                       vl = tid >= o ? part_l[tid - o] : 0;
+        const uint32_t vi = tid >= o ? part_i[tid - o] : 0;
         __syncthreads();
         part_i[tid] += vi;
-        part_c[tid] += vc;
-        part_l[tid] += vl;
         __syncthreads();
     }
-    uint32_t bi = tid ? part_i[tid - 1] : 0, bc = tid ? part_c[tid - 1] : 0, bl = tid ? part_l[tid - 1] : 0;
+    uint32_t bi = tid ? part_i[tid - 1] : 0;
     for (uint32_t j = lo; j < hi; ++j) {
         BatchJob& jb = a.jobs[j];
-        // a job whose work items would run past the map the host sized (or
-        // whose chunks would run past its slots and placement words) fails as
-        // a whole instead of being coded in part: its items keep their place
-        // in the scan, but with no chunks every wave that takes one skips it
+        // a job whose work items would run past the map the host sized fails
+        // as a whole instead of being coded in part: its items keep their
+        // place in the scan, but with no chunks every wave that takes one
+        // skips it
         const uint32_t nch_j = jb.nch, items = (nch_j + a.G - 1) / a.G;
-        const bool over = uint64_t(bi) + items > a.max_items ||
-                          (!decode && (uint64_t(bc) + nch_j > a.max_chunks ||
-                                       uint64_t(bl) + nch_j + (nch_j + 63) / 64 > a.max_lookback));
+        const bool over = uint64_t(bi) + items > a.max_items;
         if (over) {
             *jb.d_status = RANS_EINVAL;
             *jb.d_out_len = 0;
             jb.nch = 0;
         }
         jb.item_base = bi;
-        jb.chunk_base = bc;
-        jb.lb_base = bl;
-        if (items <= kSmallEntries) {
+        const uint32_t words = decode || over ? 0u : nch_j + (nch_j + 63) / 64;
+        if (items <= kSmallEntries && words <= 64) {
             // the host sized the map from the jobs' lengths; never exceed it
             for (uint32_t i = 0; i < items; ++i)
                 if (bi + i < a.max_items)
                     a.item_job[bi + i] = j;
+            for (uint32_t i = 0; i < words; ++i)  // the placement words start at zero
+                jb.lookback[i] = 0;
         } else {
             const uint32_t slot = atomicAdd(&nbig, 1u);
             if (slot < kBigJobs) {
@@ -166,6 +157,8 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
                 for (uint32_t i = 0; i < items; ++i)
                     if (bi + i < a.max_items)
                         a.item_job[bi + i] = j;
+                for (uint32_t i = 0; i < words; ++i)
+                    jb.lookback[i] = 0;
             }
         }
         if (!decode && !over && nch_j == 0) {  // no chunk will place it: the header-only container
@@ -180,13 +173,9 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
             }
         }
         bi += items;
-        bc += nch_j;
-        bl += nch_j + (nch_j + 63) / 64;
     }
-    if (tid == T - 1) {
+    if (tid == T - 1)
         a.totals[0] = min(part_i[T - 1], a.max_items);
-        a.totals[1] = min(part_c[T - 1], a.max_chunks);
-    }
     __syncthreads();
     const uint32_t nb = min(nbig, kBigJobs);
     for (uint32_t b = 0; b < nb; ++b) {
@@ -194,11 +183,12 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
         for (uint32_t i = tid; i < items; i += T)
             if (ib + i < a.max_items)
                 a.item_job[ib + i] = j;
-    }
-    if (!decode) {  // the placement words start at zero
-        const uint64_t nl = min(uint64_t(part_l[T - 1]), a.max_lookback);
-        for (uint64_t i = tid; i < nl; i += T)
-            a.lookback[i] = 0;
+        const BatchJob& jb = a.jobs[j];
+        if (!decode && jb.nch) {
+            const uint32_t words = jb.nch + (jb.nch + 63) / 64;
+            for (uint32_t i = tid; i < words; i += T)
+                jb.lookback[i] = 0;
+        }
     }
 }
 
@@ -275,21 +265,17 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
         }
         const uint32_t nch = c64::uni(jb.nch);
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
-        // the job's slots and placement words lie inside what the host sized
-        const bool room = uint64_t(jb.chunk_base) + nch <= a.max_chunks &&
-                          uint64_t(jb.lb_base) + nch + (nch + 63) / 64 <= a.max_lookback;
-        if (!room && c == 0 && (threadIdx.x & 63) == 0)
-            atomicMin(jb.d_status, RANS_EINVAL);
-        if (room && c < nch) {
-            const uint64_t g = c64::uni(jb.chunk_base) + uint64_t(c);
-            uint8_t* slot = a.slots + g * a.slot_stride;
+        if (c < nch) {
+            // the job's own slots (the host sized them for its nch chunks)
+            uint8_t* slot = reinterpret_cast<uint8_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.slots))) +
+                            uint64_t(c) * a.slot_stride;
             uint32_t x = 0, nd = 0;
             c64::encode_chunk<R, W, NL, BF>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
                                             reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes, sbuf,
                                             nullptr, nullptr, jb.d_status, &x, &nd);
             PlaceArgs pa;
             pa.ticket = nullptr;
-            pa.lookback = a.lookback + c64::uni(jb.lb_base);
+            pa.lookback = reinterpret_cast<uint64_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.lookback)));
             pa.out = jb.out;
             pa.out_cap = jb.out_cap;
             pa.total = &jb.total;

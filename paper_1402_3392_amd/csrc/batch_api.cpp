@@ -28,27 +28,48 @@ int num_cus()
     return v;
 }
 
-struct Region {
-    uint64_t ctrl, jobs, item_job, slots, lookback, total;
-};
-
-Region layout_for(uint32_t njobs, uint64_t max_items, uint64_t max_chunks, uint64_t slot_stride,
-                  uint64_t max_lookback)
-{
-    Region r{};
-    r.ctrl = 0;  // counter + totals
-    r.jobs = 256;
-    r.item_job = up256(r.jobs + sizeof(BatchJob) * uint64_t(njobs));
-    r.slots = up256(r.item_job + 4 * max_items);
-    r.lookback = up256(r.slots + slot_stride * max_chunks);
-    r.total = up256(r.lookback + 8 * max_lookback);
-    return r;
-}
-
 }  // namespace
 
-int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
-              bool decode, const rans_batch_config* cfg_override)
+uint64_t batch_item_bound(const rans_job& jb, const rans_params& p, bool decode, uint32_t G)
+{
+    uint64_t nch;
+    if (decode) {
+        // a chunk costs at least a directory entry and N states: the same
+        // bound the device's header check enforces, so no accepted job can
+        // have more chunks than this
+        const uint64_t per_chunk = uint64_t(kDirEntryBytes) + 4ull * p.interleave;
+        nch = jb.in_len >= kHeaderBytes ? (jb.in_len - kHeaderBytes) / per_chunk : 0;
+    } else {
+        const uint64_t n = jb.in_len / p.sym_bytes;
+        nch = p.chunk_syms ? (n + p.chunk_syms - 1) / p.chunk_syms : 0;
+    }
+    return (nch + G - 1) / G;
+}
+
+uint64_t batch_encode_scratch(uint64_t in_len, const rans_params& p)
+{
+    const uint64_t n = in_len / p.sym_bytes;
+    const uint64_t nch = p.chunk_syms ? (n + p.chunk_syms - 1) / p.chunk_syms : 0;
+    const uint64_t stride = slot_bytes_for(p.chunk_syms, p.prob_bits, p.radix_bits) + kSlotPad;
+    return up256(nch * stride) + up256(8 * (nch + (nch + 63) / 64));
+}
+
+void bind_encode_scratch(BatchJob* jb, uint8_t* base, uint64_t in_len, const rans_params& p)
+{
+    const uint64_t n = in_len / p.sym_bytes;
+    const uint64_t nch = p.chunk_syms ? (n + p.chunk_syms - 1) / p.chunk_syms : 0;
+    const uint64_t stride = slot_bytes_for(p.chunk_syms, p.prob_bits, p.radix_bits) + kSlotPad;
+    jb->slots = base;
+    jb->lookback = reinterpret_cast<uint64_t*>(base + up256(nch * stride));
+}
+
+uint64_t batch_ctrl_bytes(uint32_t njobs, uint64_t max_items)
+{
+    return up256(256 + sizeof(BatchJob) * uint64_t(njobs)) + up256(4 * (max_items ? max_items : 1));
+}
+
+int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, bool decode,
+               const rans_batch_config& cfg, BatchPlan* plan)
 {
     int rc = check_params(params);
     if (rc != RANS_OK)
@@ -65,22 +86,16 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         return RANS_EINVAL;
     if (!decode && (p.chunk_syms == 0 || (uint64_t(p.chunk_syms) * w) % 16 != 0))
         return RANS_EINVAL;
-    if (njobs == 0)
-        return RANS_OK;
-    rans_batch_config cfg;
-    if (cfg_override) {
-        cfg = *cfg_override;
-    } else {
-        std::lock_guard<std::mutex> lk(g_cfg_mu);
-        cfg = g_cfg;
-    }
+    if (cfg.waves_per_group < 1 || cfg.waves_per_group > 16 || cfg.groups_per_cu < 1)
+        return RANS_EINVAL;
     const uint32_t G = cfg.waves_per_group;
 
     // host checks of every descriptor and the launch shape they imply
-    uint64_t max_items = 0, max_chunks = 0, max_lookback = 0;
+    uint64_t max_items = 0;
     uint32_t tab_lds = 0, sw = 0;
     Layout layout = kPacked;
-    std::vector<BatchJob> hj(njobs);
+    std::vector<BatchJob>& hj = plan->hj;
+    hj.assign(njobs, BatchJob{});
     for (uint32_t j = 0; j < njobs; ++j) {
         const rans_job& jb = jobs[j];
         const DevTable* t = dev_table(jb.table);
@@ -96,7 +111,6 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         else if (t->sym_w != sw)
             return RANS_EINVAL;
         BatchJob& b = hj[j];
-        std::memset(&b, 0, sizeof(b));
         b.in = static_cast<const uint8_t*>(jb.in);
         b.in_len = jb.in_len;
         b.out = static_cast<uint8_t*>(jb.out);
@@ -106,37 +120,25 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         b.alphabet = t->alphabet;
         b.enc = t->enc;
         b.enc_bytes = static_cast<uint32_t>(t->enc_bytes);
-        if (decode) {
-            // a chunk costs at least a directory entry and N states: the same
-            // bound the device's header check enforces, so no accepted job can
-            // have more chunks than this
-            const uint64_t per_chunk = uint64_t(kDirEntryBytes) + 4ull * p.interleave;
-            const uint64_t nch = jb.in_len >= kHeaderBytes ? (jb.in_len - kHeaderBytes) / per_chunk : 0;
-            max_items += (nch + G - 1) / G;
-        } else {
+        if (!decode) {
             if (jb.in_len % w)
                 return RANS_EINVAL;
-            const uint64_t n = jb.in_len / w;
-            const uint64_t nch = (n + p.chunk_syms - 1) / p.chunk_syms;
-            if (nch > 0xFFFFFFFFull)
+            if ((jb.in_len / w + p.chunk_syms - 1) / p.chunk_syms > 0xFFFFFFFFull)
                 return RANS_EINVAL;
-            max_chunks += nch;
-            max_lookback += nch + (nch + 63) / 64;
-            max_items += (nch + G - 1) / G;
             const uint32_t el = enc_lds_bytes(b.enc_bytes, w);
             tab_lds = tab_lds > el ? tab_lds : el;
         }
+        max_items += batch_item_bound(jb, p, decode, G);
     }
     if (decode) {
         // table layout: the configured one, or the best one every table has
         // (fused > packed > two-level) that fits LDS next to G waves' rings
         bool all_fused = true;
-        uint64_t max_packed = 0, max_two = 0, max_fused = 0;
+        uint64_t max_packed = 0, max_fused = 0;
         for (uint32_t j = 0; j < njobs; ++j) {
             const DevTable* t = dev_table(jobs[j].table);
             all_fused = all_fused && t->fused;
             max_packed = std::max<uint64_t>(max_packed, t->sym_bytes + t->dec_bytes);
-            max_two = std::max<uint64_t>(max_two, t->sym_bytes + t->fc_bytes);
             max_fused = std::max<uint64_t>(max_fused, t->fused_bytes);
         }
         // 256 bytes stay free for the persistent kernel's static LDS
@@ -178,29 +180,15 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
             tab_lds = tab_lds > b.sym_bytes + b.ent_bytes ? tab_lds : b.sym_bytes + b.ent_bytes;
         }
     }
-    if (max_items > 0xFFFFFFF0ull || max_chunks > 0xFFFFFFF0ull || max_lookback > 0xFFFFFFF0ull)
+    if (max_items > 0xFFFFFFF0ull)
         return RANS_EINVAL;
     const uint32_t per_wave = decode ? decode64_lds_per_wave(layout) : kEncWaveLdsBytes;
     if (uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
         return RANS_EINVAL;
 
     const uint64_t slot_bytes = decode ? 0 : slot_bytes_for(p.chunk_syms, p.prob_bits, R);
-    const uint64_t slot_stride = decode ? 0 : slot_bytes + kSlotPad;
-    const Region rg = layout_for(njobs, max_items ? max_items : 1, max_chunks, slot_stride, max_lookback);
-
-    Workspace* ws = workspace_for(st);
-    if (!ws)
-        return RANS_ENOMEM;
-    std::lock_guard<std::mutex> lk(ws->mu);
-    if ((rc = ws->reserve(rg.total)) != RANS_OK)
-        return rc;
-    const uint64_t jb_bytes = sizeof(BatchJob) * uint64_t(njobs);
-    if ((rc = ws->reserve_pinned(jb_bytes)) != RANS_OK)
-        return rc;
-    uint8_t* base = static_cast<uint8_t*>(ws->dev);
-
-    BatchArgs a{};
-    a.jobs = reinterpret_cast<BatchJob*>(base + rg.jobs);
+    BatchArgs& a = plan->a;
+    a = BatchArgs{};
     a.njobs = njobs;
     a.k = p.prob_bits;
     a.r = R;
@@ -210,43 +198,49 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     a.C = p.chunk_syms;
     a.bf = p.digit_order;
     a.G = G;
-    a.counter = reinterpret_cast<uint32_t*>(base + rg.ctrl);
-    a.totals = a.counter + 4;
-    a.item_job = reinterpret_cast<uint32_t*>(base + rg.item_job);
     a.max_items = static_cast<uint32_t>(max_items ? max_items : 1);
-    a.max_chunks = static_cast<uint32_t>(max_chunks);
-    a.slots = base + rg.slots;
     a.slot_bytes = slot_bytes;
-    a.slot_stride = slot_stride;
-    a.lookback = reinterpret_cast<uint64_t*>(base + rg.lookback);
-    a.max_lookback = max_lookback;
+    a.slot_stride = decode ? 0 : slot_bytes + kSlotPad;
     a.tab_lds = (tab_lds + 15) & ~15u;
-    const uint32_t grid = static_cast<uint32_t>(num_cus()) * cfg.groups_per_cu;
-    a.grid = grid;
+    a.grid = static_cast<uint32_t>(num_cus()) * cfg.groups_per_cu;
+    plan->layout = layout;
+    plan->sw = sw;
+    plan->decode = decode;
+    plan->ctrl_bytes = batch_ctrl_bytes(njobs, max_items);
+    return RANS_OK;
+}
 
-    // job descriptors -> pinned staging -> workspace, ordered on `st`
-    std::memcpy(ws->pinned, hj.data(), jb_bytes);
-    if (hipMemcpyAsync(a.jobs, ws->pinned, jb_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
-        return RANS_EDEVICE;
-    if (!ws->staged && hipEventCreateWithFlags(&ws->staged, hipEventDisableTiming) != hipSuccess)
-        return RANS_EDEVICE;
-    if (hipEventRecord(ws->staged, st) != hipSuccess)
-        return RANS_EDEVICE;
-    ws->staged_pending = true;
+int launch_planned(BatchPlan& plan, uint8_t* ctrl, void* pinned, hipStream_t st, bool use_graph,
+                   Workspace* ws)
+{
+    BatchArgs& a = plan.a;
+    if (a.njobs == 0)
+        return RANS_OK;
+    const bool decode = plan.decode;
+    a.counter = reinterpret_cast<uint32_t*>(ctrl);  // counter + totals
+    a.totals = a.counter + 4;
+    a.jobs = reinterpret_cast<BatchJob*>(ctrl + 256);
+    a.item_job = reinterpret_cast<uint32_t*>(ctrl + up256(256 + sizeof(BatchJob) * uint64_t(a.njobs)));
 
+    // job descriptors -> pinned staging -> device, ordered on `st`
+    const uint64_t jb_bytes = sizeof(BatchJob) * uint64_t(a.njobs);
+    std::memcpy(pinned, plan.hj.data(), jb_bytes);
+    if (hipMemcpyAsync(a.jobs, pinned, jb_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return RANS_EDEVICE;
+
+    const int R = static_cast<int>(a.r), W = static_cast<int>(a.w), SW = static_cast<int>(plan.sw);
     const int kind = decode ? RANS_KERNEL_BATCH_DECODE : RANS_KERNEL_BATCH_ENCODE;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess)
         return RANS_EDEVICE;
-    if (!cfg.use_graph || cap != hipStreamCaptureStatusNone) {
+    if (!use_graph || !ws || cap != hipStreamCaptureStatusNone) {
         TimingScope ts(kind, st);
-        return launch_batch(a, decode, R, w, sw, layout, grid, st) == hipSuccess ? RANS_OK
-                                                                                 : RANS_EDEVICE;
+        return launch_batch(a, decode, R, W, SW, plan.layout, a.grid, st) == hipSuccess ? RANS_OK
+                                                                                       : RANS_EDEVICE;
     }
     // one graph per launch image: the kernel arguments and template choice
     std::string key(reinterpret_cast<const char*>(&a), sizeof(a));
-    const int shape[5] = {decode ? 1 : 0, static_cast<int>(sw), static_cast<int>(layout),
-                          static_cast<int>(grid), static_cast<int>(R)};
+    const int shape[5] = {decode ? 1 : 0, SW, static_cast<int>(plan.layout), static_cast<int>(a.grid), R};
     key.append(reinterpret_cast<const char*>(shape), sizeof(shape));
     auto it = ws->graphs.find(key);
     if (it == ws->graphs.end()) {
@@ -256,7 +250,7 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
         hipGraphExec_t exec = nullptr;
         if (hipStreamBeginCapture(ws->capture, hipStreamCaptureModeRelaxed) != hipSuccess)
             return RANS_EDEVICE;
-        const hipError_t le = launch_batch(a, decode, R, w, sw, layout, grid, ws->capture);
+        const hipError_t le = launch_batch(a, decode, R, W, SW, plan.layout, a.grid, ws->capture);
         const hipError_t ce = hipStreamEndCapture(ws->capture, &graph);
         if (le != hipSuccess || ce != hipSuccess || !graph) {
             if (graph)
@@ -271,6 +265,52 @@ int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, h
     }
     TimingScope ts(kind, st);
     return hipGraphLaunch(it->second, st) == hipSuccess ? RANS_OK : RANS_EDEVICE;
+}
+
+int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
+              bool decode, const rans_batch_config* cfg_override)
+{
+    rans_batch_config cfg;
+    if (cfg_override) {
+        cfg = *cfg_override;
+    } else {
+        std::lock_guard<std::mutex> lk(g_cfg_mu);
+        cfg = g_cfg;
+    }
+    BatchPlan plan;
+    int rc = plan_batch(jobs, njobs, params, decode, cfg, &plan);
+    if (rc != RANS_OK || njobs == 0)
+        return rc;
+    // workspace: control region, then (encode) every job's slots and
+    // placement words
+    uint64_t need = plan.ctrl_bytes;
+    if (!decode)
+        for (uint32_t j = 0; j < njobs; ++j)
+            need += batch_encode_scratch(jobs[j].in_len, *params);
+    Workspace* ws = workspace_for(st);
+    if (!ws)
+        return RANS_ENOMEM;
+    std::lock_guard<std::mutex> lk(ws->mu);
+    if ((rc = ws->reserve(need)) != RANS_OK)
+        return rc;
+    if ((rc = ws->reserve_pinned(sizeof(BatchJob) * uint64_t(njobs))) != RANS_OK)
+        return rc;
+    uint8_t* base = static_cast<uint8_t*>(ws->dev);
+    if (!decode) {
+        uint64_t off = plan.ctrl_bytes;
+        for (uint32_t j = 0; j < njobs; ++j) {
+            bind_encode_scratch(&plan.hj[j], base + off, jobs[j].in_len, *params);
+            off += batch_encode_scratch(jobs[j].in_len, *params);
+        }
+    }
+    rc = launch_planned(plan, base, ws->pinned, st, cfg.use_graph != 0, ws);
+    // the staging buffer is free again once the copy out of it has run
+    if (!ws->staged && hipEventCreateWithFlags(&ws->staged, hipEventDisableTiming) != hipSuccess)
+        return RANS_EDEVICE;
+    if (hipEventRecord(ws->staged, st) != hipSuccess)
+        return RANS_EDEVICE;
+    ws->staged_pending = true;
+    return rc;
 }
 
 rans_batch_config batch_config()

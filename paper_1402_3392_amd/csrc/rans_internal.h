@@ -157,8 +157,11 @@ struct BatchJob {
     uint64_t total;        // encode: container length
     uint32_t C, nch;       // symbols per chunk, chunks (0 when the job failed)
     uint32_t item_base;    // first work item
-    uint32_t chunk_base;   // first global chunk (encode slots)
-    uint32_t lb_base;      // encode: the job's placement words (nch chunk words, then its groups')
+    // encode scratch of this job, set by the host: one digit slot per chunk
+    // (BatchArgs::slot_stride apart) and the placement words (nch chunk
+    // words, then one per group of 64 chunks), zeroed by the planning kernel
+    uint8_t* slots;
+    uint64_t* lookback;
 };
 
 struct BatchArgs {
@@ -170,11 +173,8 @@ struct BatchArgs {
     uint32_t* counter;          // work-queue head, set by the planning kernel
     uint32_t* totals;           // [0] work items, [1] chunks
     uint32_t* item_job;         // work item -> job
-    uint32_t max_items, max_chunks;
-    uint8_t* slots;             // encode: one slot per global chunk
-    uint64_t slot_bytes, slot_stride;
-    uint64_t* lookback;         // encode: placement words of every job, zeroed by the planning kernel
-    uint64_t max_lookback;      // their count (bounds the zeroing)
+    uint32_t max_items;         // entries of item_job
+    uint64_t slot_bytes, slot_stride;  // encode digit slots (BatchJob::slots)
     uint32_t tab_lds;           // LDS bytes reserved for the largest table
     uint32_t grid;              // persistent blocks; decode: block b starts with work item b
 };

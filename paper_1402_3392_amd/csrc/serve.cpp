@@ -1,9 +1,13 @@
 // Serving runtime: continuous batching of encode/decode requests under an
 // HBM budget.
 //
-//  * The whole budget is one device arena allocated at creation; request
-//    outputs are carved from it by a first-fit allocator, so the loop itself
-//    never calls the HIP allocator.
+//  * The whole budget is one device allocation made at creation: every
+//    stream's control region (job descriptors, work-item map, status words)
+//    comes first, the rest is an arena from which each admitted request's
+//    output (and, to encode, its digit slots and placement words) is carved
+//    by a first-fit allocator.  The loop itself never calls the HIP
+//    allocator, never synchronises a stream, and the device memory the server
+//    holds is exactly its budget.
 //  * Admission is FIFO: the oldest waiting request is admitted as soon as its
 //    cost (input + output capacity + coding scratch) fits the remaining
 //    budget; nothing overtakes it.
@@ -87,7 +91,8 @@ struct Request {
     int op = 0;  // RANS_OP_ENCODE / RANS_OP_DECODE
     const rans_table* table = nullptr;
     const void* d_in = nullptr;
-    uint64_t in_len = 0, out_cap = 0, out_alloc = 0, cost = 0, out_off = 0;
+    // out_alloc: arena bytes of the request (output, then encode scratch)
+    uint64_t in_len = 0, out_cap = 0, out_alloc = 0, scratch = 0, cost = 0, out_off = 0;
     uint32_t slot = 0;  // index in its launch's status arrays
     Clock::time_point t_arrive, t_launch;
     bool admitted = false;
@@ -98,10 +103,12 @@ struct Lane {
     hipEvent_t ev = nullptr;
     bool busy = false;
     std::vector<Request*> reqs;
+    uint8_t* ctrl = nullptr;      // control region of the lane's batched launches
     int32_t* d_status = nullptr;  // max_batch entries each, device
     uint64_t* d_len = nullptr;
     int32_t* h_status = nullptr;  // pinned copies
     uint64_t* h_len = nullptr;
+    uint8_t* h_jobs = nullptr;    // pinned staging of job descriptors: encode half, decode half
 };
 
 }  // namespace
@@ -110,16 +117,20 @@ struct Lane {
 struct rans_server {
     std::mutex mu;
     rans::Arena arena;
-    uint8_t* base = nullptr;
-    uint64_t budget = 0, used = 0, peak = 0;
+    uint8_t* mem = nullptr;   // the one device allocation (budget bytes)
+    uint8_t* base = nullptr;  // the arena inside it
+    uint64_t budget = 0, fixed = 0, used = 0, peak = 0;
     rans_params params{};
+    rans_batch_config cfg{};  // launch shape of every batched launch
     uint32_t max_batch = 0;
+    uint64_t ctrl_cap = 0;    // control bytes per lane
+    uint64_t launches = 0, multi_launches = 0;
+    uint32_t max_launch_reqs = 0, peak_busy = 0;
     std::vector<rans::Lane> lanes;
     std::deque<rans::Request*> waiting;
     std::vector<rans::Request*> ready;
     std::map<uint64_t, rans::Request*> live;  // admitted or waiting, by id
     std::vector<rans::Request*> done_keep;    // completed, output still held
-    uint8_t* ctrl = nullptr;                  // per-stream status arrays
     uint64_t next_id = 1;
     std::vector<rans_completion> finished;
 };
@@ -127,13 +138,20 @@ struct rans_server {
 namespace rans {
 namespace {
 
-uint64_t request_cost(const rans_server* s, int op, uint64_t in_len, uint64_t out_cap)
+uint64_t up256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+// What a request holds while admitted: its input (caller memory, counted
+// against the budget all the same), its output and, to encode, the digit
+// slots and placement words of its chunks (both in the arena).
+uint64_t request_cost(uint64_t in_len, uint64_t out_alloc) { return up256(in_len) + up256(out_alloc); }
+
+// Work items of one launch: at most max_batch requests whose inputs together
+// fit the budget.
+uint64_t lane_item_bound(const rans_params& p, uint64_t budget, uint32_t max_batch, uint32_t G)
 {
-    // encode also holds its digit slots (up to 2 bytes per symbol plus the
-    // per-chunk placement words) in the stream's workspace while it runs
-    const uint64_t scratch = op == RANS_OP_ENCODE ? 2 * in_len + in_len / 64 + 4096 : 0;
-    (void)s;
-    return ((in_len + 255) & ~uint64_t(255)) + ((out_cap + 255) & ~uint64_t(255)) + scratch;
+    const uint64_t dec_chunks = budget / (uint64_t(kDirEntryBytes) + 4ull * p.interleave);
+    const uint64_t enc_chunks = p.chunk_syms ? budget / (uint64_t(p.chunk_syms) * p.sym_bytes) : 0;
+    return std::max(dec_chunks, enc_chunks) / G + 2ull * max_batch;
 }
 
 void launch_ready(rans_server* s, Lane& ln)
@@ -168,14 +186,34 @@ void launch_ready(rans_server* s, Lane& ln)
             decr.push_back(r);
         }
     }
-    rans_batch_config cfg = batch_config();
-    cfg.use_graph = 0;  // batch sizes vary from launch to launch
+    // batch sizes vary from launch to launch: direct launches, no graphs.
+    // Encode runs first, then decode, in stream order on the lane, so both
+    // use the lane's control region; each stages through its own half of
+    // the pinned buffer (both copies are queued before either runs).
     int rc = RANS_OK;
-    if (!enc.empty())
-        rc = run_batch(enc.data(), static_cast<uint32_t>(enc.size()), &s->params, ln.st, false, &cfg);
-    if (rc == RANS_OK && !dec.empty())
-        rc = run_batch(dec.data(), static_cast<uint32_t>(dec.size()), &s->params, ln.st, true, &cfg);
+    const uint64_t half = sizeof(BatchJob) * uint64_t(s->max_batch);
+    for (int pass = 0; pass < 2 && rc == RANS_OK; ++pass) {
+        const bool decode = pass == 1;
+        const std::vector<rans_job>& js = decode ? dec : enc;
+        if (js.empty())
+            continue;
+        BatchPlan plan;
+        rc = plan_batch(js.data(), static_cast<uint32_t>(js.size()), &s->params, decode, s->cfg, &plan);
+        if (rc == RANS_OK && plan.ctrl_bytes > s->ctrl_cap)
+            rc = RANS_EINVAL;  // cannot happen for admitted requests (bounded at creation)
+        if (rc != RANS_OK)
+            break;
+        if (!decode)
+            for (size_t i = 0; i < encr.size(); ++i)
+                bind_encode_scratch(&plan.hj[i], s->base + encr[i]->out_off + up256(encr[i]->out_alloc - encr[i]->scratch),
+                                    encr[i]->in_len, s->params);
+        rc = launch_planned(plan, ln.ctrl, ln.h_jobs + (decode ? half : 0), ln.st, false, nullptr);
+    }
     const uint32_t m = static_cast<uint32_t>(take.size());
+    ++s->launches;
+    if (m > 1)
+        ++s->multi_launches;
+    s->max_launch_reqs = std::max(s->max_launch_reqs, m);
     (void)hipMemcpyAsync(ln.h_status, ln.d_status, m * sizeof(int32_t), hipMemcpyDeviceToHost, ln.st);
     (void)hipMemcpyAsync(ln.h_len, ln.d_len, m * sizeof(uint64_t), hipMemcpyDeviceToHost, ln.st);
     (void)hipEventRecord(ln.ev, ln.st);
@@ -186,13 +224,17 @@ void launch_ready(rans_server* s, Lane& ln)
     }
     ln.busy = true;
     ln.reqs = take;
+    uint32_t busy = 0;
+    for (auto& l : s->lanes)
+        busy += l.busy;
+    s->peak_busy = std::max(s->peak_busy, busy);
 }
 
 void admit(rans_server* s)
 {
     while (!s->waiting.empty()) {
         Request* r = s->waiting.front();
-        if (s->used + r->cost > s->budget)
+        if (s->used + r->cost > s->budget)  // used starts at the fixed control bytes
             break;
         if (!s->arena.alloc(r->out_alloc, &r->out_off))
             break;  // fragmentation: wait for releases
@@ -239,7 +281,7 @@ using namespace rans;
 extern "C" int rans_server_create(const rans_server_config* cfg, rans_server** out)
 {
     if (!cfg || !out || cfg->streams < 1 || cfg->streams > 16 || cfg->max_batch < 1 ||
-        cfg->hbm_budget < (1u << 20))
+        cfg->max_batch > (1u << 16) || cfg->hbm_budget < (1u << 20))
         return RANS_EINVAL;
     *out = nullptr;
     int rc = check_params(&cfg->params);
@@ -247,32 +289,47 @@ extern "C" int rans_server_create(const rans_server_config* cfg, rans_server** o
         return rc;
     if (cfg->params.escape)  // requests run on the batched kernels
         return RANS_EINVAL;
+    if (cfg->params.interleave != 32 && cfg->params.interleave != 64)
+        return RANS_EINVAL;
     rans_server* s = new rans_server();
     s->budget = cfg->hbm_budget;
     s->params = cfg->params;
     s->max_batch = cfg->max_batch;
-    void* arena = nullptr;
-    if (hipMalloc(&arena, s->budget) != hipSuccess) {
+    s->cfg = batch_config();  // fixed for the server's life: it sizes the control regions
+    s->cfg.use_graph = 0;
+    // per lane: the control region of a launch of max_batch requests whose
+    // inputs fit the budget, then the status words
+    s->ctrl_cap = batch_ctrl_bytes(cfg->max_batch,
+                                   lane_item_bound(s->params, s->budget, cfg->max_batch, s->cfg.waves_per_group));
+    const uint64_t per_lane = s->ctrl_cap + up256(16ull * cfg->max_batch);
+    s->fixed = per_lane * cfg->streams;
+    if (s->fixed + (1u << 16) > s->budget) {
+        delete s;
+        return RANS_ENOMEM;  // the budget does not even hold the control regions
+    }
+    void* mem = nullptr;
+    if (hipMalloc(&mem, s->budget) != hipSuccess) {
+        (void)hipGetLastError();
         delete s;
         return RANS_ENOMEM;
     }
-    s->base = static_cast<uint8_t*>(arena);
-    s->arena.init(s->budget);
+    s->mem = static_cast<uint8_t*>(mem);
+    s->base = s->mem + s->fixed;
+    s->arena.init(s->budget - s->fixed);
+    s->used = s->peak = s->fixed;
     s->lanes.resize(cfg->streams);
-    const uint64_t per_lane = uint64_t(cfg->max_batch) * 16;
-    if (hipMalloc(reinterpret_cast<void**>(&s->ctrl), per_lane * cfg->streams) != hipSuccess) {
-        rans_server_destroy(s);
-        return RANS_ENOMEM;
-    }
     for (size_t i = 0; i < s->lanes.size(); ++i) {
         auto& ln = s->lanes[i];
-        ln.d_len = reinterpret_cast<uint64_t*>(s->ctrl + i * per_lane);
-        ln.d_status = reinterpret_cast<int32_t*>(s->ctrl + i * per_lane + 8ull * cfg->max_batch);
+        ln.ctrl = s->mem + i * per_lane;
+        ln.d_len = reinterpret_cast<uint64_t*>(ln.ctrl + s->ctrl_cap);
+        ln.d_status = reinterpret_cast<int32_t*>(ln.ctrl + s->ctrl_cap + 8ull * cfg->max_batch);
         if (hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void**>(&ln.h_status), 4ull * cfg->max_batch,
                           hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc(reinterpret_cast<void**>(&ln.h_len), 8ull * cfg->max_batch,
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&ln.h_jobs), 2 * sizeof(BatchJob) * uint64_t(cfg->max_batch),
                           hipHostMallocDefault) != hipSuccess) {
             rans_server_destroy(s);
             return RANS_EDEVICE;
@@ -297,13 +354,13 @@ extern "C" void rans_server_destroy(rans_server* s)
             (void)hipHostFree(ln.h_status);
         if (ln.h_len)
             (void)hipHostFree(ln.h_len);
+        if (ln.h_jobs)
+            (void)hipHostFree(ln.h_jobs);
     }
     for (auto& kv : s->live)
         delete kv.second;
-    if (s->base)
-        (void)hipFree(s->base);
-    if (s->ctrl)
-        (void)hipFree(s->ctrl);
+    if (s->mem)
+        (void)hipFree(s->mem);
     delete s;
 }
 
@@ -312,6 +369,8 @@ extern "C" int rans_server_submit(rans_server* s, int op, const rans_table* tabl
 {
     if (!s || !table || !id || (op != RANS_OP_ENCODE && op != RANS_OP_DECODE) || (in_len && !d_in))
         return RANS_EINVAL;
+    if (op == RANS_OP_ENCODE && in_len % s->params.sym_bytes)
+        return RANS_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     Request* r = new Request();
     r->op = op;
@@ -319,9 +378,10 @@ extern "C" int rans_server_submit(rans_server* s, int op, const rans_table* tabl
     r->d_in = d_in;
     r->in_len = in_len;
     r->out_cap = out_cap;
-    r->out_alloc = out_cap ? out_cap : 16;
-    r->cost = request_cost(s, op, in_len, r->out_alloc);
-    if (r->cost > s->budget) {
+    r->scratch = op == RANS_OP_ENCODE ? batch_encode_scratch(in_len, s->params) : 0;
+    r->out_alloc = up256(out_cap ? out_cap : 16) + r->scratch;
+    r->cost = request_cost(in_len, r->out_alloc);
+    if (r->cost > s->budget - s->fixed) {
         delete r;
         return RANS_ENOMEM;
     }
@@ -390,6 +450,11 @@ extern "C" int rans_server_stats(rans_server* s, rans_server_stats_t* st)
     for (auto& ln : s->lanes)
         busy += ln.busy;
     st->busy_streams = busy;
+    st->peak_busy_streams = s->peak_busy;
+    st->launches = s->launches;
+    st->multi_request_launches = s->multi_launches;
+    st->max_launch_requests = s->max_launch_reqs;
+    st->fixed = s->fixed;
     return RANS_OK;
 }
 

@@ -29,6 +29,40 @@ Workspace* workspace_for(hipStream_t stream)
     return w;
 }
 
+void release_workspace(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return;
+    Workspace* w = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_ws.find(std::make_pair(dev, stream));
+        if (it == g_ws.end())
+            return;
+        w = it->second;
+        g_ws.erase(it);
+    }
+    {
+        // no call holds it any more once it is out of the map and its lock
+        // has been taken once
+        std::lock_guard<std::mutex> lk(w->mu);
+        (void)hipStreamSynchronize(stream);
+        w->drop_graphs();
+        if (w->dev)
+            (void)hipFree(w->dev);
+        if (w->pinned)
+            (void)hipHostFree(w->pinned);
+        if (w->host)
+            (void)hipHostFree(w->host);
+        if (w->staged)
+            (void)hipEventDestroy(w->staged);
+        if (w->capture)
+            (void)hipStreamDestroy(w->capture);
+    }
+    delete w;
+}
+
 void Workspace::drop_graphs()
 {
     for (auto& g : graphs)
@@ -102,3 +136,9 @@ EncodeLayout encode_layout(uint64_t n_chunks, uint32_t N, uint64_t slot_bytes)
 }
 
 }  // namespace rans
+
+extern "C" int rans_workspace_release(void* stream)
+{
+    rans::release_workspace(static_cast<hipStream_t>(stream));
+    return RANS_OK;
+}

@@ -5,6 +5,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "rans_internal.h"
 
@@ -67,6 +68,37 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out);
 bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra = 0);
 int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
               bool decode, const rans_batch_config* cfg_override);
+
+// A batched launch planned on the host: validated job descriptors and the
+// launch shape.  Its device memory is bound by the caller: a control region
+// of ctrl_bytes (counter, job array, item map) and, to encode, each job's
+// scratch (batch_encode_scratch bytes, bound with bind_encode_scratch).
+struct BatchPlan {
+    BatchArgs a{};
+    std::vector<BatchJob> hj;
+    Layout layout = kPacked;
+    uint32_t sw = 1;
+    bool decode = false;
+    uint64_t ctrl_bytes = 0;
+};
+int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, bool decode,
+               const rans_batch_config& cfg, BatchPlan* plan);
+// Work items job `jb` can take at most (decode: from its container length).
+uint64_t batch_item_bound(const rans_job& jb, const rans_params& p, bool decode, uint32_t G);
+// Control bytes of a launch of njobs jobs and max_items work items.
+uint64_t batch_ctrl_bytes(uint32_t njobs, uint64_t max_items);
+// Encode scratch of one job of in_len symbol bytes: its digit slots and
+// placement words (256-byte aligned parts).
+uint64_t batch_encode_scratch(uint64_t in_len, const rans_params& p);
+void bind_encode_scratch(BatchJob* jb, uint8_t* base, uint64_t in_len, const rans_params& p);
+// Copies the job descriptors through `pinned` (host, pinned, free to
+// overwrite) into ctrl and enqueues the planning and persistent kernels on
+// st: replayed as a graph cached in ws when use_graph, else launched.
+int launch_planned(BatchPlan& plan, uint8_t* ctrl, void* pinned, hipStream_t st, bool use_graph,
+                   Workspace* ws);
+// Frees the workspace of (current device, stream), if there is one; waits
+// for the stream first.
+void release_workspace(hipStream_t stream);
 rans_batch_config batch_config();
 void fill_decode_tables(const DevTable& t, Layout layout, DecodeArgs* a);
 

@@ -140,3 +140,36 @@ def test_quantizer_hand_computed_cases(lr):
             nm = key[len("counts_"):]
             got = lr.rans_quantize(np.array(g[key], dtype=np.uint64), g["k_" + nm][0])
             assert [int(v) for v in got] == g["expect_" + nm], nm
+
+
+def test_struct_layouts_match_the_header(lr, tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes
+    and field offsets (a mismatch would shift every field after it)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"rans_params": lr.rans_params, "rans_batch_config": lr.rans_batch_config,
+               "rans_tune_result": lr.rans_tune_result, "rans_job": lr.rans_job,
+               "rans_server_config": lr.rans_server_config, "rans_completion": lr.rans_completion,
+               "rans_server_stats_t": lr.rans_server_stats_t,
+               "rans_server_request": lr.rans_server_request}
+    # the binding names a field "in_" where C says "in"
+    cname = {"in_": "in"}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "librans.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {cname.get(f, f)}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == ct.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)

@@ -333,3 +333,38 @@ def test_batch_autotune_on_the_batch(lr, tmp_path):
     finally:
         lr.rans_batch_set_config(16, 1, 0, 1)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("G", [16, 1])
+def test_batch_decode_many_small_low_entropy_chunks(lr, G):
+    """N = 32 chunks of 4096 bytes of a two-symbol source with p0 = 0.995
+    cost about 170 bytes each (16 directory bytes, 128 of states, a few
+    digits): more chunks per
+    container byte than a 64-coder chunk can have.  A batch of such
+    containers decodes every chunk of every job, with one wave per work item
+    (G = 1: the most work items) too."""
+    import torch
+    k, r, l, N, C = 11, 16, 16, 32, 4096
+    data = []
+    for i in range(3):
+        rng = np.random.Generator(np.random.PCG64(4800 + i))
+        data.append(datagen.sample(datagen.dominant_probs(2, 0.995), (1 << 20) + 77 * i, rng))
+    refs, tables = [], []
+    for s in data:
+        c = datagen.counts(s, 256)
+        refs.append(oracle.encode(oracle.quantize(c, k), s, k, r, l, N, C))
+        tables.append(lr.rans_tables_build(c, k))
+    # more chunks than a 16 + 4 * 64 byte per chunk bound would allow
+    for s, ref in zip(data, refs):
+        assert (s.size + C - 1) // C > (ref.size - 32) // (16 + 4 * 64)
+    cfg = lr.rans_batch_get_config()
+    lr.rans_batch_set_config(G, 1, 0, 1)
+    try:
+        dec, st, n = run_decode_batch(lr, tables, refs, [s.size for s in data], k, r, l, N=N)
+    finally:
+        lr.rans_batch_set_config(cfg["waves_per_group"], cfg["groups_per_cu"], cfg["table_layout"],
+                                 cfg["use_graph"])
+    torch.cuda.synchronize()
+    assert (st == 0).all(), st
+    for i, s in enumerate(data):
+        assert n[i] == s.size and (dec[i] == s).all(), i

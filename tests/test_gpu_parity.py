@@ -316,5 +316,9 @@ def test_digit_orders_equal_hand_derived_streams(lr, name):
         got = gpu_encode(lr, table, (k, r, l, 1, N, 0, order), msg)
         states = got[off:off + 4 * N].view("<u4")
         assert [int(v) for v in states] == g["states"], order
-        assert [int(v) for v in got[off + 4 * N:]] == g[key], order
+        # the chunk's digits, then zero padding to the container's 16-byte end
+        digits = g[key]
+        end = off + 4 * N + len(digits)
+        assert [int(v) for v in got[off + 4 * N:end]] == digits, order
+        assert got.size == (end + 15) // 16 * 16 and not got[end:].any(), order
         assert (gpu_decode(lr, table, got, msg.size, 1) == msg).all(), order

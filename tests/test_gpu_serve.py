@@ -77,42 +77,68 @@ def alone(lr, req, params):
     return d[:n].cpu().numpy()
 
 
-@pytest.mark.parametrize("budget_mib,streams,max_batch", [(512, 4, 64), (8, 2, 4)])
+def check_result(lr, q, c, params, solo=True):
+    """A completion's output equals the request run alone and the oracle."""
+    assert c.status == 0, c.status
+    assert c.latency_us >= c.queue_us >= 0
+    got = device_bytes(c.d_out, c.out_len)
+    if q["op"] == lr.RANS_OP_ENCODE:
+        ref = oracle.encode(q["f"], q["syms"], K, R, L, N, C)
+        assert got.size == ref.size and (got == ref).all()
+    else:
+        assert got.size == q["syms"].size and (got == q["syms"]).all()
+    if solo:
+        alone_out = alone(lr, q, params)
+        assert got.size == alone_out.size and (got == alone_out).all()
+
+
+@pytest.mark.parametrize("budget_mib,streams,max_batch", [(512, 4, 16), (8, 2, 4)])
 def test_same_alone_and_in_the_mix(lr, budget_mib, streams, max_batch):
+    """A burst of every request at once, polled from here: each output,
+    checked (and released) as soon as it completes while the others run,
+    equals the request run alone and the oracle, and the server's counters
+    show that launches held several requests and that several streams ran at
+    once.  Then Poisson arrivals through the replay loop: every request
+    completes with the oracle's output length, and free device memory is the
+    same before and after (the server allocates nothing while serving)."""
+    import torch
     reqs, params = make_requests(lr, 60, seed=5101)
-    arrivals = poisson(len(reqs), rate_per_us=1 / 30.0, seed=7)
     srv = lr.rans_server_create(budget_mib << 20, streams, max_batch, params)
     try:
+        ids = {lr.rans_server_submit(srv, q["op"], q["table"], q["d_in"], q["in_len"],
+                                     q["out_cap"]): q for q in reqs}
+        done = 0
+        for _ in range(1000000):
+            for c in lr.rans_server_poll(srv, keep_outputs=True):
+                check_result(lr, ids[c.id], c, params, solo=done % 3 == 0)
+                lr.rans_server_release(srv, c.id)
+                done += 1
+            if done == len(reqs):
+                break
+        assert done == len(reqs)
+        st = lr.rans_server_stats(srv)
+        assert st["peak"] <= st["budget"] and st["used"] == st["fixed"]
+        assert st["max_launch_requests"] > 1 and st["multi_request_launches"] >= 1, st
+        assert st["peak_busy_streams"] > 1, st
+
+        arrivals = poisson(len(reqs), rate_per_us=1 / 30.0, seed=7)
         spec = [(q["op"], q["table"], q["d_in"], q["in_len"], q["out_cap"], t)
                 for q, t in zip(reqs, arrivals)]
-        # keep outputs only if the budget can hold all of them
-        total = sum(q["in_len"] + q["out_cap"] + 3 * q["in_len"] for q in reqs)
-        keep = total < (budget_mib << 20)
-        if keep:
-            res, mk = lr.rans_server_replay(srv, spec, keep_outputs=True)
-        else:
-            res, mk = lr.rans_server_replay(srv, spec, keep_outputs=False)
-        st = lr.rans_server_stats(srv)
-        assert st["peak"] <= st["budget"]
-        assert mk > 0
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        res, mk = lr.rans_server_replay(srv, spec, keep_outputs=False)
+        free1 = torch.cuda.mem_get_info()[0]
+        assert free1 == free0, (free0, free1)
+        st2 = lr.rans_server_stats(srv)
+        assert st2["peak"] <= st2["budget"] and st2["used"] == st2["fixed"]
+        assert st2["launches"] > st["launches"] and mk > 0
         for q, c in zip(reqs, res):
             assert c.status == 0, c.status
             assert c.latency_us >= c.queue_us >= 0
             if q["op"] == lr.RANS_OP_ENCODE:
-                ref = oracle.encode(q["f"], q["syms"], K, R, L, N, C)
-                assert c.out_len == ref.size
+                assert c.out_len == oracle.encode(q["f"], q["syms"], K, R, L, N, C).size
             else:
                 assert c.out_len == q["syms"].size
-            if keep:
-                got = device_bytes(c.d_out, c.out_len)
-                solo = alone(lr, q, params)
-                assert got.size == solo.size and (got == solo).all()
-                if q["op"] == lr.RANS_OP_ENCODE:
-                    assert (got == ref).all()
-                else:
-                    assert (got == q["syms"]).all()
-                lr.rans_server_release(srv, c.id)
-        assert lr.rans_server_stats(srv)["used"] == 0
     finally:
         lr.rans_server_destroy(srv)
 
