@@ -199,6 +199,24 @@ int rans_encode_async(const rans_table *table, const rans_params *params, const 
                       uint64_t n_syms, void *d_out, uint64_t out_cap, uint64_t *d_out_len,
                       int32_t *d_status, void *stream);
 
+/* rans_encode_async for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same container, but the scratch that
+ * rans_encode_async keeps in a per-stream workspace (digit slots, chunk
+ * offsets, placement words) lives in one fixed 64 MiB array of device
+ * memory that every GPU the library runs on holds until the process ends.
+ * The call allocates nothing (no hipMalloc, no pinned memory, no events) and
+ * clears what must start at zero with a kernel.  A call needing more scratch
+ * than the array holds (about 2 bytes per symbol plus 1.3 KiB per chunk:
+ * some 31 million symbols in 64 KiB chunks) returns RANS_ENOMEM and launches
+ * nothing.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (two streams, or two host threads) race and must be ordered by
+ * the caller.  Arguments, errors and d_status / d_out_len as
+ * rans_encode_async (rANS only). */
+int rans_encode_async_noalloc(const rans_table *table, const rans_params *params,
+                              const void *d_syms, uint64_t n_syms, void *d_out, uint64_t out_cap,
+                              uint64_t *d_out_len, int32_t *d_status, void *stream);
+
 /* Stream-ordered decode.  h_header (host) is a copy of the container's first
  * 32 bytes, which the caller already holds (it is validated here, so no
  * device-to-host copy is needed).  *d_status as for rans_encode_async

@@ -110,6 +110,8 @@ _sig = {
                                ct.c_uint64, _u64p, ct.c_void_p]),
     "rans_encode_async": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
                                      ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "rans_encode_async_noalloc": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
+                                             ct.c_uint64, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "rans_decode_async": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_uint64, ct.c_char_p,
                                      ct.c_void_p, ct.c_uint64, ct.c_void_p, ct.c_void_p]),
     "rans_pfx_encode": (ct.c_int, [ct.c_void_p, _P, ct.c_void_p, ct.c_uint64, ct.c_void_p,
@@ -286,6 +288,17 @@ def rans_encode_async(table: Table, params, d_syms, n_syms: int, d_out, out_cap:
     _check(_lib.rans_encode_async(table.handle, ct.byref(p), _ptr(d_syms), n_syms, _ptr(d_out),
                                   out_cap, _ptr(d_out_len), _ptr(d_status), _stream(stream)),
            "rans_encode_async")
+
+
+def rans_encode_async_noalloc(table: Table, params, d_syms, n_syms: int, d_out, out_cap: int,
+                              d_out_len, d_status, stream=None):
+    """rans_encode_async with its scratch in the library's fixed device array
+    (allocates nothing; calls overlapping on one GPU race)."""
+    p = _params(params)
+    _check(_lib.rans_encode_async_noalloc(table.handle, ct.byref(p), _ptr(d_syms), n_syms,
+                                          _ptr(d_out), out_cap, _ptr(d_out_len), _ptr(d_status),
+                                          _stream(stream)),
+           "rans_encode_async_noalloc")
 
 
 def rans_decode_async(table: Table, d_in, in_len: int, header: bytes, d_syms, syms_cap: int,

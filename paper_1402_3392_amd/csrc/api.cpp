@@ -219,9 +219,9 @@ static bool fast64(uint32_t N, uint32_t C, uint32_t W, const void* syms)
 
 // Validates an encode call and fills the launch arguments (host only).
 // pfx: the prefix-code family multiplexed as Section 4 describes.
-static int prepare_encode(const rans_table* table, const rans_params* params, const void* d_syms,
-                          uint64_t n, void* d_out, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
-                          PlaceArgs* pa, uint64_t* ws_need, bool pfx = false)
+int rans::prepare_encode(const rans_table* table, const rans_params* params, const void* d_syms,
+                         uint64_t n, void* d_out, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
+                   PlaceArgs* pa, uint64_t* ws_need, bool pfx)
 {
     if (!table || !d_out)
         return RANS_EINVAL;
@@ -302,8 +302,7 @@ static int prepare_encode(const rans_table* table, const rans_params* params, co
     return RANS_OK;
 }
 
-static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
-                           PlaceArgs* pa)
+void rans::bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca, PlaceArgs* pa)
 {
     auto rb = [base](auto* p) { return reinterpret_cast<decltype(p)>(base + reinterpret_cast<uintptr_t>(p)); };
     ea->slots = rb(ea->slots);
@@ -322,8 +321,8 @@ static void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactA
     pa->total = sa->total;
 }
 
-static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
-                                 const PlaceArgs& pa, int R, int W, hipStream_t st, bool pfx = false)
+hipError_t rans::enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
+                                const PlaceArgs& pa, int R, int W, hipStream_t st, bool pfx, bool timed)
 {
     hipError_t e;
     if (pfx) {
@@ -334,7 +333,7 @@ static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const
                             2 * (ea.n_chunks + (ea.n_chunks + 63) / 64 + 1), st);
         if (e != hipSuccess)
             return e;
-        TimingScope ts(RANS_KERNEL_ENCODE, st);
+        TimingScope ts(RANS_KERNEL_ENCODE, st, timed);
         return launch_pfx_encode64(ea, pa, W, st);
     }
     if (ea.n_chunks > 0 && fast64(ea.N, ea.C, W, ea.syms)) {
@@ -344,19 +343,19 @@ static hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const
                             2 * (ea.n_chunks + (ea.n_chunks + 63) / 64 + 1), st);
         if (e != hipSuccess)
             return e;
-        TimingScope ts(RANS_KERNEL_ENCODE, st);
+        TimingScope ts(RANS_KERNEL_ENCODE, st, timed);
         return launch_encode64_place(ea, pa, R, W, st);
     }
     {
-        TimingScope ts(RANS_KERNEL_ENCODE, st);
+        TimingScope ts(RANS_KERNEL_ENCODE, st, timed);
         e = launch_encode(ea, R, W, st);
     }
     if (e == hipSuccess) {
-        TimingScope ts(RANS_KERNEL_SCAN, st);
+        TimingScope ts(RANS_KERNEL_SCAN, st, timed);
         e = launch_scan(sa, st);
     }
     if (e == hipSuccess) {
-        TimingScope ts(RANS_KERNEL_COMPACT, st);
+        TimingScope ts(RANS_KERNEL_COMPACT, st, timed);
         e = launch_compact(ca, st);
     }
     return e;

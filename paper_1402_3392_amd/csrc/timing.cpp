@@ -34,8 +34,10 @@ hipEvent_t get_event()
 }
 }  // namespace
 
-TimingScope::TimingScope(int kind, hipStream_t st) : kind_(kind), st_(st)
+TimingScope::TimingScope(int kind, hipStream_t st, bool allowed) : kind_(kind), st_(st)
 {
+    if (!allowed)
+        return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on)
         return;

@@ -4,10 +4,11 @@
 
 namespace rans {
 
-// RAII bracket of one kernel launch (no-op unless timing is enabled).
+// RAII bracket of one kernel launch (no-op unless timing is enabled and
+// `allowed`: callers that must not create events pass false).
 class TimingScope {
 public:
-    TimingScope(int kind, hipStream_t st);
+    TimingScope(int kind, hipStream_t st, bool allowed = true);
     ~TimingScope();
     TimingScope(const TimingScope&) = delete;
     TimingScope& operator=(const TimingScope&) = delete;

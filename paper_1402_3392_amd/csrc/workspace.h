@@ -96,6 +96,19 @@ void bind_encode_scratch(BatchJob* jb, uint8_t* base, uint64_t in_len, const ran
 // st: replayed as a graph cached in ws when use_graph, else launched.
 int launch_planned(BatchPlan& plan, uint8_t* ctrl, void* pinned, hipStream_t st, bool use_graph,
                    Workspace* ws);
+// Single-buffer encode (api.cpp).  prepare_encode validates the call on the
+// host and lays out its scratch as offsets (*ws_need bytes in all);
+// bind_workspace rebases them onto the scratch at `base`; enqueue_encode
+// launches the kernels on st.  pfx: the prefix-code family; timed = false
+// keeps the launches out of the diagnostic timing (which creates events).
+int prepare_encode(const rans_table* table, const rans_params* params, const void* d_syms,
+                   uint64_t n, void* d_out, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca,
+                   PlaceArgs* pa, uint64_t* ws_need, bool pfx = false);
+void bind_workspace(uint8_t* base, EncodeArgs* ea, ScanArgs* sa, CompactArgs* ca, PlaceArgs* pa);
+hipError_t enqueue_encode(const EncodeArgs& ea, const ScanArgs& sa, const CompactArgs& ca,
+                          const PlaceArgs& pa, int R, int W, hipStream_t st, bool pfx = false,
+                          bool timed = true);
+
 // Frees the workspace of (current device, stream), if there is one; waits
 // for the stream first.
 void release_workspace(hipStream_t stream);
