@@ -143,7 +143,13 @@ int rans_quantize(const uint64_t *counts, uint32_t alphabet, uint32_t prob_bits,
 
 /* Builds a table from host counts[alphabet] (quantised as rans_quantize
  * does) on the current device.  alphabet <= 65536, prob_bits 8..15.
- * *out receives a handle to destroy with rans_table_destroy.  Synchronous. */
+ * The table is the coding pair's data (Section 2: f_s and cum_s with
+ * M = 2^k, the symbol of every slot of [0, M) for D) plus, per symbol, the
+ * renormalisation bound of Algorithm 1's encoder and an exact reciprocal
+ * of f_s for C's division; one static table per input, as Section 7's
+ * order-0 model.  *out receives a handle to destroy with rans_table_destroy.
+ * Errors: RANS_EINVAL, RANS_EPREC (as rans_quantize), RANS_ENOMEM,
+ * RANS_EDEVICE.  Synchronous. */
 int rans_tables_build(const uint64_t *counts, uint32_t alphabet, uint32_t prob_bits,
                       rans_table **out);
 
@@ -167,7 +173,13 @@ int rans_params_check(const rans_params *params);
 uint64_t rans_encode_bound(uint64_t n_syms, const rans_params *params);
 
 /* Encodes d_syms[n_syms] (device; uint8 or uint16 per params->sym_bytes)
- * into a container at d_out (device, out_cap bytes).  The table's
+ * into a container at d_out (device, out_cap bytes).  Each chunk is coded by
+ * N interleaved coders (Section 3: symbol i of the chunk goes to coder
+ * i mod N), each one Algorithm 1's encoder (Section 2): starting from state
+ * L and walking the chunk backwards, a coder emits low digits of its state
+ * while it is at or above f_s*b*L/M, then applies C(s, x); the digits of a
+ * step are written in the order the decoders will read them, and the final
+ * states go to the head of the chunk's stream.  The table's
  * prob_bits must equal params->prob_bits.  *out_len (host) receives the
  * container length.  Blocks until the result is known (stream-ordered
  * before that).  Errors: RANS_EINVAL, RANS_ENOSYM (a symbol of frequency 0
@@ -179,7 +191,11 @@ int rans_encode(const rans_table *table, const rans_params *params, const void *
                 void *stream);
 
 /* Decodes the container d_in[in_len] (device) into d_syms (device,
- * syms_cap symbols of the container's width).  The table must be the one
+ * syms_cap symbols of the container's width).  Per chunk, the N coders start
+ * from the transmitted states and take the chunk's symbols round-robin
+ * (Section 3); each step is Algorithm 1's decoder (Section 2): (s, x) = D(x),
+ * then, while x < L, x = b*x + the next digit, the reading coders taking
+ * consecutive digits in coder order (Section 6's ballot and prefix count).  The table must be the one
  * the container was encoded with (same prob_bits; the library cannot check
  * more).  *n_syms (host) receives the symbol count.  The header is read
  * through a small device-to-host copy; the call blocks until the decode has
@@ -279,7 +295,10 @@ typedef struct rans_job {
 } rans_job;
 
 /* Batched encode of njobs independent streams with shared params in one
- * persistent-kernel pass (replayed as a HIP graph).  Asynchronous: results
+ * persistent-kernel pass (replayed as a HIP graph).  Every job is coded as
+ * rans_encode codes it (same container, byte for byte), with its own table;
+ * chunks of all jobs are independent coding units (Section 3), which is
+ * what lets one launch hold thousands of streams.  Asynchronous: results
  * are in the jobs' d_out_len / d_status once `stream` reaches this point.
  * Returns RANS_EINVAL for invalid params or job descriptors (checked on the
  * host), RANS_ENOMEM / RANS_EDEVICE for runtime failures. */
@@ -288,7 +307,8 @@ int rans_encode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *p
 
 /* Batched decode of njobs containers, all encoded with params' k, r, l, w,
  * N and digit order (checked per job on the device; a mismatch fails that
- * job with RANS_EINVAL).  Asynchronous, as rans_encode_batch. */
+ * job with RANS_EINVAL).  Each job decodes as rans_decode does (Sections 2,
+ * 3 and 6).  Asynchronous, as rans_encode_batch. */
 int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *params,
                       void *stream);
 

@@ -123,25 +123,30 @@ int parse_header(const uint8_t* h, uint64_t in_len, Header* out)
     return RANS_OK;
 }
 
-bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra)
+bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra, uint32_t seg_n)
 {
     const uint64_t maxl = static_cast<uint64_t>(max_lds_bytes());
+    // LDS per wave of the kernel that will run: the segment decoder for
+    // symbol output (seg_n = N), else the one-chunk decoder
+    auto per_wave = [seg_n](Layout lay) {
+        return seg_n ? decode_seg_lds_per_wave(lay, seg_n) : decode64_lds_per_wave(lay);
+    };
     const uint64_t packed = t.dec_bytes + t.sym_bytes + extra, two = t.sym_bytes + t.fc_bytes + extra;
     // One LDS read per symbol when the fused table leaves room for 16 waves'
     // rings; else the packed table (two independent reads) while it leaves
     // room for a second block; else the small two-level table with room for
     // at least one wave.  `extra`: LDS the kernel stages beside the table.
-    if (t.fused && t.fused_bytes + extra + 16 * decode64_lds_per_wave(kFused) <= maxl) {
+    if (t.fused && t.fused_bytes + extra + 16 * per_wave(kFused) <= maxl) {
         *layout = kFused;
         *lds = static_cast<uint32_t>(t.fused_bytes + extra);
         return true;
     }
-    if (packed + decode64_lds_per_wave(kPacked) <= maxl && packed <= 96 * 1024) {
+    if (packed + per_wave(kPacked) <= maxl && packed <= 96 * 1024) {
         *layout = kPacked;
         *lds = static_cast<uint32_t>(packed);
         return true;
     }
-    if (two + decode64_lds_per_wave(kTwoLevel) <= maxl) {
+    if (two + per_wave(kTwoLevel) <= maxl) {
         *layout = kTwoLevel;
         *lds = static_cast<uint32_t>(two);
         return true;
@@ -510,7 +515,8 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
                    (h->n && !fast64(h->p.interleave, h->p.chunk_syms, h->p.sym_bytes, d_syms))))
         return RANS_EINVAL;  // the one-wave-per-chunk decoder, symbol output only
     uint32_t lds;
-    if (!choose_layout(t, layout, &lds, lut_w ? lut_lds_bytes(t.alphabet, lut_w) : 0))
+    const uint32_t seg_n = lut_w == 0 && !h->p.escape && !h->pfx ? h->p.interleave : 0;
+    if (!choose_layout(t, layout, &lds, lut_w ? lut_lds_bytes(t.alphabet, lut_w) : 0, seg_n))
         return RANS_EINVAL;
     *da = DecodeArgs{};
     da->in = static_cast<const uint8_t*>(d_in);

@@ -12,7 +12,7 @@
 // every chunk a wave waits on belongs to a block that is already running,
 // and the copy overlaps the coding of other items.  Every block leaves when
 // the counter passes the last item.
-#include "coder64.h"
+#include "decode_seg.h"
 
 namespace rans {
 namespace {
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
     uint32_t si = 0;
     for (uint32_t j = lo; j < hi; ++j) {
         plan_job(a, j, decode);
-        si += (a.jobs[j].nch + a.G - 1) / a.G;
+        si += (a.jobs[j].nch + a.cpi - 1) / a.cpi;
     }
     part_i[tid] = si;
     __syncthreads();
@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_batch_prepare(BatchArgs a, boo
         // as a whole instead of being coded in part: its items keep their
         // place in the scan, but with no chunks every wave that takes one
         // skips it
-        const uint32_t nch_j = jb.nch, items = (nch_j + a.G - 1) / a.G;
+        const uint32_t nch_j = jb.nch, items = (nch_j + a.cpi - 1) / a.cpi;
         const bool over = uint64_t(bi) + items > a.max_items;
         if (over) {
             *jb.d_status = RANS_EINVAL;
@@ -218,8 +218,9 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
     // the waves' rings and output blocks first (low LDS addresses for the
     // direct-to-LDS loads), the job's tables after them
-    uint8_t* wave_lds = lds + wave * c64::wave_lds_bytes(LAYOUT);
-    uint8_t* tab = lds + a.G * c64::wave_lds_bytes(LAYOUT);
+    constexpr uint32_t SEG = c64::seg_count(NL);  // chunks per wave
+    uint8_t* wave_lds = lds + wave * c64::seg_wave_lds_bytes(LAYOUT, NL);
+    uint8_t* tab = lds + a.G * c64::seg_wave_lds_bytes(LAYOUT, NL);
     int cur = -1;
     uint32_t item;
     for (bool first = true;; first = false) {
@@ -233,13 +234,19 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
             cur = j;
         }
         const uint32_t nch = c64::uni(jb.nch);
-        const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
+        const uint32_t c = c64::uni(((item - jb.item_base) * a.G + wave) * SEG);
         if (c < nch) {
             const uint32_t sym_bytes = c64::uni(jb.sym_bytes);
-            c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
-                                                a.k, a.l, tab,
-                                                reinterpret_cast<const uint32_t*>(tab + sym_bytes),
-                                                wave_lds, jb.d_status);
+            if constexpr (SEG == 1)
+                c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n,
+                                                            jb.out, a.k, a.l, tab,
+                                                            reinterpret_cast<const uint32_t*>(tab + sym_bytes),
+                                                            wave_lds, jb.d_status);
+            else
+                c64::decode_seg<R, W, SW, LAYOUT, NL, BF>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
+                                                          a.k, a.l, tab,
+                                                          reinterpret_cast<const uint32_t*>(tab + sym_bytes),
+                                                          wave_lds, jb.d_status);
         }
     }
 }
@@ -303,7 +310,7 @@ hipError_t set_lds(K kernel, uint32_t bytes)
 template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
 hipError_t persistent_decode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
-    const uint32_t lds = a.tab_lds + a.G * c64::wave_lds_bytes(LAYOUT);
+    const uint32_t lds = a.tab_lds + a.G * c64::seg_wave_lds_bytes(LAYOUT, NL);
     auto kern = k_batch_decode64<R, W, SW, LAYOUT, NL, BF>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)

@@ -30,6 +30,12 @@ int num_cus()
 
 }  // namespace
 
+uint32_t batch_chunks_per_item(const rans_params& p, bool decode, uint32_t G)
+{
+    // a decoding wave codes 64 / N chunks, an encoding wave one
+    return decode ? G * (64u / p.interleave) : G;
+}
+
 uint64_t batch_item_bound(const rans_job& jb, const rans_params& p, bool decode, uint32_t G)
 {
     uint64_t nch;
@@ -43,7 +49,8 @@ uint64_t batch_item_bound(const rans_job& jb, const rans_params& p, bool decode,
         const uint64_t n = jb.in_len / p.sym_bytes;
         nch = p.chunk_syms ? (n + p.chunk_syms - 1) / p.chunk_syms : 0;
     }
-    return (nch + G - 1) / G;
+    const uint32_t cpi = batch_chunks_per_item(p, decode, G);
+    return (nch + cpi - 1) / cpi;
 }
 
 uint64_t batch_encode_scratch(uint64_t in_len, const rans_params& p)
@@ -88,7 +95,7 @@ int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, 
         return RANS_EINVAL;
     if (cfg.waves_per_group < 1 || cfg.waves_per_group > 16 || cfg.groups_per_cu < 1)
         return RANS_EINVAL;
-    const uint32_t G = cfg.waves_per_group;
+    uint32_t G = cfg.waves_per_group;
 
     // host checks of every descriptor and the launch shape they imply
     uint64_t max_items = 0;
@@ -128,7 +135,6 @@ int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, 
             const uint32_t el = enc_lds_bytes(b.enc_bytes, w);
             tab_lds = tab_lds > el ? tab_lds : el;
         }
-        max_items += batch_item_bound(jb, p, decode, G);
     }
     if (decode) {
         // table layout: the configured one, or the best one every table has
@@ -142,8 +148,10 @@ int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, 
             max_fused = std::max<uint64_t>(max_fused, t->fused_bytes);
         }
         // 256 bytes stay free for the persistent kernel's static LDS
-        const uint64_t room_fused = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave(kFused) - 256;
-        const uint64_t room = uint64_t(max_lds_bytes()) - uint64_t(G) * decode64_lds_per_wave(kPacked) - 256;
+        const uint64_t room_fused =
+            uint64_t(max_lds_bytes()) - uint64_t(G) * decode_seg_lds_per_wave(kFused, p.interleave) - 256;
+        const uint64_t room =
+            uint64_t(max_lds_bytes()) - uint64_t(G) * decode_seg_lds_per_wave(kPacked, p.interleave) - 256;
         if (cfg.table_layout == 1)
             layout = kPacked;
         else if (cfg.table_layout == 2)
@@ -180,10 +188,16 @@ int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, 
             tab_lds = tab_lds > b.sym_bytes + b.ent_bytes ? tab_lds : b.sym_bytes + b.ent_bytes;
         }
     }
-    if (max_items > 0xFFFFFFF0ull)
-        return RANS_EINVAL;
-    const uint32_t per_wave = decode ? decode64_lds_per_wave(layout) : kEncWaveLdsBytes;
+    // waves_per_group is a maximum: fewer waves per block when their rings
+    // and the table do not fit LDS together
+    const uint32_t per_wave = decode ? decode_seg_lds_per_wave(layout, p.interleave) : kEncWaveLdsBytes;
+    while (G > 1 && uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
+        --G;
     if (uint64_t(tab_lds) + uint64_t(G) * per_wave + 256 > uint64_t(max_lds_bytes()))
+        return RANS_EINVAL;
+    for (uint32_t j = 0; j < njobs; ++j)
+        max_items += batch_item_bound(jobs[j], p, decode, G);
+    if (max_items > 0xFFFFFFF0ull)
         return RANS_EINVAL;
 
     const uint64_t slot_bytes = decode ? 0 : slot_bytes_for(p.chunk_syms, p.prob_bits, R);
@@ -198,6 +212,7 @@ int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, 
     a.C = p.chunk_syms;
     a.bf = p.digit_order;
     a.G = G;
+    a.cpi = batch_chunks_per_item(p, decode, G);
     a.max_items = static_cast<uint32_t>(max_items ? max_items : 1);
     a.slot_bytes = slot_bytes;
     a.slot_stride = decode ? 0 : slot_bytes + kSlotPad;

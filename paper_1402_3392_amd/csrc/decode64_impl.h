@@ -6,7 +6,7 @@
 // output kind.
 #pragma once
 
-#include "coder64.h"
+#include "decode_seg.h"
 
 namespace rans {
 namespace {
@@ -54,20 +54,61 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
         a.status, lut, a.alphabet);
 }
 
+// Symbol output, rANS without escapes: 64 / NL chunks per wave (no lane
+// idles with N = 32), the decoder in decode_seg.h.
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
+__global__ void __launch_bounds__(1024) k_decode64_seg(const DecodeArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    constexpr uint32_t SEG = c64::seg_count(NL);
+    const void* symsrc = LAYOUT == kPacked ? a.tab1 : (LAYOUT == kFused ? nullptr : a.tab0);
+    const void* ent = LAYOUT == kPacked ? a.tab0 : (LAYOUT == kFused ? a.tab0 : a.tab1);
+    const uint32_t sym_bytes = LAYOUT == kPacked ? a.tab1_bytes : (LAYOUT == kFused ? 0 : a.tab0_bytes);
+    const uint32_t ent_bytes = LAYOUT == kPacked ? a.tab0_bytes : (LAYOUT == kFused ? a.tab0_bytes : a.tab1_bytes);
+    uint8_t* tab = lds + c64::uni(blockDim.x >> 6) * c64::seg_wave_lds_bytes(LAYOUT, NL);
+    c64::stage2(tab, symsrc, sym_bytes, ent, ent_bytes);
+    __syncthreads();
+    const uint32_t wave = c64::uni(threadIdx.x >> 6);
+    const uint64_t chunk0 = (uint64_t(blockIdx.x) * (blockDim.x >> 6) + wave) * SEG;
+    if (chunk0 >= a.n_chunks)
+        return;  // no barrier follows
+    uint8_t* wave_lds = lds + wave * c64::seg_wave_lds_bytes(LAYOUT, NL);
+    if constexpr (SEG == 1)
+        c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(a.in, a.in_len, a.n_chunks, chunk0, a.C, a.n, a.out, a.k,
+                                                    a.l, tab, reinterpret_cast<const uint32_t*>(tab + sym_bytes),
+                                                    wave_lds, a.status);
+    else
+        c64::decode_seg<R, W, SW, LAYOUT, NL, BF>(a.in, a.in_len, a.n_chunks, chunk0, a.C, a.n, a.out, a.k, a.l,
+                                                  tab, reinterpret_cast<const uint32_t*>(tab + sym_bytes), wave_lds,
+                                                  a.status);
+}
+
 // Waves per block: 16 when the tables leave room for them, fewer otherwise.
 template <int R, int W, int SW, int LAYOUT, int NL, bool BF, int LW, bool ESC, bool PFX = false>
 hipError_t run(const DecodeArgs& a, hipStream_t st)
 {
+    constexpr bool SEGK = LW == 0 && !ESC && !PFX;  // the segment decoder
+    constexpr uint32_t SEG = SEGK ? c64::seg_count(NL) : 1;
     const uint32_t tabs = a.tab0_bytes + a.tab1_bytes + lut_lds_bytes(a.alphabet, LW);
-    const uint32_t per = c64::wave_lds_bytes(LAYOUT);
+    const uint32_t per = SEGK ? c64::seg_wave_lds_bytes(LAYOUT, NL) : c64::wave_lds_bytes(LAYOUT);
     const uint32_t maxl = static_cast<uint32_t>(max_lds_bytes());
     const uint32_t fit = tabs + per <= maxl ? (maxl - tabs) / per : 0;
     if (fit == 0)
         return hipErrorInvalidValue;
-    uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
+    const uint32_t waves = (a.n_chunks + SEG - 1) / SEG;
+    uint32_t wpb = waves < 16 ? waves : 16;
     wpb = wpb < fit ? wpb : fit;
-    const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
+    const uint32_t blocks = (waves + wpb - 1) / wpb;
     const uint32_t lds = tabs + wpb * per;
+    if constexpr (SEGK) {
+        auto kern = k_decode64_seg<R, W, SW, LAYOUT, NL, BF>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a);
+        return hipGetLastError();
+    }
     auto kern = k_decode64<R, W, SW, LAYOUT, NL, BF, LW, ESC, PFX>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -169,7 +169,8 @@ struct BatchArgs {
     uint32_t njobs;
     uint32_t k, r, l, w, N, C;  // C: encode chunk size (0 = whole input)
     uint32_t bf;                // breadth-first digit order (Section 5)
-    uint32_t G;                 // chunks per work item = waves per block
+    uint32_t G;                 // waves per block
+    uint32_t cpi;               // chunks per work item: G times the chunks one wave decodes
     uint32_t* counter;          // work-queue head, set by the planning kernel
     uint32_t* totals;           // [0] work items, [1] chunks
     uint32_t* item_job;         // work item -> job
@@ -193,6 +194,8 @@ hipError_t launch_encode64_place(const EncodeArgs& a, const PlaceArgs& p, int R,
 // the code entries (a.enc_bytes), a.slots one slot of a.slot_bytes per chunk.
 hipError_t launch_pfx_encode64(const EncodeArgs& a, const PlaceArgs& p, int W, hipStream_t stream);
 uint32_t decode64_lds_per_wave(Layout layout);
+// LDS per wave of the decoder that codes 64 / N chunks per wave (N = 32, 64).
+uint32_t decode_seg_lds_per_wave(Layout layout, uint32_t N);
 // Decode fused with a table lookup: out[i] = lut[symbol i] (a.lut, a.lut_w).
 hipError_t launch_decode64_lut(const DecodeArgs& a, int R, Layout layout, hipStream_t stream);
 // LDS bytes of a staged lookup table of `alphabet` entries of lw bytes.

@@ -297,6 +297,21 @@ extern "C" int rans_server_create(const rans_server_config* cfg, rans_server** o
     s->max_batch = cfg->max_batch;
     s->cfg = batch_config();  // fixed for the server's life: it sizes the control regions
     s->cfg.use_graph = 0;
+    {
+        // waves per block that fit next to the largest two-level table of
+        // these parameters (a launch never runs with fewer, so the work-item
+        // bound below holds)
+        const uint32_t w = cfg->params.sym_bytes;
+        const uint64_t tab = (uint64_t(1) << cfg->params.prob_bits) * w + 4ull * (w == 1 ? 256 : 4096) + 256;
+        const uint64_t per = decode_seg_lds_per_wave(kTwoLevel, cfg->params.interleave);
+        const uint64_t maxl = static_cast<uint64_t>(max_lds_bytes());
+        const uint64_t fit = maxl > tab ? (maxl - tab) / per : 0;
+        if (fit == 0) {
+            delete s;
+            return RANS_EINVAL;
+        }
+        s->cfg.waves_per_group = static_cast<uint32_t>(std::min<uint64_t>(s->cfg.waves_per_group, fit));
+    }
     // per lane: the control region of a launch of max_batch requests whose
     // inputs fit the budget, then the status words
     s->ctrl_cap = batch_ctrl_bytes(cfg->max_batch,

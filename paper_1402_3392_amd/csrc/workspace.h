@@ -65,7 +65,8 @@ uint32_t raw_digits(uint32_t r);
 uint64_t slot_bytes_for(uint32_t C, uint32_t k, uint32_t r, bool esc = false);
 void make_header(uint8_t* h, const rans_params& p, uint32_t C, uint64_t n, uint32_t nch);
 int parse_header(const uint8_t* h, uint64_t in_len, Header* out);
-bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra = 0);
+bool choose_layout(const DevTable& t, Layout* layout, uint32_t* lds, uint32_t extra = 0,
+                   uint32_t seg_n = 0);
 int run_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, hipStream_t st,
               bool decode, const rans_batch_config* cfg_override);
 
@@ -83,6 +84,8 @@ struct BatchPlan {
 };
 int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, bool decode,
                const rans_batch_config& cfg, BatchPlan* plan);
+// Chunks one work item covers: waves per block times chunks per wave.
+uint32_t batch_chunks_per_item(const rans_params& p, bool decode, uint32_t G);
 // Work items job `jb` can take at most (decode: from its container length).
 uint64_t batch_item_bound(const rans_job& jb, const rans_params& p, bool decode, uint32_t G);
 // Control bytes of a launch of njobs jobs and max_items work items.
