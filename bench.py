@@ -1,18 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of interleaved streaming rANS on one MI355X.
 
-Workload: three 256 MiB uint8 buffers, i.i.d. Zipf(s) over 256 symbols for
-s in {0.8, 1.1, 1.5}; M = 2^14, b = L = 2^16, 64 interleaved coders per chunk
-(one per wave64 lane), 64 KiB chunks.  One step = encode every buffer into a
-container and decode it back (rANS encode + decode GB/s, the library's
-stream-ordered entry points; inputs resident in HBM; static tables built
-once per buffer before timing, as the paper's static order-0 model is fixed
-once per input).
+Default line (the metric: decode/encode GB/s, batched vs plain, p99 decode
+latency): the radix/precision sweep -- 84 feasible points of 64 MiB of
+symbol bytes (alphabets 2, 16, 256 as uint8 and 4096 as uint16; M = 2^11 or
+2^15; one dominant symbol, Zipf(1.1) or near-uniform; byte or 16-bit
+digits; 32 or 64 coders per chunk), each point with its own table -- coded
+by batched persistent launches, one per group of points sharing (k, r, l,
+w, N).  One step = batched encode + batched decode of every point (inputs
+resident in HBM; tables built once before timing, as the paper's static
+order-0 model is fixed once per input).
 
 value = uncompressed bytes encoded-and-decoded per second (GB = 1e9 B).
-Also reported: per-kernel times from HIP events recorded on the launch
-stream, the roofline of the dominant kernel, and the CPU oracle on a bounded
-sample of the same workload.
+Also reported: the batched kernels' roofline fractions from HIP events
+recorded on the launch stream, one plain launch per point at its own best
+chunk size (the speedup), the 4096-stream batch against plain per-stream
+calls, the serving loop's p50/p99 latency, the plain 256 MiB round trip,
+and the CPU oracle on a bounded sample (one thread and every host thread).
 """
 from __future__ import annotations
 
@@ -72,10 +76,13 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--workload", default="roundtrip",
-                    choices=["roundtrip", "batched", "sweep", "serving", "dequant", "escape",
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "roundtrip", "batched", "sweep", "serving", "dequant", "escape",
                              "prefix"],
-                    help="roundtrip: the headline line (3 x 256 MiB encode+decode); "
+                    help="headline: the metric's line (the radix/precision sweep encoded and decoded "
+                         "by batched launches, with the 4096-stream batch, serving and the round trip "
+                         "beside it); "
+                         "roundtrip: 3 x 256 MiB encode+decode by the plain entry points; "
                          "batched: 4096 uneven streams, one persistent launch vs plain calls; "
                          "sweep: radix/precision/alphabet sweep, batched vs plain decode; "
                          "serving: Poisson request loop, p50/p99 latency; "
@@ -93,6 +100,10 @@ def parse():
                     help="sweep: digit order within a step, depth-first or breadth-first "
                          "(differs only with byte digits)")
     ap.add_argument("--source-hash", action="store_true", help="print the kernels' source hash")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1402_3392_amd", "tune_mi355x.txt"),
+                    help="autotuner cache file (results measured on MI355X; '' disables it)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="headline: only the sweep line (no 4096-stream, serving, round-trip extras)")
     return ap.parse_args()
 
 
@@ -180,17 +191,19 @@ def base_result(metric, value, unit, args, config, higher=True):
             "vs_baseline": None, "dtype": "u32", "data": "synthetic", "config": config}
 
 
-def run_batched(args):
+def run_batched(args, emit=True):
     """Many independent streams of uneven length, each with its own table:
-    one persistent batched launch (a graph replay) against one plain
-    rans_decode_async / rans_encode_async call per stream on the same stream."""
+    one persistent batched launch (a graph replay; interleave factor, chunk
+    size and launch shape from the autotuner on the whole batch) against one
+    plain rans_decode_async / rans_encode_async call per stream on the same
+    stream, the plain calls at the chunk size that suits them best."""
     import numpy as np
     import torch
 
     import datagen
     import paper_1402_3392_amd as lr
 
-    K, R, L, N = 14, 16, 16, 64
+    K, R, L = 14, 16, 16
     log(f"generating {args.streams} streams")
     data = datagen.dirichlet_streams(nstreams=args.streams)
     sizes = [int(s.size) for s, _ in data]
@@ -198,8 +211,8 @@ def run_batched(args):
     log(f"{total / 2**30:.2f} GiB in {len(data)} streams; building tables")
     tables = [lr.rans_tables_build(datagen.counts(s, 256), K) for s, _ in data]
 
-    # the smallest chunk size bounds every container the tuner may choose
-    caps = [lr.rans_encode_bound(n, lr.rans_params.make(K, R, L, 1, N, 4096)) for n in sizes]
+    # 64 coders and the smallest chunk size bound every container the tuner may choose
+    caps = [lr.rans_encode_bound(n, lr.rans_params.make(K, R, L, 1, 64, 4096)) for n in sizes]
     pool = DevPool(sum((n + 255) // 256 * 256 for n in sizes) * 2 + sum(caps) + 256 * len(sizes))
     d_in = [pool.take(n) for n in sizes]
     for a, (s, _) in zip(d_in, data):
@@ -207,8 +220,9 @@ def run_batched(args):
     # chunk size and launch shape from the autotuner, timed on the whole batch
     tune_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], 0, 0, 0, 0) for i in range(len(data)))
     log("autotuning on the batch")
-    tune = lr.rans_autotune_batch(tune_jobs, len(data), lr.rans_params.make(K, R, L, 1, N, 65536))
-    C = int(tune["chunk_syms"])
+    tune = lr.rans_autotune_batch(tune_jobs, len(data), lr.rans_params.make(K, R, L, 1, 0, 65536),
+                                  args.tune_cache or None)
+    C, N = int(tune["chunk_syms"]), int(tune["interleave"])
     params = lr.rans_params.make(K, R, L, 1, N, C)
     d_cont = [pool.take(c) for c in caps]
     d_dec = [pool.take(n) for n in sizes]
@@ -247,8 +261,9 @@ def run_batched(args):
 
     reps = max(3, args.steps)
     res = {}
-    for name, fn in [("batched_decode", batched_decode), ("plain_decode", plain_decode),
-                     ("batched_encode", batched_encode), ("plain_encode", plain_encode)]:
+    lr.rans_timing_reset()
+    lr.rans_timing_enable(True)
+    for name, fn in [("batched_decode", batched_decode), ("batched_encode", batched_encode)]:
         for _ in range(max(1, args.warmup)):
             fn()
         torch.cuda.synchronize()
@@ -263,27 +278,73 @@ def run_batched(args):
             assert torch.equal(lens, lens_enc), name
         res[name] = t
         log(f"{name}: {t * 1e3:.2f} ms, {total / t / 1e9:.1f} GB/s")
+    lr.rans_timing_enable(False)
+    kt = {name: lr.rans_timing_read(kind) for name, kind in
+          (("decode", lr.RANS_KERNEL_BATCH_DECODE), ("encode", lr.RANS_KERNEL_BATCH_ENCODE))}
+    lr.rans_timing_reset()
+
+    # plain per-stream calls at each candidate chunk size (and N = 64, 32):
+    # the fastest decode and the fastest encode count as the plain baseline
+    plain = {}
+    for pn in (64, 32):
+        for pc in (65536, 16384, 4096):
+            pp = lr.rans_params.make(K, R, L, 1, pn, pc)
+
+            def penc(pp=pp):
+                for i in range(len(data)):
+                    lr.rans_encode_async(tables[i], pp, pool.view(d_in[i], sizes[i]), sizes[i],
+                                         pool.view(d_cont[i], caps[i]), caps[i], lens[i:i + 1], st[i:i + 1])
+            st.zero_()
+            penc()
+            torch.cuda.synchronize()
+            assert int(st.abs().sum()) == 0, "plain encode failed"
+            plen = [int(v) for v in lens.cpu().tolist()]
+            phdr = [bytes(pool.view(d_cont[i], 32).cpu().numpy().tobytes()) for i in range(len(data))]
+
+            def pdec(plen=plen, phdr=phdr):
+                for i in range(len(data)):
+                    lr.rans_decode_async(tables[i], pool.view(d_cont[i], plen[i]), plen[i], phdr[i],
+                                         pool.view(d_dec[i], sizes[i]), sizes[i], st[i:i + 1])
+            te, td = timed(penc, 2), timed(pdec, 2)
+            torch.cuda.synchronize()
+            assert int(st.abs().sum()) == 0, "plain decode failed"
+            plain[(pn, pc)] = (te, td)
+            log(f"plain N={pn} C={pc}: encode {total / te / 1e9:.1f} GB/s, decode {total / td / 1e9:.1f} GB/s")
+    best_dec = min(plain, key=lambda q: plain[q][1])
+    best_enc = min(plain, key=lambda q: plain[q][0])
+    res["plain_decode"], res["plain_encode"] = plain[best_dec][1], plain[best_enc][0]
+    # the batched containers again (the plain runs overwrote them)
+    lr.rans_encode_batch(enc_jobs, len(data), params)
+    lr.rans_decode_batch(dec_jobs, len(data), params)
+    torch.cuda.synchronize()
+    assert int(st.abs().sum()) == 0
     alg = comp + total + 4 * 256 * len(data)
+    dec_us = 1e3 * kt["decode"][1] / max(kt["decode"][0], 1)
     out = base_result("rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
                       round(total / res["batched_decode"] / 1e9, 3), "GB/s", args,
                       {"workload": f"{len(data)} uint8 streams, lengths 2^U(10,22) B "
                                    f"({total / 2**30:.2f} GiB), Dirichlet(alpha in 0.05..5) tables, "
-                                   f"M=2^14, b=L=2^16, N=64, C={C} (autotuned), batched decode"})
+                                   f"M=2^14, b=L=2^16, N={N}, C={C} (autotuned), batched decode"})
     out.update({
         "batched_decode_gbps": round(total / res["batched_decode"] / 1e9, 2),
         "plain_decode_gbps": round(total / res["plain_decode"] / 1e9, 2),
+        "plain_decode_choice": {"N": best_dec[0], "C": best_dec[1]},
         "decode_speedup": round(res["plain_decode"] / res["batched_decode"], 2),
         "batched_encode_gbps": round(total / res["batched_encode"] / 1e9, 2),
         "plain_encode_gbps": round(total / res["plain_encode"] / 1e9, 2),
+        "plain_encode_choice": {"N": best_enc[0], "C": best_enc[1]},
         "encode_speedup": round(res["plain_encode"] / res["batched_encode"], 2),
         "compression_ratio": round(comp / total, 4),
         "autotune": {k: (round(v, 2) if isinstance(v, float) else v) for k, v in tune.items()},
         "roofline": {"bound": "hbm", "kernel": "k_batch_decode64", "unit": "GB/s",
-                     "achieved": round(alg / res["batched_decode"] / 1e9, 1), "peak": HBM_PEAK_GBPS,
-                     "frac": round(alg / res["batched_decode"] / 1e9 / HBM_PEAK_GBPS, 4),
-                     "traffic": None, "note": "whole launch incl. planning kernels"},
+                     "achieved": round(alg / (dec_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "frac": round(alg / (dec_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "avg_us": round(dec_us, 1),
+                     "note": "events around each launch (planning kernel included)"},
     })
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def run_sweep(args):
@@ -486,6 +547,328 @@ def run_dequant(args):
                      "frac": round(alg / t / 1e9 / HBM_PEAK_GBPS, 4), "traffic": None},
     })
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    """The host CPU's model name (as /proc/cpuinfo gives it), or ''."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
+def host_threads():
+    """Threads the CPU baseline may use: the cores this process may run on,
+    at most 16 (one GPU's share of the host on the GPU machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_points(points, one_bytes, many_bytes):
+    """The oracle, as it is, on a bounded sample of the sweep: encode + decode
+    of the first one_bytes of every point with one thread, and of the first
+    many_bytes of every point with every host thread (over chunks)."""
+    import numpy as np
+
+    import oracle
+
+    def run(nbytes, threads):
+        tot_b, tot_s = 0, 0.0
+        for p, syms, f, C in points:
+            s = np.ascontiguousarray(syms[: nbytes // syms.itemsize])
+            t0 = time.perf_counter()
+            c = oracle.encode(f, s, p["k"], p["r"], p["l"], p["N"], C, threads=threads)
+            d = oracle.decode(f, c, threads=threads)
+            tot_s += time.perf_counter() - t0
+            assert (d == s).all()
+            tot_b += s.nbytes
+        return tot_b / tot_s / 1e9
+
+    many = host_threads()
+    single = run(one_bytes, 1)
+    multi = run(many_bytes, many)
+    return {"value": round(multi, 4), "unit": "GB/s", "cores": many, "kind": "oracle",
+            "single_thread_gbps": round(single, 4), "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
+            "sample": f"encode+decode of the first {many_bytes >> 20} MiB of each of the "
+                      f"{len(points)} sweep points with {many} threads over chunks; single-thread "
+                      f"figure on the first {one_bytes >> 20} MiB of each point"}
+
+
+class SweepGroups:
+    """The radix/precision sweep as batches: the points sharing (k, r, l, w,
+    N) -- the three distributions of every alphabet of one symbol width --
+    form one job list, each point with its own table; all stay resident."""
+
+    def __init__(self, args, tune_cache):
+        import numpy as np
+        import torch
+
+        import datagen
+        import paper_1402_3392_amd as lr
+
+        self.lr = lr
+        pts = [p for p in datagen.sweep_points() if p["feasible"]]
+        groups = {}
+        for p in pts:
+            groups.setdefault((p["k"], p["r"], p["l"], p["w"], p["N"]), []).append(p)
+        data = {}
+        for p in pts:
+            key = (p["alphabet"], p["dist"])
+            if key not in data:
+                data[key] = datagen.sweep_data(p["alphabet"], p["dist"])[0]
+        self.groups = []
+        self.points = []  # (point, symbols, quantised frequencies, C) for the CPU baseline
+        for (k, r, l, w, N), gp in sorted(groups.items()):
+            syms = [data[(p["alphabet"], p["dist"])] for p in gp]
+            sizes = [int(x.nbytes) for x in syms]
+            tables = [lr.rans_tables_build(datagen.counts(x, p["alphabet"]), k) for p, x in zip(gp, syms)]
+            d_in = [torch.from_numpy(x.view(np.uint8)).cuda() for x in syms]
+            # the largest container any tuned chunk size can give
+            cap_params = lr.rans_params.make(k, r, l, w, N, 4096 // w)
+            caps = [lr.rans_encode_bound(x.size, cap_params) for x in syms]
+            d_cont = [torch.empty(c, dtype=torch.uint8, device="cuda") for c in caps]
+            d_dec = [torch.empty_like(x) for x in d_in]
+            lens = torch.zeros(len(gp), dtype=torch.int64, device="cuda")
+            st = torch.zeros(len(gp), dtype=torch.int32, device="cuda")
+            tune_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], 0, 0, 0, 0) for i in range(len(gp)))
+            tune = lr.rans_autotune_batch(tune_jobs, len(gp), lr.rans_params.make(k, r, l, w, N, 65536 // w),
+                                          tune_cache)
+            C = int(tune["chunk_syms"])
+            params = lr.rans_params.make(k, r, l, w, N, C)
+            cfg = (int(tune["waves_per_group"]), int(tune["groups_per_cu"]), int(tune["table_layout"]),
+                   int(tune["use_graph"]))
+            enc_jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], d_cont[i], caps[i],
+                                     int(lens.data_ptr()) + 8 * i, int(st.data_ptr()) + 4 * i)
+                                    for i in range(len(gp)))
+            lr.rans_batch_set_config(*cfg)
+            lr.rans_encode_batch(enc_jobs, len(gp), params)
+            torch.cuda.synchronize()
+            assert int(st.abs().sum()) == 0, f"batched encode status {st.tolist()}"
+            clen = [int(v) for v in lens.cpu().tolist()]
+            dec_jobs = lr.make_jobs((tables[i], d_cont[i], clen[i], d_dec[i], sizes[i],
+                                     int(lens.data_ptr()) + 8 * i, int(st.data_ptr()) + 4 * i)
+                                    for i in range(len(gp)))
+            g = dict(key=(k, r, l, w, N), points=gp, syms=syms, sizes=sizes, tables=tables, d_in=d_in,
+                     d_cont=d_cont, d_dec=d_dec, caps=caps, lens=lens, st=st, clen=clen, C=C, cfg=cfg,
+                     params=params, enc_jobs=enc_jobs, dec_jobs=dec_jobs,
+                     alg=sum(clen) + sum(sizes) + sum(4 * p["alphabet"] for p in gp))
+            self.groups.append(g)
+            import oracle
+            for p, x in zip(gp, syms):
+                self.points.append((p, x, oracle.quantize(datagen.counts(x, p["alphabet"]), k), C))
+            log(f"group k={k} r={r} w={w} N={N}: {len(gp)} points, C={C}, shape {cfg}, "
+                f"ratio {sum(clen) / sum(sizes):.4f}")
+        self.total = sum(sum(g["sizes"]) for g in self.groups)
+        self.alg = sum(g["alg"] for g in self.groups)
+
+    def encode(self, g):
+        self.lr.rans_batch_set_config(*g["cfg"])
+        self.lr.rans_encode_batch(g["enc_jobs"], len(g["points"]), g["params"])
+
+    def decode(self, g):
+        self.lr.rans_batch_set_config(*g["cfg"])
+        self.lr.rans_decode_batch(g["dec_jobs"], len(g["points"]), g["params"])
+
+    def step(self):
+        for g in self.groups:
+            g["st"].zero_()
+            self.encode(g)
+            self.decode(g)
+
+    def check(self):
+        import torch
+        for g in self.groups:
+            assert int(g["st"].abs().sum()) == 0, (g["key"], g["st"].tolist())
+            assert [int(v) for v in g["lens"].cpu().tolist()] == [x.size for x in g["syms"]]
+            for a, b in zip(g["d_dec"], g["d_in"]):
+                assert torch.equal(a, b), g["key"]
+
+    def group_times(self, reps):
+        """Batched decode and encode of each group alone (median of reps)."""
+        rows = []
+        for g in self.groups:
+            td = timed(lambda: self.decode(g), reps)
+            te = timed(lambda: self.encode(g), reps)
+            k, r, l, w, N = g["key"]
+            rows.append({"k": k, "r": r, "w": w, "N": N, "points": len(g["points"]), "C": g["C"],
+                         "shape": list(g["cfg"]), "ratio": round(sum(g["clen"]) / sum(g["sizes"]), 4),
+                         "batched_decode_gbps": round(sum(g["sizes"]) / td / 1e9, 1),
+                         "batched_encode_gbps": round(sum(g["sizes"]) / te / 1e9, 1),
+                         "decode_roofline_frac": round(g["alg"] / td / 1e9 / HBM_PEAK_GBPS, 4),
+                         "encode_roofline_frac": round(g["alg"] / te / 1e9 / HBM_PEAK_GBPS, 4),
+                         "t_decode": td, "t_encode": te})
+        return rows
+
+    def plain_best(self, reps):
+        """One plain launch per point, each at the chunk size that suits it
+        best (the fastest of 64, 32, 16, 8 and 4 KiB chunks, separately for
+        decode and encode); returns the total times over all points."""
+        import torch
+        lr = self.lr
+        t_dec, t_enc = 0.0, 0.0
+        for g in self.groups:
+            k, r, l, w, N = g["key"]
+            for i, p in enumerate(g["points"]):
+                n = g["syms"][i].size
+                st = torch.zeros(1, dtype=torch.int32, device="cuda")
+                olen = torch.zeros(1, dtype=torch.int64, device="cuda")
+                best_d, best_e = 1e30, 1e30
+                for C in (65536, 32768, 16384, 8192, 4096):
+                    Cw = C // w
+                    pp = lr.rans_params.make(k, r, l, w, N, Cw)
+                    cap = lr.rans_encode_bound(n, pp)
+                    out = g["d_cont"][i]
+                    assert cap <= out.numel()
+                    enc = lambda: lr.rans_encode_async(g["tables"][i], pp, g["d_in"][i], n, out, cap, olen, st)
+                    te = timed(enc, reps)
+                    torch.cuda.synchronize()
+                    nb = int(olen)
+                    hdr = bytes(out[:32].cpu().numpy().tobytes())
+                    dec = lambda: lr.rans_decode_async(g["tables"][i], out, nb, hdr, g["d_dec"][i], n, st)
+                    td = timed(dec, reps)
+                    torch.cuda.synchronize()
+                    assert int(st) == 0 and torch.equal(g["d_dec"][i], g["d_in"][i])
+                    best_d, best_e = min(best_d, td), min(best_e, te)
+                t_dec += best_d
+                t_enc += best_e
+        # the batched containers again (the plain runs overwrote them)
+        for g in self.groups:
+            g["st"].zero_()
+            self.encode(g)
+        torch.cuda.synchronize()
+        return t_dec, t_enc
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per step of `kernel` on `workload` from profiles/traffic.txt
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or None
+    when they were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = kernel_source_hash()
+    for line in open(path):
+        if line.startswith("#") or "=" not in line:
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split())
+        if kv.get("kernel") == kernel and kv.get("source") == src and kv.get("workload") == workload:
+            return int(kv["traffic_bytes"])
+    return None
+
+
+def run_headline(args):
+    """The metric's line.  Value: the radix/precision sweep (84 feasible
+    points of 64 MiB each) encoded and decoded by batched persistent launches,
+    one per group of points sharing (k, r, l, w, N), in uncompressed GB/s.
+    Beside it: the batched kernels' roofline fractions, one plain launch per
+    point at its own best chunk size (the speedup), the 4096-stream batch
+    against plain per-stream calls, the serving loop's p50/p99, the plain
+    256 MiB round trip, and the CPU oracle."""
+    import torch
+
+    import paper_1402_3392_amd as lr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tune_cache = args.tune_cache or None
+    log("sweep: generating 12 x 64 MiB, building 84 tables, batching by (k, r, l, w, N)")
+    sw = SweepGroups(args, tune_cache)
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        sw.step()
+    torch.cuda.synchronize()
+    sw.check()
+    log(f"timing {args.steps} steps")
+    lr.rans_timing_reset()
+    lr.rans_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sw.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lr.rans_timing_enable(False)
+    sw.check()
+    kt = {name: lr.rans_timing_read(kind) for name, kind in
+          (("decode", lr.RANS_KERNEL_BATCH_DECODE), ("encode", lr.RANS_KERNEL_BATCH_ENCODE))}
+    lr.rans_timing_reset()
+    elapsed = t1 - t0
+    value = args.steps * sw.total / elapsed / 1e9
+    nlaunch = len(sw.groups)
+
+    def roof(name, kname):
+        cnt, ms = kt[name]
+        avg_us = 1e3 * ms / max(cnt, 1)
+        alg_launch = sw.alg / nlaunch
+        ach = args.steps * sw.alg / (ms / 1e3) / 1e9
+        tr = traffic_for(kname, "sweep84")
+        return {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                "traffic": None if tr is None else int(tr / nlaunch),
+                "alg_bytes_per_launch": int(alg_launch), "launches": cnt, "avg_us": round(avg_us, 1),
+                "note": "12 launches per step (one per group); events around each launch, "
+                        "planning kernel included"}
+
+    dom, other = ("encode", "decode") if kt["encode"][1] >= kt["decode"][1] else ("decode", "encode")
+    knames = {"decode": "k_batch_decode64", "encode": "k_batch_encode64"}
+    log("per-group times")
+    rows = sw.group_times(max(3, args.steps))
+    log("plain launches per point at their best chunk size")
+    plain_dec, plain_enc = sw.plain_best(3)
+    bat_dec = sum(r["t_decode"] for r in rows)
+    bat_enc = sum(r["t_encode"] for r in rows)
+    for r in rows:
+        del r["t_decode"], r["t_encode"]
+    res = base_result("rANS decode/encode GB/s on 1 MI355X, batched vs plain; p99 decode latency",
+                      round(value, 2), "GB/s", args,
+                      {"workload": "radix/precision sweep: 84 feasible points of 64 MiB of symbol bytes "
+                                   "(alphabets 2/16/256 uint8 and 4096 uint16; M=2^11/2^15; p0=0.995, "
+                                   "Zipf(1.1), near-uniform; (b,L)=(2^8,2^23)/(2^16,2^16); N=32/64), "
+                                   "each with its own table, batched by (k,r,l,w,N): 12 persistent "
+                                   "launches per direction, chunk size and launch shape autotuned per "
+                                   "batch; one step = batched encode + batched decode of every point",
+                       "points": 84, "launches_per_step": 2 * nlaunch,
+                       "symbol_bytes_per_step": sw.total, "parallelism": "none"})
+    res["ms_per_step"] = round(1e3 * elapsed / args.steps, 3)
+    res["batched_decode_gbps"] = round(sw.total / bat_dec / 1e9, 1)
+    res["batched_encode_gbps"] = round(sw.total / bat_enc / 1e9, 1)
+    res["plain_decode_gbps"] = round(sw.total / plain_dec / 1e9, 1)
+    res["plain_encode_gbps"] = round(sw.total / plain_enc / 1e9, 1)
+    res["decode_speedup_vs_plain"] = round(plain_dec / bat_dec, 2)
+    res["encode_speedup_vs_plain"] = round(plain_enc / bat_enc, 2)
+    res["plain_note"] = "one launch per point, each at its fastest of 64/32/16/8/4 KiB chunks"
+    res["roofline"] = roof(dom, knames[dom])
+    res[f"roofline_{other}"] = roof(other, knames[other])
+    res["groups"] = rows
+    if not args.headline_only:
+        log("4096 streams: batched vs plain")
+        b = run_batched(args, emit=False)
+        res["batched_4096_streams"] = {k: b[k] for k in (
+            "value", "batched_decode_gbps", "plain_decode_gbps", "plain_decode_choice", "decode_speedup",
+            "batched_encode_gbps", "plain_encode_gbps", "plain_encode_choice", "encode_speedup",
+            "compression_ratio", "autotune", "roofline")}
+        res["batched_4096_streams"]["workload"] = b["config"]["workload"]
+        log("serving")
+        sv = run_serving(args, emit=False, rates=(0.5, 1.0))
+        at1 = [r for r in sv["rates"] if r["rate_frac"] == 1.0][0]
+        res["serving"] = {"workload": sv["config"]["workload"], "saturated_gbps": sv["saturated_gbps"],
+                          "decode_p50_ms": at1.get("decode_p50_ms"), "decode_p99_ms": at1.get("decode_p99_ms"),
+                          "encode_p50_ms": at1.get("encode_p50_ms"), "encode_p99_ms": at1.get("encode_p99_ms"),
+                          "rates": sv["rates"]}
+        log("256 MiB round trip")
+        rt = run_roundtrip(args, emit=False)
+        res["roundtrip_3x256MiB"] = {k: rt[k] for k in ("value", "decode_gbps_kernel", "encode_gbps_kernels",
+                                                        "kernels", "roofline", "roofline_decode")}
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: 1 thread and {host_threads()} threads")
+        res["cpu_baseline"] = cpu_baseline_points(sw.points, 1 << 20, 8 << 20)
+    print(json.dumps(res), flush=True)
 
 
 def run_sweep_grouped(args):
@@ -747,7 +1130,7 @@ def run_prefix(args):
     print(json.dumps(out), flush=True)
 
 
-def run_serving(args):
+def run_serving(args, emit=True, rates=(0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
     """Request loop: Poisson arrivals of mixed encode/decode requests under an
     8 GiB HBM budget, rates swept around the saturated throughput; p50/p99
     latency (arrival to completion) per operation and aggregate GB/s."""
@@ -762,8 +1145,7 @@ def run_serving(args):
     reqs = datagen.serving_requests(nreq=args.requests)
     log(f"{len(reqs)} requests, {sum(q['size'] for q in reqs) / 2**30:.2f} GiB; staging")
     staged = []
-    for q in reqs:
-        syms = datagen.request_data(q)
+    for q, syms in zip(reqs, datagen.requests_data(reqs)):
         table = lr.rans_tables_build(datagen.counts(syms, 256), K)
         d = torch.from_numpy(syms).cuda()
         if q["op"] == "encode":
@@ -792,7 +1174,7 @@ def run_serving(args):
     _, mk = replay(np.zeros(len(staged)))
     sat_rate = len(staged) / mk  # requests per microsecond
     rows = []
-    for frac in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+    for frac in rates:
         rng = np.random.Generator(np.random.PCG64(5001 + int(frac * 100)))
         arr = np.cumsum(rng.exponential(1.0 / (frac * sat_rate), len(staged)))
         arr -= arr[0]
@@ -816,7 +1198,9 @@ def run_serving(args):
                                    "8 GiB HBM budget, Poisson arrivals"}, higher=False)
     out.update({"saturated_gbps": round(total / (len(staged) / sat_rate * 1e-6) / 1e9, 2),
                 "rates": rows, "server": stats})
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -833,14 +1217,17 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    if args.workload != "roundtrip":
-        if args.workload == "sweep" and args.grouped:
-            run_sweep_grouped(args)
-            return
-        {"batched": run_batched, "sweep": run_sweep, "serving": run_serving,
-         "dequant": run_dequant, "escape": run_escape, "prefix": run_prefix}[args.workload](args)
+    if args.workload == "sweep" and args.grouped:
+        run_sweep_grouped(args)
         return
+    {"headline": run_headline, "roundtrip": run_roundtrip, "batched": run_batched, "sweep": run_sweep,
+     "serving": run_serving, "dequant": run_dequant, "escape": run_escape,
+     "prefix": run_prefix}[args.workload](args)
 
+
+def run_roundtrip(args, emit=True):
+    """Three 256 MiB Zipf buffers encoded and decoded by the plain
+    single-buffer entry points (64 KiB chunks, 64 coders)."""
     import numpy as np
     import torch
 
@@ -963,11 +1350,13 @@ def main():
                               "frac": round(alg_total / (kt[other][1] / 1e3) / 1e9 /
                                             HBM_PEAK_GBPS, 4)},
     }
-    if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+    if emit and not args.no_cpu_baseline:
+        threads = args.cpu_threads or host_threads()
         log(f"cpu baseline with {threads} threads")
         res["cpu_baseline"] = cpu_baseline(list(zip(work, freqs)), threads)
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res
 
 
 if __name__ == "__main__":

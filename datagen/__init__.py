@@ -231,14 +231,18 @@ def dirichlet_streams(nstreams: int = 4096, lo_log2: float = 10.0, hi_log2: floa
     top = np.random.Generator(np.random.PCG64(ss))
     lens = np.floor(np.exp2(top.uniform(lo_log2, hi_log2, nstreams))).astype(np.int64)
     alphas = np.power(10.0, top.uniform(math.log10(0.05), math.log10(5.0), nstreams))
-    out = []
-    for i, child in enumerate(ss.spawn(nstreams)):
-        rng = np.random.Generator(np.random.PCG64(child))
+    children = ss.spawn(nstreams)
+
+    def one(i):
+        rng = np.random.Generator(np.random.PCG64(children[i]))
         p = rng.dirichlet(np.full(alphabet, alphas[i]))
         p = np.maximum(p, 0.0)
         p = p / p.sum()
-        out.append((sample(p, int(lens[i]), rng), p))
-    return out
+        return sample(p, int(lens[i]), rng, threads=1), p
+
+    # each stream has its own generator: the pool does not change the result
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, range(nstreams)))
 
 
 def serving_requests(nreq: int = 1000, seed: int = 5001, lo_log2: float = 12.0,
@@ -260,3 +264,12 @@ def serving_requests(nreq: int = 1000, seed: int = 5001, lo_log2: float = 12.0,
 def request_data(req: dict, seed: int = 5001) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64([seed, req["id"]]))
     return sample(req["probs"], req["size"], rng)
+
+
+def requests_data(reqs, seed: int = 5001, threads: int | None = None):
+    """request_data for every request, drawn on a thread pool (each request
+    has its own generator, so the result does not depend on the pool)."""
+    if threads is None:
+        threads = min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        return list(ex.map(lambda q: request_data(q, seed), reqs))

@@ -313,15 +313,19 @@ int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *p
                       void *stream);
 
 /* Launch shape of the batched entry points (process-wide; the autotuner
- * sets it).  waves_per_group: chunks one work item covers, i.e. waves per
- * persistent block sharing one staged table (1..16); groups_per_cu:
+ * sets it).  waves_per_group: waves per persistent block sharing one staged
+ * table (1..16; a maximum: a launch uses fewer when their rings and the
+ * table do not fit LDS together); a work item covers waves_per_group
+ * times 64 / N chunks (a decoding wave codes 64 / N chunks, an encoding
+ * wave one); groups_per_cu:
  * persistent blocks per compute unit (1..8); table_layout: decode table
  * layout in LDS, 0 = automatic, 1 = per-slot packed entries plus symbol
  * map, 2 = symbol map plus per-symbol entries, 3 = one 8-byte entry per slot
  * holding f, bias and symbol (8-bit alphabets, prob_bits <= 14); use_graph: replay the batch as a captured HIP
  * graph (1) or launch its kernels directly (0).  The batched kernels code
- * 32 or 64 interleaved coders per chunk (params->interleave 32 or 64; one
- * wave per chunk, so with 32 half of each wave idles); batched encode
+ * 32 or 64 interleaved coders per chunk (params->interleave 32 or 64; with
+ * 32 a decoding wave codes two chunks, lanes 0-31 and 32-63, and an
+ * encoding wave one chunk on half its lanes); batched encode
  * needs chunk_syms != 0 with chunk_syms * sym_bytes a multiple of 16, and
  * every buffer 16-byte aligned.  Batched calls on a stream that is being
  * captured launch directly (no nested graph). */
@@ -336,15 +340,20 @@ int rans_batch_get_config(rans_batch_config *cfg);
 
 /* Autotuner.  Times the batched kernels on a sample (d_syms[n_syms],
  * device, 16-byte aligned, coded with `table` and base's k, r, l, w) over
- * chunk sizes C in {4096 .. 65536} (chosen at encode time, written into
- * the container) and decode launch shapes (waves per work item, blocks per
- * CU, table layout), with 64 coders per chunk, then whether the best shape
- * runs faster replayed as a HIP graph or launched directly.  A candidate's
+ * the interleave factor N in {32, 64} (lanes per stream: a decoding wave
+ * codes 64 / N chunks at once) and chunk sizes C in {4096 .. 65536} (both
+ * chosen at encode time and written into the container), and decode
+ * launch shapes (waves per work item, blocks per CU, table layout), then
+ * whether the best shape runs faster replayed as a HIP graph or launched
+ * directly.  base->interleave 0 searches N over {32, 64}; 32 or 64 keeps
+ * it; base->chunk_syms is ignored.  A candidate's
  * score is its encode + decode time, penalised when its container exceeds
- * the 64 KiB-chunk container by more than 1%.  The best shape becomes the
- * process-wide rans_batch_config; *out reports it with the measured rates.  Results are
- * appended to cache_path (text, one line per device / parameter / alphabet
- * class / size class; NULL disables the cache) and reused on a hit. */
+ * the container of 64 coders and 64 KiB chunks by more than 1%.  The best
+ * shape becomes the process-wide rans_batch_config; *out reports it with
+ * the measured rates (the caller encodes with out->interleave and
+ * out->chunk_syms).  Results are appended to cache_path (text, one line
+ * per device / parameter / alphabet class / size class; NULL disables the
+ * cache) and reused on a hit. */
 typedef struct rans_tune_result {
     uint32_t chunk_syms;
     uint32_t waves_per_group;
@@ -353,7 +362,9 @@ typedef struct rans_tune_result {
     double encode_gbps;
     double decode_gbps;
     uint32_t use_graph;
-    uint32_t reserved;
+    uint32_t interleave;       /* N: coders per chunk */
+    uint32_t lanes_per_stream; /* lanes that code one chunk (N) */
+    uint32_t chunks_per_wave;  /* chunks a decoding wave codes at once (64 / N) */
 } rans_tune_result;
 int rans_autotune(const rans_table *table, const void *d_syms, uint64_t n_syms,
                   const rans_params *base, const char *cache_path, rans_tune_result *out);

@@ -55,7 +55,8 @@ class rans_tune_result(ct.Structure):
     _fields_ = [("chunk_syms", ct.c_uint32), ("waves_per_group", ct.c_uint32),
                 ("groups_per_cu", ct.c_uint32), ("table_layout", ct.c_uint32),
                 ("encode_gbps", ct.c_double), ("decode_gbps", ct.c_double),
-                ("use_graph", ct.c_uint32), ("reserved", ct.c_uint32)]
+                ("use_graph", ct.c_uint32), ("interleave", ct.c_uint32),
+                ("lanes_per_stream", ct.c_uint32), ("chunks_per_wave", ct.c_uint32)]
 
 
 class rans_job(ct.Structure):

@@ -1,10 +1,11 @@
 // Autotuner for the batched path.  Two kinds of knobs:
-//  * bitstream-visible, chosen at encode time: the chunk size C (smaller
-//    chunks mean more independent waves but 256 bytes of states and 16 bytes
-//    of directory per chunk);
-//  * bitstream-invisible, chosen at decode time: waves per work item (the
-//    lanes that work on one stream together: 64 per wave), persistent blocks
-//    per CU, and the LDS table layout.
+//  * bitstream-visible, chosen at encode time: the interleave factor N (32
+//    or 64 coders per chunk, i.e. lanes per stream: a decoding wave codes
+//    64 / N chunks at once) and the chunk size C (smaller chunks mean more
+//    independent waves but 4N bytes of states and 16 bytes of directory per
+//    chunk);
+//  * bitstream-invisible, chosen at decode time: waves per work item,
+//    persistent blocks per CU, and the LDS table layout.
 // Every candidate is timed on the caller's sample with the real batched
 // kernels (median of a few runs, HIP events on a private stream).  Results
 // are cached in a text file keyed by device, parameters, alphabet class and
@@ -48,7 +49,7 @@ std::string cache_key(const rans_params& p, uint32_t alphabet, uint64_t bytes)
     std::ostringstream os;
     os << prop.gcnArchName << "|k" << int(p.prob_bits) << "|r" << int(p.radix_bits) << "|l"
        << int(p.state_lbits) << "|w" << int(p.sym_bytes) << "|o" << int(p.digit_order) << "|a"
-       << alpha_class << "|s" << size_class;
+       << alpha_class << "|s" << size_class << "|n" << int(p.interleave);
     std::string k = os.str();
     std::replace(k.begin(), k.end(), ' ', '_');
     return k;
@@ -65,7 +66,8 @@ bool cache_lookup(const char* path, const std::string& key, rans_tune_result* r)
         std::string k;
         rans_tune_result t{};
         if (is >> k >> t.chunk_syms >> t.waves_per_group >> t.groups_per_cu >> t.table_layout >>
-                t.encode_gbps >> t.decode_gbps >> t.use_graph &&
+                t.encode_gbps >> t.decode_gbps >> t.use_graph >> t.interleave >> t.lanes_per_stream >>
+                t.chunks_per_wave &&
             k == key) {
             *r = t;
             return true;
@@ -80,7 +82,8 @@ void cache_store(const char* path, const std::string& key, const rans_tune_resul
         return;
     std::ofstream out(path, std::ios::app);
     out << key << ' ' << r.chunk_syms << ' ' << r.waves_per_group << ' ' << r.groups_per_cu << ' '
-        << r.table_layout << ' ' << r.encode_gbps << ' ' << r.decode_gbps << ' ' << r.use_graph << '\n';
+        << r.table_layout << ' ' << r.encode_gbps << ' ' << r.decode_gbps << ' ' << r.use_graph << ' '
+        << r.interleave << ' ' << r.lanes_per_stream << ' ' << r.chunks_per_wave << '\n';
 }
 
 // Median time (ms) of `reps` runs of fn() on stream st.
@@ -130,7 +133,8 @@ int tune(const std::vector<Sample>& smp, const rans_params& p, const std::string
     if (!st && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
         return RANS_EDEVICE;
     rans_params small = p;
-    small.chunk_syms = 4096;  // the smallest candidate bounds every container
+    small.chunk_syms = 4096;  // the smallest candidate with 64 coders bounds every container
+    small.interleave = 64;
     std::vector<uint64_t> cap(nj), coff(nj), doff(nj);
     uint64_t ctot = 0, dtot = 0, total = 0;
     for (uint32_t j = 0; j < nj; ++j) {
@@ -170,11 +174,19 @@ int tune(const std::vector<Sample>& smp, const rans_params& p, const std::string
     double best_score = 1e30, ref_bytes = 0;
     rans_tune_result best{};
     const uint32_t chunk_sizes[] = {65536, 32768, 16384, 8192, 4096};
+    // the caller's interleave factor, or both when it leaves it open (0)
+    std::vector<uint32_t> interleaves;
+    if (p.interleave)
+        interleaves.push_back(p.interleave);
+    else
+        interleaves = {64, 32};
+    for (uint32_t N : interleaves)
     for (uint32_t C : chunk_sizes) {
         if ((uint64_t(C) * w) % 16 != 0)
             continue;
         rans_params pc = p;
         pc.chunk_syms = C;
+        pc.interleave = static_cast<uint16_t>(N);
         int e = RANS_OK;
         const double enc_ms = time_ms(st, 5, [&] {
             return run_batch(ej.data(), nj, &pc, st, false, &base_cfg);
@@ -187,7 +199,7 @@ int tune(const std::vector<Sample>& smp, const rans_params& p, const std::string
             bytes += double(clen[j]);
         }
         if (ref_bytes == 0)
-            ref_bytes = bytes;
+            ref_bytes = bytes;  // the first candidate: the largest chunks (and N = 64 when open)
         // decode shapes for these containers
         for (uint32_t G : {16u, 8u, 4u}) {
             for (uint32_t gpc : {1u, 2u, 4u}) {
@@ -205,6 +217,9 @@ int tune(const std::vector<Sample>& smp, const rans_params& p, const std::string
                     if (score < best_score) {
                         best_score = score;
                         best.chunk_syms = C;
+                        best.interleave = N;
+                        best.lanes_per_stream = N;
+                        best.chunks_per_wave = 64 / N;
                         best.waves_per_group = G;
                         best.groups_per_cu = gpc;
                         best.table_layout = lay;
@@ -221,6 +236,7 @@ int tune(const std::vector<Sample>& smp, const rans_params& p, const std::string
     {
         rans_params pc = p;
         pc.chunk_syms = best.chunk_syms;
+        pc.interleave = static_cast<uint16_t>(best.interleave);
         double t[2] = {0, 0};
         for (uint32_t g = 0; g < 2; ++g) {
             rans_batch_config cfg{best.waves_per_group, best.groups_per_cu, best.table_layout, g};
@@ -254,11 +270,15 @@ extern "C" int rans_autotune(const rans_table* table, const void* d_syms, uint64
     if (!table || !base || !out || (n_syms && !d_syms) || (reinterpret_cast<uintptr_t>(d_syms) & 15))
         return RANS_EINVAL;
     rans_params p = *base;
+    if (p.interleave != 0 && p.interleave != 32 && p.interleave != 64)
+        return RANS_EINVAL;
+    const uint16_t n_fixed = p.interleave;  // 0: searched over 32 and 64
     p.interleave = 64;
     p.chunk_syms = 65536;
     int rc = check_params(&p);
     if (rc != RANS_OK)
         return rc;
+    p.interleave = n_fixed;
     const DevTable* t = dev_table(table);
     if (t->k != p.prob_bits)
         return RANS_EINVAL;
@@ -278,11 +298,15 @@ extern "C" int rans_autotune_batch(const rans_job* jobs, uint32_t njobs, const r
     if (!jobs || njobs == 0 || !base || !out)
         return RANS_EINVAL;
     rans_params p = *base;
+    if (p.interleave != 0 && p.interleave != 32 && p.interleave != 64)
+        return RANS_EINVAL;
+    const uint16_t n_fixed = p.interleave;  // 0: searched over 32 and 64
     p.interleave = 64;
     p.chunk_syms = 65536;
     int rc = check_params(&p);
     if (rc != RANS_OK)
         return rc;
+    p.interleave = n_fixed;
     std::vector<Sample> smp;
     uint64_t total = 0;
     uint32_t alpha = 0;

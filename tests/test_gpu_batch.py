@@ -270,9 +270,11 @@ def test_autotune_result_is_valid_applied_and_cached(lr, tmp_path):
     table = lr.rans_tables_build(datagen.counts(s, 256), k)
     d = torch.from_numpy(s).cuda()
     cache = str(tmp_path / "tune.txt")
-    base = lr.rans_params.make(k, r, l, 1, 64, 65536)
+    base = lr.rans_params.make(k, r, l, 1, 64, 65536)  # N fixed at 64
     res = lr.rans_autotune(table, d, s.size, base, cache)
     assert res["chunk_syms"] in (65536, 32768, 16384, 8192, 4096)
+    N = res["interleave"]
+    assert N == 64 and res["lanes_per_stream"] == N and res["chunks_per_wave"] == 1
     assert res["waves_per_group"] in (16, 8, 4) and res["groups_per_cu"] in (1, 2, 4)
     assert res["table_layout"] in (1, 2, 3) and res["use_graph"] in (0, 1)
     assert res["encode_gbps"] > 0 and res["decode_gbps"] > 0
@@ -286,11 +288,11 @@ def test_autotune_result_is_valid_applied_and_cached(lr, tmp_path):
     assert again["chunk_syms"] == res["chunk_syms"] and len(open(cache).read().splitlines()) == 1
     # the tuned shape codes bit-exactly
     C = res["chunk_syms"]
-    tables, outs, st, _ = run_encode_batch(lr, [(s, None)], k, r, l, C)
+    tables, outs, st, _ = run_encode_batch(lr, [(s, None)], k, r, l, C, N=N)
     assert (st == 0).all()
-    ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+    ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, N, C)
     assert outs[0].size == ref.size and (outs[0] == ref).all()
-    dec, st2, _ = run_decode_batch(lr, tables, outs, [s.size], k, r, l)
+    dec, st2, _ = run_decode_batch(lr, tables, outs, [s.size], k, r, l, N=N)
     assert (st2 == 0).all() and (dec[0] == s).all()
     lr.rans_batch_set_config(16, 1, 0, 1)
 
@@ -310,9 +312,11 @@ def test_batch_autotune_on_the_batch(lr, tmp_path):
         ins.append(a)
     jobs = lr.make_jobs((tables[i], ins[i], data[i][0].size, 0, 0, 0, 0) for i in range(len(data)))
     cache = str(tmp_path / "tune.txt")
-    base = lr.rans_params.make(k, r, l, 1, 64, 65536)
+    base = lr.rans_params.make(k, r, l, 1, 0, 65536)  # N searched over 32 and 64
     res = lr.rans_autotune_batch(jobs, len(data), base, cache)
     assert res["chunk_syms"] in (65536, 32768, 16384, 8192, 4096)
+    N = res["interleave"]
+    assert N in (32, 64) and res["lanes_per_stream"] == N and res["chunks_per_wave"] == 64 // N
     assert res["waves_per_group"] in (16, 8, 4) and res["groups_per_cu"] in (1, 2, 4)
     assert res["table_layout"] in (1, 2, 3) and res["decode_gbps"] > 0
     cfg = lr.rans_batch_get_config()
@@ -323,12 +327,12 @@ def test_batch_autotune_on_the_batch(lr, tmp_path):
     assert again["chunk_syms"] == res["chunk_syms"] and len(open(cache).read().splitlines()) == 1
     try:
         C = res["chunk_syms"]
-        tabs, outs, st, _ = run_encode_batch(lr, data, k, r, l, C)
+        tabs, outs, st, _ = run_encode_batch(lr, data, k, r, l, C, N=N)
         assert (st == 0).all()
         for i, (s, _) in enumerate(data):
-            ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C)
+            ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, N, C)
             assert (outs[i] == ref).all(), i
-        dec, st2, _ = run_decode_batch(lr, tabs, outs, [s.size for s, _ in data], k, r, l)
+        dec, st2, _ = run_decode_batch(lr, tabs, outs, [s.size for s, _ in data], k, r, l, N=N)
         assert (st2 == 0).all() and all((dec[i] == s).all() for i, (s, _) in enumerate(data))
     finally:
         lr.rans_batch_set_config(16, 1, 0, 1)
