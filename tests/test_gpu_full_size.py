@@ -2,10 +2,11 @@
 
 The containers the GPU writes are compared byte for byte with the oracle's
 and the GPU decodes the oracle's containers back to the input: the 1 MiB
-four-coder stream in one chunk, the three 256 MiB Zipf buffers, points of the
-64 MiB radix/precision sweep (plain and batched paths), uneven streams from
-the batched workload's generator in one batched launch, and serving requests
-drawn from the serving workload's size distribution.
+four-coder stream in one chunk, the three 256 MiB Zipf buffers, every one of
+the 84 feasible 64 MiB points of the radix/precision sweep (batched and
+plain paths, in the configuration the benchmark times), the 4096 uneven
+streams of the batched workload in one batched launch each way, and the
+1000 requests of the serving workload through one server.
 """
 import numpy as np
 import pytest
@@ -52,67 +53,163 @@ def test_256MiB_zipf(lr, s):
     check_roundtrip(lr, w.syms, 256, k, r, l, N, C)
 
 
-# sweep points (alphabet, distribution, k, (r, l), N), at 64 MiB of symbol
-# bytes, with 16 KiB chunks
-SWEEP = [(2, "dominant", 11, (8, 23), 64), (16, "zipf1.1", 15, (16, 16), 32),
-         (256, "near_uniform", 11, (16, 16), 64), (256, "zipf1.1", 15, (8, 23), 32),
-         (4096, "dominant", 15, (16, 16), 64), (4096, "near_uniform", 15, (8, 23), 64)]
+def tuned(lr, tmp_path, jobs, njobs, base):
+    """The autotuner's choice for these jobs from the tuning results that ship
+    with the library (the configuration bench.py times); a copy of the cache
+    is used, so a miss tunes without touching the shipped file."""
+    import os
+    import shutil
+    src = os.path.join(os.path.dirname(lr.__file__), "tune_mi355x.txt")
+    cache = str(tmp_path / "tune.txt")
+    if os.path.exists(src):
+        shutil.copy(src, cache)
+    return lr.rans_autotune_batch(jobs, njobs, base, cache)
 
 
-@pytest.mark.parametrize("pt", SWEEP, ids=[f"a{p[0]}-{p[1]}-k{p[2]}-r{p[3][0]}-N{p[4]}" for p in SWEEP])
-def test_sweep_point_64MiB_plain_and_batched(lr, pt):
+def sweep_groups():
+    groups = {}
+    for p in datagen.sweep_points():
+        if p["feasible"]:
+            groups.setdefault((p["k"], p["r"], p["l"], p["w"], p["N"]), []).append(p)
+    return sorted(groups.items())
+
+
+SWEEP_GROUPS = sweep_groups()
+
+
+@pytest.mark.parametrize("group", SWEEP_GROUPS, ids=[f"k{g[0][0]}-r{g[0][1]}-w{g[0][3]}-N{g[0][4]}"
+                                                     for g in SWEEP_GROUPS])
+def test_sweep_group_64MiB_every_point(lr, group, tmp_path):
+    """Every feasible point of the radix/precision sweep (84 in 12 groups
+    sharing k, r, l, w, N; 64 MiB of symbol bytes each, its own table), in
+    the configuration bench.py times: one batched encode of the group at the
+    tuned chunk size and launch shape writes the oracle's containers byte for
+    byte; the plain encoder writes them too; the plain decoder and one
+    batched decode of the group return every input from the oracle's
+    containers."""
     import torch
-    alphabet, dist, k, (r, l), N = pt
-    syms = datagen.sweep_data(alphabet, dist)[0]
-    w = syms.dtype.itemsize
-    C = 16384 // w
-    table, ref = check_roundtrip(lr, syms, alphabet, k, r, l, N, C)
-    # the batched persistent kernel decodes the same container
-    params = lr.rans_params.make(k, r, l, w, N, 0)
-    d_in = torch.from_numpy(ref).cuda()
-    out = torch.zeros(syms.size * w, dtype=torch.uint8, device="cuda")
-    lens = torch.zeros(1, dtype=torch.int64, device="cuda")
-    st = torch.full((1,), 99, dtype=torch.int32, device="cuda")
-    jobs = lr.make_jobs([(table, d_in, ref.size, out, syms.size * w, int(lens.data_ptr()),
-                          int(st.data_ptr()))])
-    lr.rans_decode_batch(jobs, 1, params)
+    from rans_util import dev
+    (k, r, l, w, N), pts = group
+    data = [datagen.sweep_data(p["alphabet"], p["dist"])[0] for p in pts]
+    counts = [datagen.counts(x, p["alphabet"]) for p, x in zip(pts, data)]
+    tables = [lr.rans_tables_build(c, k) for c in counts]
+    d_in = [dev(x) for x in data]
+    sizes = [x.nbytes for x in data]
+    jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], 0, 0, 0, 0) for i in range(len(pts)))
+    tune = tuned(lr, tmp_path, jobs, len(pts), lr.rans_params.make(k, r, l, w, N, 65536 // w))
+    C = int(tune["chunk_syms"])
+    assert int(tune["interleave"]) == N
+    print(f"[sweep-group] k={k} r={r} w={w} N={N} C={C} shape={tune['waves_per_group']},"
+          f"{tune['groups_per_cu']},{tune['table_layout']}", flush=True)
+    params = lr.rans_params.make(k, r, l, w, N, C)
+    refs = [oracle.encode(oracle.quantize(c, k), x, k, r, l, N, C, threads=THREADS)
+            for c, x in zip(counts, data)]
+    caps = [lr.rans_encode_bound(x.size, params) for x in data]
+    d_cont = [torch.full((cap,), 0xA5, dtype=torch.uint8, device="cuda") for cap in caps]
+    lens = torch.zeros(len(pts), dtype=torch.int64, device="cuda")
+    st = torch.full((len(pts),), 99, dtype=torch.int32, device="cuda")
+    enc = lr.make_jobs((tables[i], d_in[i], sizes[i], d_cont[i], caps[i], int(lens.data_ptr()) + 8 * i,
+                        int(st.data_ptr()) + 4 * i) for i in range(len(pts)))
+    lr.rans_encode_batch(enc, len(pts), params)
     torch.cuda.synchronize()
-    assert int(st[0]) == 0 and int(lens[0]) == syms.size
-    assert (out.cpu().numpy().view(syms.dtype) == syms).all()
+    assert (st.cpu().numpy() == 0).all(), st.tolist()
+    for i, ref in enumerate(refs):
+        got = d_cont[i][: int(lens[i])].cpu().numpy()
+        assert got.size == ref.size and (got == ref).all(), (i, first_diff(got, ref))
+        plain = gpu_encode(lr, tables[i], (k, r, l, w, N, C), data[i])
+        assert plain.size == ref.size and (plain == ref).all(), (i, "plain", first_diff(plain, ref))
+        dec = gpu_decode(lr, tables[i], ref, data[i].size, w)
+        assert (dec.view(data[i].dtype) == data[i]).all(), (i, "plain decode")
+    # one batched decode of the oracle's containers
+    d_ref = [dev(ref) for ref in refs]
+    d_out = [torch.zeros(n, dtype=torch.uint8, device="cuda") for n in sizes]
+    st.fill_(99)
+    dj = lr.make_jobs((tables[i], d_ref[i], refs[i].size, d_out[i], sizes[i], int(lens.data_ptr()) + 8 * i,
+                       int(st.data_ptr()) + 4 * i) for i in range(len(pts)))
+    lr.rans_decode_batch(dj, len(pts), params)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all(), st.tolist()
+    for i, x in enumerate(data):
+        assert int(lens[i]) == x.size
+        assert (d_out[i].cpu().numpy().view(x.dtype) == x).all(), (i, "batched decode")
 
 
-def test_uneven_streams_one_batched_launch(lr):
-    """192 streams from the batched workload's generator (1 KiB .. 4 MiB,
-    Dirichlet tables), encoded and decoded in one batched call each."""
+def test_4096_uneven_streams_one_batched_launch(lr, tmp_path):
+    """The batched workload at full size: 4096 streams of 2^U(10,22) bytes
+    (about 2 GiB) with Dirichlet tables, at the tuned interleave factor, chunk
+    size and launch shape (as bench.py times them): one batched encode writes
+    every stream's oracle container byte for byte, one batched decode of the
+    oracle's containers returns every stream."""
     import torch
-    from test_gpu_batch import run_decode_batch, run_encode_batch
-    data = datagen.dirichlet_streams(nstreams=192, seed=4001)
-    k, r, l, C = 14, 16, 16, 8192
-    tables, outs, st, lens = run_encode_batch(lr, data, k, r, l, C)
-    assert (st == 0).all()
-    for i, (s, _) in enumerate(data):
-        ref = oracle.encode(oracle.quantize(datagen.counts(s, 256), k), s, k, r, l, 64, C,
-                            threads=THREADS)
-        assert outs[i].size == ref.size and (outs[i] == ref).all(), (i, first_diff(outs[i], ref))
-    dec, st2, n2 = run_decode_batch(lr, tables, outs, [s.size for s, _ in data], k, r, l)
-    assert (st2 == 0).all()
-    for i, (s, _) in enumerate(data):
-        assert n2[i] == s.size and (dec[i] == s).all(), i
+    from test_gpu_batch import Pool
+    k, r, l = 14, 16, 16
+    data = datagen.dirichlet_streams(nstreams=4096, seed=4001)
+    sizes = [s.size for s, _ in data]
+    # containers of any tuned shape fit the 64-coder, 4096-symbol-chunk bound
+    bound = sum(lr.rans_encode_bound(n, lr.rans_params.make(k, r, l, 1, 64, 4096)) for n in sizes)
+    pool = Pool(2 * sum(sizes) + 2 * bound + 4 * 256 * len(data))
+    tables = [lr.rans_tables_build(datagen.counts(s, 256), k) for s, _ in data]
+    d_in = []
+    for s, _ in data:
+        a = pool.take(s.size)
+        pool.put(a, s)
+        d_in.append(a)
+    jobs = lr.make_jobs((tables[i], d_in[i], sizes[i], 0, 0, 0, 0) for i in range(len(data)))
+    tune = tuned(lr, tmp_path, jobs, len(data), lr.rans_params.make(k, r, l, 1, 0, 65536))
+    N, C = int(tune["interleave"]), int(tune["chunk_syms"])
+    print(f"[4096-streams] N={N} C={C}", flush=True)
+    params = lr.rans_params.make(k, r, l, 1, N, C)
+    caps = [lr.rans_encode_bound(n, params) for n in sizes]
+    d_cont = [pool.take(c) for c in caps]
+    lens = torch.zeros(len(data), dtype=torch.int64, device="cuda")
+    st = torch.full((len(data),), 99, dtype=torch.int32, device="cuda")
+    enc = lr.make_jobs((tables[i], d_in[i], sizes[i], d_cont[i], caps[i], int(lens.data_ptr()) + 8 * i,
+                        int(st.data_ptr()) + 4 * i) for i in range(len(data)))
+    lr.rans_encode_batch(enc, len(data), params)
     torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    clen = lens.cpu().numpy()
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(THREADS) as ex:  # one oracle call per stream, streams in parallel
+        refs = list(ex.map(lambda sp: oracle.encode(oracle.quantize(datagen.counts(sp[0], 256), k), sp[0],
+                                                    k, r, l, N, C), data))
+    for i, ref in enumerate(refs):
+        got = pool.get(d_cont[i], int(clen[i]))
+        assert got.size == ref.size and (got == ref).all(), (i, first_diff(got, ref))
+    d_ref, d_out = [], []
+    for ref, n in zip(refs, sizes):
+        a = pool.take(ref.size)
+        pool.put(a, ref)
+        d_ref.append(a)
+        d_out.append(pool.take(n))
+    st.fill_(99)
+    dj = lr.make_jobs((tables[i], d_ref[i], refs[i].size, d_out[i], sizes[i], int(lens.data_ptr()) + 8 * i,
+                       int(st.data_ptr()) + 4 * i) for i in range(len(data)))
+    lr.rans_decode_batch(dj, len(data), params)
+    torch.cuda.synchronize()
+    assert (st.cpu().numpy() == 0).all()
+    n2 = lens.cpu().numpy()
+    for i, (s, _) in enumerate(data):
+        assert n2[i] == s.size and (pool.get(d_out[i], s.size) == s).all(), i
 
 
-def test_serving_requests_at_full_size_range(lr):
-    """40 requests from the serving workload's distribution (4 KiB .. 64 MiB),
-    replayed with Poisson arrivals under the 8 GiB budget: every encode result
-    equals the oracle's container, every decode result the input."""
+def test_serving_1000_requests_full_size_range(lr):
+    """The serving workload at full size, as bench.py runs it: 1000 requests
+    of 2^U(12,26) bytes (encode/decode 50/50, Zipf tables; about 6.8 GiB),
+    one server with the 8 GiB budget, 4 streams and up to 64 requests per
+    launch.  All requests arrive at once; each output is checked as soon as it
+    completes (every encode result is the oracle's container, every decode
+    result the input) and released, so requests keep being admitted as
+    memory frees up.  The server's counters show launches of several
+    requests and several streams busy at once, and the budget held.  Then the
+    same requests under Poisson arrivals complete with the oracle's lengths."""
     import torch
     from test_gpu_serve import device_bytes
     K, R, L, W, N, C = 14, 16, 16, 1, 64, 65536
     params = lr.rans_params.make(K, R, L, W, N, C)
-    reqs = datagen.serving_requests(nreq=40, seed=5201)
+    reqs = datagen.serving_requests(nreq=1000, seed=5001)
     staged, want = [], []
-    for q in reqs:
-        syms = datagen.request_data(q, seed=5201)
+    for q, syms in zip(reqs, datagen.requests_data(reqs, seed=5001)):
         counts = datagen.counts(syms, 256)
         table = lr.rans_tables_build(counts, K)
         ref = oracle.encode(oracle.quantize(counts, K), syms, K, R, L, N, C, threads=THREADS)
@@ -124,17 +221,30 @@ def test_serving_requests_at_full_size_range(lr):
             d = torch.from_numpy(ref).cuda()
             staged.append((lr.RANS_OP_DECODE, table, d, ref.size, syms.size))
             want.append(syms)
-    rng = np.random.Generator(np.random.PCG64(11))
-    arrivals = np.cumsum(rng.exponential(200.0, len(staged)))
+    print(f"[serving] {len(staged)} requests staged", flush=True)
     srv = lr.rans_server_create(8 << 30, 4, 64, params)
     try:
-        res, _ = lr.rans_server_replay(srv, [s + (float(t),) for s, t in zip(staged, arrivals)],
-                                       keep_outputs=True)
+        ids = {}
+        for i, (op, table, d, inl, cap) in enumerate(staged):
+            ids[lr.rans_server_submit(srv, op, table, d, inl, cap)] = i
+        done = 0
+        while done < len(staged):
+            for c in lr.rans_server_poll(srv, keep_outputs=True, max_out=64):
+                i = ids[c.id]
+                assert c.status == 0 and c.out_len == want[i].size, (i, c.status)
+                assert (device_bytes(c.d_out, c.out_len) == want[i]).all(), i
+                lr.rans_server_release(srv, c.id)
+                done += 1
+        st = lr.rans_server_stats(srv)
+        print(f"[serving] {st}", flush=True)
+        assert st["peak"] <= st["budget"] and st["used"] == st["fixed"]
+        assert st["max_launch_requests"] > 1 and st["multi_request_launches"] > 0
+        assert st["peak_busy_streams"] > 1
+        rng = np.random.Generator(np.random.PCG64(11))
+        arrivals = np.cumsum(rng.exponential(5.0, len(staged)))
+        res, _ = lr.rans_server_replay(srv, [s + (float(t),) for s, t in zip(staged, arrivals)])
         for c, ref in zip(res, want):
             assert c.status == 0 and c.out_len == ref.size
-            got = device_bytes(c.d_out, c.out_len)
-            assert (got == ref).all()
-            lr.rans_server_release(srv, c.id)
     finally:
         lr.rans_server_destroy(srv)
 
