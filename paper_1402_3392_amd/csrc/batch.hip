@@ -12,7 +12,7 @@
 // every chunk a wave waits on belongs to a block that is already running,
 // and the copy overlaps the coding of other items.  Every block leaves when
 // the counter passes the last item.
-#include "decode_seg.h"
+#include "encode_seg.h"
 
 namespace rans {
 namespace {
@@ -271,6 +271,46 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
             cur = j;
         }
         const uint32_t nch = c64::uni(jb.nch);
+        if constexpr (NL == 32) {
+            // two chunks per wave: lanes 0-31 code chunk c, lanes 32-63 chunk c + 1
+            const uint32_t c = c64::uni(((item - jb.item_base) * a.G + wave) * 2);
+            if (c < nch) {
+                uint8_t* s0 = reinterpret_cast<uint8_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.slots))) +
+                              uint64_t(c) * a.slot_stride;
+                uint8_t* s1 = s0 + a.slot_stride;
+                uint32_t x = 0, nd[2];
+                c64::encode_seg<R, W, BF>(jb.in, jb.n, c64::uni(jb.C), c, nch, a.l, jb.alphabet,
+                                          reinterpret_cast<const uint4*>(lds), s0, s1, a.slot_bytes, sbuf,
+                                          jb.d_status, &x, nd);
+                PlaceArgs pa;
+                pa.ticket = nullptr;
+                pa.lookback = reinterpret_cast<uint64_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.lookback)));
+                pa.out = jb.out;
+                pa.out_cap = jb.out_cap;
+                pa.total = &jb.total;
+                pa.total_out = jb.d_out_len;
+                uint32_t h[8];
+                job_header(a, jb, nch, h);
+                for (int q = 0; q < 8; ++q)
+                    reinterpret_cast<uint32_t*>(pa.hdr)[q] = h[q];
+                const uint32_t nd0 = c64::uni(nd[0]), nd1 = c64::uni(nd[1]);
+                const uint32_t x1 =
+                    static_cast<uint32_t>(__shfl(static_cast<int>(x), static_cast<int>((threadIdx.x & 63) | 32)));
+                const bool two = c + 1 < nch;
+                c64::publish_chunk<R, 32>(c, nd0, pa);
+                if (two)
+                    c64::publish_chunk<R, 32>(c + 1, nd1, pa);
+                bool t0 = false, t1 = false;
+                const uint64_t l0 = c64::chunk_local<R, 32>(c, nch, nd0, pa, t0);
+                const uint64_t l1 = two ? c64::chunk_local<R, 32>(c + 1, nch, nd1, pa, t1) : 0;
+                c64::place_chunk<R, 32>(c, nch, x, nd0, s0 + a.slot_bytes - uint64_t(nd0) * (R / 8), pa,
+                                        jb.d_status, true, l0, t0);
+                if (two)
+                    c64::place_chunk<R, 32>(c + 1, nch, x1, nd1, s1 + a.slot_bytes - uint64_t(nd1) * (R / 8), pa,
+                                            jb.d_status, true, l1, t1);
+            }
+            continue;
+        }
         const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
         if (c < nch) {
             // the job's own slots (the host sized them for its nch chunks)

@@ -32,8 +32,9 @@ int num_cus()
 
 uint32_t batch_chunks_per_item(const rans_params& p, bool decode, uint32_t G)
 {
-    // a decoding wave codes 64 / N chunks, an encoding wave one
-    return decode ? G * (64u / p.interleave) : G;
+    // a wave codes 64 / N chunks (two with 32 coders per chunk)
+    (void)decode;
+    return G * (64u / p.interleave);
 }
 
 uint64_t batch_item_bound(const rans_job& jb, const rans_params& p, bool decode, uint32_t G)

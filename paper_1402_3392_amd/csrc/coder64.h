@@ -1000,23 +1000,53 @@ __device__ __forceinline__ void encode_chunk_pfx(const void* syms_base, uint64_t
 // waits end; they are bounded anyway, and a timeout reports RANS_EINVAL and
 // writes nothing.  p.lookback holds nch chunk words, then the group words,
 // all zero before the kernel.
+// Publishes chunk `chunk`'s aligned length (nd digits) for the look-back of
+// the chunks above it.
+template <int R, int NL>
+__device__ __forceinline__ void publish_chunk(uint32_t chunk, uint32_t nd, const PlaceArgs& p)
+{
+    const uint64_t al = (uint64_t(4 * NL + nd * (R / 8)) + 15) & ~15ull;
+    if ((threadIdx.x & 63) == 0)
+        __hip_atomic_store(&p.lookback[chunk], kFlag | al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The sum of the aligned lengths of the chunks below `chunk` in its group
+// of 64 (awaited); the group's last chunk also publishes the group total.
+template <int R, int NL>
+__device__ __forceinline__ uint64_t chunk_local(uint32_t chunk, uint32_t nch, uint32_t nd, const PlaceArgs& p,
+                                                bool& timeout)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t al = (uint64_t(4 * NL + nd * (R / 8)) + 15) & ~15ull;
+    const uint32_t g = chunk >> 6, g0 = chunk & ~63u;
+    const uint64_t local = wave_sum(g0 + lane < chunk ? await_word(&p.lookback[g0 + lane], timeout) : 0);
+    if ((chunk & 63) == 63 && lane == 0)
+        __hip_atomic_store(&p.lookback[nch + g], kFlag | (local + al), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return local;
+}
+
+// Places a chunk: publish its length, sum its predecessors' (its group's,
+// then the earlier groups' totals), write its directory entry, states and
+// digits.  pre: a wave that codes two chunks publishes both lengths and
+// takes both group sums (local, timeout) before placing either, so that no
+// chunk above them, in this group or a later one, waits on its copies.
 template <int R, int NL>
 __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32_t x, uint32_t nd,
-                                            const uint8_t* src, const PlaceArgs& p, int32_t* status)
+                                            const uint8_t* src, const PlaceArgs& p, int32_t* status,
+                                            bool pre = false, uint64_t pre_local = 0, bool pre_timeout = false)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t pay = nd * (R / 8);
     const uint32_t len = 4 * NL + pay;
     const uint64_t al = (uint64_t(len) + 15) & ~15ull;
-    uint64_t* agg = p.lookback;
     uint64_t* grp = p.lookback + nch;
-    if (lane == 0)
-        __hip_atomic_store(&agg[chunk], kFlag | al, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool timeout = false;
-    const uint32_t g = chunk >> 6, g0 = chunk & ~63u;
-    const uint64_t local = wave_sum(g0 + lane < chunk ? await_word(&agg[g0 + lane], timeout) : 0);
-    if ((chunk & 63) == 63 && lane == 0)
-        __hip_atomic_store(&grp[g], kFlag | (local + al), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool timeout = pre_timeout;
+    uint64_t local = pre_local;
+    if (!pre) {
+        publish_chunk<R, NL>(chunk, nd, p);
+        local = chunk_local<R, NL>(chunk, nch, nd, p, timeout);
+    }
+    const uint32_t g = chunk >> 6;
     uint64_t before = 0;
     for (uint32_t b = 0; b < g; b += 64)
         before += wave_sum(b + lane < g ? await_word(&grp[b + lane], timeout) : 0);

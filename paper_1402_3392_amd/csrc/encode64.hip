@@ -2,7 +2,7 @@
 // per chunk, encoder entries staged in LDS once per block; the chunk coder is
 // c64::encode_chunk and the chunk is placed into the container in the same
 // kernel by c64::place_chunk.
-#include "coder64.h"
+#include "encode_seg.h"
 
 namespace rans {
 namespace {
@@ -20,6 +20,34 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
     uint32_t t = 0;
     if ((threadIdx.x & 63) == 0)
         t = atomicAdd(p.ticket, 1u);
+    if constexpr (NL == 32 && !ESC) {
+        // two chunks per wave: lanes 0-31 code chunk 2t, lanes 32-63 chunk 2t + 1
+        const uint32_t chunk = 2 * c64::uni(t);
+        if (chunk >= a.n_chunks)
+            return;
+        uint8_t* s0 = a.slots + uint64_t(chunk) * a.slot_stride;
+        uint8_t* s1 = s0 + a.slot_stride;
+        uint32_t x = 0, nd[2];
+        c64::encode_seg<R, W, BF>(a.syms, a.n, a.C, chunk, a.n_chunks, a.l, a.alphabet,
+                                  reinterpret_cast<const uint4*>(lds), s0, s1, a.slot_bytes,
+                                  lds + tab + wave * c64::kEncWaveLds, a.status, &x, nd);
+        // the lower chunk first: the upper one's look-back waits on it
+        const uint32_t nd0 = c64::uni(nd[0]), nd1 = c64::uni(nd[1]);
+        const uint32_t x1 = static_cast<uint32_t>(__shfl(static_cast<int>(x), static_cast<int>((threadIdx.x & 63) | 32)));
+        const bool two = chunk + 1 < a.n_chunks;
+        c64::publish_chunk<R, 32>(chunk, nd0, p);
+        if (two)
+            c64::publish_chunk<R, 32>(chunk + 1, nd1, p);
+        bool t0 = false, t1 = false;
+        const uint64_t l0 = c64::chunk_local<R, 32>(chunk, a.n_chunks, nd0, p, t0);
+        const uint64_t l1 = two ? c64::chunk_local<R, 32>(chunk + 1, a.n_chunks, nd1, p, t1) : 0;
+        c64::place_chunk<R, 32>(chunk, a.n_chunks, x, nd0, s0 + a.slot_bytes - uint64_t(nd0) * (R / 8), p,
+                                a.status, true, l0, t0);
+        if (two)
+            c64::place_chunk<R, 32>(chunk + 1, a.n_chunks, x1, nd1, s1 + a.slot_bytes - uint64_t(nd1) * (R / 8),
+                                    p, a.status, true, l1, t1);
+        return;
+    }
     const uint32_t chunk = c64::uni(t);
     if (chunk >= a.n_chunks)
         return;
@@ -38,8 +66,10 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
 template <int R, int W, int NL, bool BF, bool ESC = false>
 hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 {
-    const uint32_t wpb = a.n_chunks < 16 ? a.n_chunks : 16;
-    const uint32_t blocks = (a.n_chunks + wpb - 1) / wpb;
+    const uint32_t per = NL == 32 && !ESC ? 2 : 1;  // chunks per wave
+    const uint32_t waves = (a.n_chunks + per - 1) / per;
+    const uint32_t wpb = waves < 16 ? waves : 16;
+    const uint32_t blocks = (waves + wpb - 1) / wpb;
     const uint32_t lds = enc_lds_bytes(a.enc_bytes, W) + wpb * c64::kEncWaveLds;
     auto kern = k_encode64_place<R, W, NL, BF, ESC>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
