@@ -97,6 +97,47 @@ __device__ __forceinline__ uint32_t select_mask(uint64_t m, uint32_t a, uint32_t
     return r;
 }
 
+// The same address as a pointer into global memory.  Accesses through it are
+// global_* instructions, which count in vmcnt only and complete in issue
+// order, so the compiler waits for exactly the load it needs.  Through a
+// generic pointer (one read from a job descriptor, say) they are flat_*
+// instructions, which also count in lgkmcnt and may target LDS: the
+// compiler then waits for every outstanding memory operation, loads just
+// issued ahead and stores included, before an LDS result or a prefetched
+// register is used.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// 8- and 16-byte global stores and a 16-byte global load (the HIP vector
+// classes have no assignment across address spaces)
+__device__ __forceinline__ void gstore(void* p, const uint4& v)
+{
+    v4u t;
+    t.x = v.x;
+    t.y = v.y;
+    t.z = v.z;
+    t.w = v.w;
+    *gmem(static_cast<v4u*>(p)) = t;
+}
+__device__ __forceinline__ void gstore(void* p, const uint2& v)
+{
+    v2u t;
+    t.x = v.x;
+    t.y = v.y;
+    *gmem(static_cast<v2u*>(p)) = t;
+}
+__device__ __forceinline__ uint4 gload16(const void* p)
+{
+    const v4u t = *gmem(static_cast<const v4u*>(p));
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+
 // All but the `n` most recent vector-memory operations of this wave have
 // completed (loads and stores complete in issue order).
 template <int n>
@@ -398,7 +439,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         lane_fence();
         const Piece v = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
         lane_fence();
-        *reinterpret_cast<Piece*>(reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL) + PIECE * lane) = v;
+        gstore(reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL) + PIECE * lane, v);
         ++cur;  // one store instruction (more would only make waits longer)
     };
     auto step1 = [&](OutT* dst, auto dense) {
@@ -519,7 +560,7 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         const uint32_t nbytes = (nsym - tb * NL) * OW;  // valid bytes of this block
         uint8_t* dst = reinterpret_cast<uint8_t*>(out + uint64_t(tb) * NL);
         if (PIECE * lane + PIECE <= nbytes) {
-            *reinterpret_cast<Piece*>(dst + PIECE * lane) = *reinterpret_cast<const Piece*>(obuf + PIECE * lane);
+            gstore(dst + PIECE * lane, *reinterpret_cast<const Piece*>(obuf + PIECE * lane));
         } else if (PIECE * lane < nbytes) {
             for (uint32_t b = PIECE * lane; b < nbytes; ++b)
                 dst[b] = obuf[b];
@@ -532,7 +573,6 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
 }
 
 // Four dwords as the compiler's vector type (for the non-temporal builtins).
-typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 // Per-wave LDS of the encoder: a 1 KiB symbol block, a 4 KiB digit ring,
 // then 128 bytes where lanes with nothing to emit write.
@@ -746,7 +786,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
             const uint32_t lo = wtop - (j + 1) * WD;
             uint8_t* dst = j < cnt ? slot + uint64_t(lo) * DB : slot + slot_bytes;
             const uint4 v = ring_word(lo);
-            reinterpret_cast<uint4*>(dst)[lane] = v;
+            gstore(reinterpret_cast<uint4*>(dst) + lane, v);
         }
         lane_fence();
         wtop = wc;
@@ -756,7 +796,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     for (uint32_t t = steps; t-- > nblk * SPB;) {
         const uint64_t i = uint64_t(t) * NL + lane;
         const bool act = live && i < nsym;
-        const uint32_t s = act ? static_cast<uint32_t>(in[i]) : 0u;
+        const uint32_t s = act ? static_cast<uint32_t>(gmem(in)[i]) : 0u;
         if (ESC)
             enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], s, act, dring, lane);
         else
@@ -769,7 +809,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         // marked non-temporal (each symbol is read once)
         const uint4* blk = reinterpret_cast<const uint4*>(in) + lane;
         auto load_blk = [&](int64_t b) {
-            const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(blk + (b < 0 ? 0 : b) * 64));
+            const v4u v = __builtin_nontemporal_load(gmem(reinterpret_cast<const v4u*>(blk + (b < 0 ? 0 : b) * 64)));
             return make_uint4(v.x, v.y, v.z, v.w);
         };
         // The block's symbols are read from LDS up front and each step's
@@ -831,7 +871,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     if (wpos < wtop) {  // the window holding the stream's first digits
         lane_fence();
         const uint4 v = ring_word(wtop - WD);
-        reinterpret_cast<uint4*>(slot + uint64_t(wtop - WD) * DB)[lane] = v;
+        gstore(reinterpret_cast<uint4*>(slot + uint64_t(wtop - WD) * DB) + lane, v);
     }
     if (states_out && live)
         states_out[lane] = x;
@@ -1085,7 +1125,7 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
             t.y = v.y;
             t.z = v.z;
             t.w = v.w;
-            __builtin_nontemporal_store(t, reinterpret_cast<v4u*>(D + q));
+            __builtin_nontemporal_store(t, gmem(reinterpret_cast<v4u*>(D + q)));
         };
         // KU rounds of loads in flight before their stores: one round at a
         // time would wait a full memory latency per KiB
@@ -1095,15 +1135,15 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
             uint4 lo[KU], hi[KU];
 #pragma unroll
             for (uint32_t u = 0; u < KU; ++u) {
-                lo[u] = S[q0 + 64 * u];
-                hi[u] = S[q0 + 64 * u + 1];
+                lo[u] = gload16(S + q0 + 64 * u);
+                hi[u] = gload16(S + q0 + 64 * u + 1);
             }
 #pragma unroll
             for (uint32_t u = 0; u < KU; ++u)
                 piece(q0 + 64 * u, lo[u], hi[u]);
         }
         for (uint32_t q = q0; q < pieces; q += 64)
-            piece(q, S[q], S[q + 1]);
+            piece(q, gload16(S + q), gload16(S + q + 1));
     } else if (lane == 0) {
         atomicMin(status, timeout ? RANS_EINVAL : RANS_ENOSPC);
     }

@@ -344,7 +344,7 @@ __device__ __forceinline__ void decode_seg(const uint8_t* in, uint64_t in_len, u
         const Piece v = *reinterpret_cast<const Piece*>(piece_lds);
         lane_fence();
         if (all || live)
-            *reinterpret_cast<Piece*>(out_lane + uint64_t(tb) * NL * OW) = v;
+            gstore(out_lane + uint64_t(tb) * NL * OW, v);
         ++nops;  // one store instruction (at least one segment is live)
     };
     // a test block of TB steps starting below wend reads at most TB MAXB
@@ -426,7 +426,7 @@ __device__ __forceinline__ void decode_seg(const uint8_t* in, uint64_t in_len, u
         uint8_t* dst = out_lane + uint64_t(tb) * NL * OW;
         if (ballot(mine == PIECE)) {
             if (mine == PIECE)
-                *reinterpret_cast<Piece*>(dst) = *reinterpret_cast<const Piece*>(piece_lds);
+                gstore(dst, *reinterpret_cast<const Piece*>(piece_lds));
             ++nops;
         }
         if (ballot(mine != 0 && mine != PIECE)) {

@@ -28,32 +28,35 @@ static_assert(2 * kSegRing + 1024 + 128 == kEncWaveLds && kSlotAlign % kSegWindo
               "two-segment encoder geometry");
 
 // One encoder step of both segments.  wpos: each segment's lowest digit
-// written so far (it grows downwards); vhi: all ones in the upper segment's
-// lanes; segoff: the lane's ring (0 or kSegRing).  As enc_step, with the
-// prefix count taken over the whole wave and the upper segment's lanes moved
-// to their own position by a per-lane offset (the count also covers the
-// lower segment's emitting lanes, which the offset takes back out).
-template <int R, bool BF>
+// written so far (it grows downwards); amask: the lanes that code a symbol on
+// this step (wave-uniform; every lane when FULL); vhi: all ones in the upper
+// segment's lanes; segoff: the lane's ring (0 or kSegRing).  As enc_step,
+// with the prefix count taken over the whole wave and the upper segment's
+// lanes moved to their own position by a per-lane offset (the count also
+// covers the lower segment's emitting lanes, which the offset takes back
+// out).  Idle lanes keep their state through selects on amask: the ballots
+// are masked with it, so no per-lane predicate is formed and no exec-mask
+// branch splits the unrolled block.
+template <int R, bool BF, bool FULL>
 __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32_t& bad, const uint4& e,
-                                             bool act, uint8_t* dring, uint32_t lane, uint32_t vhi,
+                                             uint64_t amask, uint8_t* dring, uint32_t lane, uint32_t vhi,
                                              uint32_t segoff)
 {
     constexpr uint32_t RB = kSegRing;
-    uint8_t* junk = dring + 2 * kSegRing;
-    bad |= act ? e.w : 0u;
-    const bool e1 = act && x > e.y;
+    const uint64_t am = FULL ? ~0ull : amask;
+    bad |= FULL ? e.w : select_mask(am, 0u, e.w);
     if (R == 16) {
-        const uint64_t m = ballot(e1);
+        const uint64_t m = ballot(x > e.y) & am;
         const uint32_t lo = __popc(static_cast<uint32_t>(m)), hi = __popc(static_cast<uint32_t>(m >> 32));
         wpos[0] -= lo;
         wpos[1] -= hi;
         const uint32_t acc = wpos[0] + and_sv(wpos[1] - wpos[0] - lo, vhi);
         const uint32_t o = select_mask(m, 2 * kSegRing + 2 * lane, ((mbcnt(m, acc) << 1) & (RB - 1)) | segoff);
         *reinterpret_cast<uint16_t*>(dring + o) = static_cast<uint16_t>(x);
-        x = e1 ? x >> 16 : x;
+        x = select_mask(m, x, x >> 16);
     } else {
-        const bool e2 = act && (x >> 8) > e.y;
-        const uint64_t m1 = ballot(e1), m2 = ballot(e2);
+        // a lane that emits two digits also emits one: m2 is within m1
+        const uint64_t m1 = ballot(x > e.y) & am, m2 = ballot((x >> 8) > e.y) & am;
         const uint32_t lo1 = __popc(static_cast<uint32_t>(m1)), hi1 = __popc(static_cast<uint32_t>(m1 >> 32));
         const uint32_t lo2 = __popc(static_cast<uint32_t>(m2)), hi2 = __popc(static_cast<uint32_t>(m2 >> 32));
         wpos[0] -= lo1 + lo2;
@@ -69,13 +72,15 @@ __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32
         }
         const uint32_t o1 = select_mask(m1, 2 * kSegRing + lane, (i1 & (RB - 1)) | segoff);
         const uint32_t o2 = select_mask(m2, 2 * kSegRing + 64 + lane, (i2 & (RB - 1)) | segoff);
-        (void)junk;
-        dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
+        dring[o1] = static_cast<uint8_t>(select_mask(m2, x, x >> 8));
         dring[o2] = static_cast<uint8_t>(x);
-        x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
+        x = select_mask(m2, select_mask(m1, x, x >> 8), x >> 16);
     }
     const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
-    x = act ? c_update(x, q, e.z, e.w) : x;
+    // computed on every lane and selected: C's result through a branch on a
+    // per-lane condition would split the block
+    const uint32_t xn = c_update(x, q, e.z, e.w);
+    x = FULL ? xn : select_mask(am, x, xn);
 }
 
 // Encodes chunks chunk0 and chunk0 + 1 (the second only when it is below
@@ -145,7 +150,7 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
             const uint32_t lo = mytop - (j + 1) * WD;
             uint8_t* dst = j < mycnt ? myslot + uint64_t(lo) * DB : myslot + slot_bytes;
             const uint4 v = ring_word(lo);
-            reinterpret_cast<uint4*>(dst)[jl] = v;
+            gstore(reinterpret_cast<uint4*>(dst) + jl, v);
         }
         lane_fence();
         wtop[0] = wc[0];
@@ -166,15 +171,19 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
     auto load_blk = [&](int64_t b) {
         uint32_t bb = b < 0 ? 0u : static_cast<uint32_t>(b);
         bb = bb > clampb ? clampb : bb;
-        const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(myblk + bb * 32));
+        const v4u v = __builtin_nontemporal_load(gmem(reinterpret_cast<const v4u*>(myblk + bb * 32)));
         return make_uint4(v.x, v.y, v.z, v.w);
     };
     const InT* sb = reinterpret_cast<const InT*>(sbuf + 512 * seg) + jl;
     constexpr int PF = 3;
-    auto run_blk = [&](uint4 v, bool act) {
+    // a block's symbols go to LDS once every read of the previous block's
+    // has been issued (the reads come first in each block)
+    auto stage_blk = [&](const uint4& v) {
         lane_fence();
         *reinterpret_cast<uint4*>(sbuf + 16 * lane) = v;
         lane_fence();
+    };
+    auto run_blk = [&](uint64_t amask, auto full) {
         uint32_t sy[SPB];
 #pragma unroll
         for (int q = 0; q < int(SPB); ++q) {
@@ -191,37 +200,41 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
         for (int q = int(SPB) - 1; q >= 0; --q) {
             if (q - PF >= 0)
                 ent[q - PF] = entry(q - PF);
-            enc_step_seg<R, BF>(x, wpos, bad, ent[q], act, dring, lane, vhi, segoff);
+            enc_step_seg<R, BF, decltype(full)::value>(x, wpos, bad, ent[q], amask, dring, lane, vhi, segoff);
         }
     };
     int64_t b = int64_t(nb) - 1;
-    uint4 cur = make_uint4(0, 0, 0, 0), nxt = cur;
-    if (any_full) {
-        cur = load_blk(b);
-        nxt = load_blk(b - 1);
-    }
+    if (any_full)
+        stage_blk(load_blk(b));
     for (; b >= 0; --b) {
         const uint32_t ub = static_cast<uint32_t>(b);
+        // the next block's symbols load while this one is coded; held in
+        // registers defined and consumed within the iteration, so no copy
+        // at the back edge has to wait for them
+        uint4 nv = make_uint4(0, 0, 0, 0);
+        if (any_full && b > 0)
+            nv = load_blk(b - 1);
         const bool clean0 = ub < nblk[0] || ub * SPB >= steps[0];
         const bool clean1 = ub < nblk[1] || ub * SPB >= steps[1];
         if (clean0 && clean1) {
             // each segment's lanes take part when the block is whole for it
-            const bool act = ub < mynblk;
-            run_blk(cur, act);
+            const uint64_t amask = (ub < nblk[0] ? 0xFFFFFFFFull : 0ull) | (ub < nblk[1] ? ~0xFFFFFFFFull : 0ull);
+            if (amask == ~0ull)
+                run_blk(amask, std::true_type());
+            else
+                run_blk(amask, std::false_type());
         } else {
             for (uint32_t t = (ub + 1) * SPB; t-- > ub * SPB;) {
                 const uint32_t i = t * NL + jl;
                 const bool act = i < mynsym;
-                const uint32_t s = act ? static_cast<uint32_t>(myin[i]) : 0u;
-                enc_step_seg<R, BF>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], act, dring, lane,
-                                    vhi, segoff);
+                const uint32_t s = act ? static_cast<uint32_t>(gmem(myin)[i]) : 0u;
+                enc_step_seg<R, BF, false>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], ballot(act), dring,
+                                           lane, vhi, segoff);
             }
         }
         flush();
-        if (any_full) {
-            cur = nxt;
-            nxt = load_blk(b - 2);
-        }
+        if (any_full && b > 0)
+            stage_blk(nv);
     }
     // the window holding each stream's first digits
     {
@@ -229,7 +242,7 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
         lane_fence();
         const uint4 v = ring_word(mytop - WD);
         if (mypos < mytop)
-            reinterpret_cast<uint4*>(myslot + uint64_t(mytop - WD) * DB)[jl] = v;
+            gstore(reinterpret_cast<uint4*>(myslot + uint64_t(mytop - WD) * DB) + jl, v);
     }
     *x_out = x;
     nd[0] = top - wpos[0];
