@@ -316,16 +316,16 @@ int rans_decode_batch(const rans_job *jobs, uint32_t njobs, const rans_params *p
  * sets it).  waves_per_group: waves per persistent block sharing one staged
  * table (1..16; a maximum: a launch uses fewer when their rings and the
  * table do not fit LDS together); a work item covers waves_per_group
- * times 64 / N chunks (a decoding wave codes 64 / N chunks, an encoding
- * wave one); groups_per_cu:
- * persistent blocks per compute unit (1..8); table_layout: decode table
+ * times 64 / N chunks (a wave codes 64 / N chunks); groups_per_cu:
+ * persistent blocks per compute unit (1..16; blocks beyond what the
+ * registers and LDS of a compute unit hold wait for others to end);
+ * table_layout: decode table
  * layout in LDS, 0 = automatic, 1 = per-slot packed entries plus symbol
  * map, 2 = symbol map plus per-symbol entries, 3 = one 8-byte entry per slot
  * holding f, bias and symbol (8-bit alphabets, prob_bits <= 14); use_graph: replay the batch as a captured HIP
  * graph (1) or launch its kernels directly (0).  The batched kernels code
  * 32 or 64 interleaved coders per chunk (params->interleave 32 or 64; with
- * 32 a decoding wave codes two chunks, lanes 0-31 and 32-63, and an
- * encoding wave one chunk on half its lanes); batched encode
+ * 32 a wave codes two chunks, lanes 0-31 and 32-63); batched encode
  * needs chunk_syms != 0 with chunk_syms * sym_bytes a multiple of 16, and
  * every buffer 16-byte aligned.  Batched calls on a stream that is being
  * captured launch directly (no nested graph). */

@@ -251,13 +251,37 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
     }
 }
 
+// The placement arguments of job jb (nch chunks).
+__device__ __forceinline__ PlaceArgs job_place_args(const BatchArgs& a, BatchJob& jb, uint32_t nch)
+{
+    PlaceArgs pa;
+    pa.ticket = nullptr;
+    pa.lookback = reinterpret_cast<uint64_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.lookback)));
+    pa.out = jb.out;
+    pa.out_cap = jb.out_cap;
+    pa.total = &jb.total;
+    pa.total_out = jb.d_out_len;
+    uint32_t h[8];
+    job_header(a, jb, nch, h);
+    for (int q = 0; q < 8; ++q)
+        reinterpret_cast<uint32_t*>(pa.hdr)[q] = h[q];
+    return pa;
+}
+
 template <int R, int W, int NL, bool BF>
 __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
 {
+    // LDS: the waves' digit rings from address 0 (the kernel has no static
+    // LDS, so each ring's address is a multiple of its size), their symbol
+    // areas, the job's encoder entries, the work-item slot
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t s_slot[2];
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
-    uint8_t* sbuf = lds + a.tab_lds + wave * c64::kEncWaveLds;
+    uint8_t* ring = lds + wave * c64::kEncRing;
+    uint8_t* sbuf = lds + a.G * c64::kEncRing + wave * c64::kEncSymArea;
+    uint8_t* tab = lds + a.G * c64::kEncWaveLds;
+    uint32_t* s_slot = reinterpret_cast<uint32_t*>(tab + a.tab_lds);
+    // chunks per wave: with N = 32, lanes 0-31 code chunk c, lanes 32-63 c + 1
+    constexpr uint32_t PER = NL == 32 ? 2 : 1;
     int cur = -1;
     uint32_t item;
     for (;;) {
@@ -266,76 +290,50 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
             break;
         BatchJob& jb = a.jobs[j];
         if (j != cur) {
-            c64::stage_enc(lds, jb.enc, jb.enc_bytes, a.l + R - a.k, ~0u, W == 1 ? 256u : 0u);
+            c64::stage_enc(tab, jb.enc, jb.enc_bytes, a.l + R - a.k, ~0u, W == 1 ? 256u : 0u);
             __syncthreads();
             cur = j;
         }
         const uint32_t nch = c64::uni(jb.nch);
-        if constexpr (NL == 32) {
-            // two chunks per wave: lanes 0-31 code chunk c, lanes 32-63 chunk c + 1
-            const uint32_t c = c64::uni(((item - jb.item_base) * a.G + wave) * 2);
-            if (c < nch) {
-                uint8_t* s0 = reinterpret_cast<uint8_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.slots))) +
-                              uint64_t(c) * a.slot_stride;
-                uint8_t* s1 = s0 + a.slot_stride;
-                uint32_t x = 0, nd[2];
-                c64::encode_seg<R, W, BF>(jb.in, jb.n, c64::uni(jb.C), c, nch, a.l, jb.alphabet,
-                                          reinterpret_cast<const uint4*>(lds), s0, s1, a.slot_bytes, sbuf,
-                                          jb.d_status, &x, nd);
-                PlaceArgs pa;
-                pa.ticket = nullptr;
-                pa.lookback = reinterpret_cast<uint64_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.lookback)));
-                pa.out = jb.out;
-                pa.out_cap = jb.out_cap;
-                pa.total = &jb.total;
-                pa.total_out = jb.d_out_len;
-                uint32_t h[8];
-                job_header(a, jb, nch, h);
-                for (int q = 0; q < 8; ++q)
-                    reinterpret_cast<uint32_t*>(pa.hdr)[q] = h[q];
-                const uint32_t nd0 = c64::uni(nd[0]), nd1 = c64::uni(nd[1]);
-                const uint32_t x1 =
-                    static_cast<uint32_t>(__shfl(static_cast<int>(x), static_cast<int>((threadIdx.x & 63) | 32)));
-                const bool two = c + 1 < nch;
-                c64::publish_chunk<R, 32>(c, nd0, pa);
-                if (two)
-                    c64::publish_chunk<R, 32>(c + 1, nd1, pa);
-                bool t0 = false, t1 = false;
-                const uint64_t l0 = c64::chunk_local<R, 32>(c, nch, nd0, pa, t0);
-                const uint64_t l1 = two ? c64::chunk_local<R, 32>(c + 1, nch, nd1, pa, t1) : 0;
-                c64::place_chunk<R, 32>(c, nch, x, nd0, s0 + a.slot_bytes - uint64_t(nd0) * (R / 8), pa,
-                                        jb.d_status, true, l0, t0);
-                if (two)
-                    c64::place_chunk<R, 32>(c + 1, nch, x1, nd1, s1 + a.slot_bytes - uint64_t(nd1) * (R / 8), pa,
-                                            jb.d_status, true, l1, t1);
-            }
+        const uint32_t c = c64::uni(((item - jb.item_base) * a.G + wave) * PER);
+        if (c >= nch)
             continue;
-        }
-        const uint32_t c = c64::uni((item - jb.item_base) * a.G + wave);
-        if (c < nch) {
-            // the job's own slots (the host sized them for its nch chunks)
-            uint8_t* slot = reinterpret_cast<uint8_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.slots))) +
-                            uint64_t(c) * a.slot_stride;
-            uint32_t x = 0, nd = 0;
+        // the job's own slots (the host sized them for its nch chunks); the
+        // digits end at a slot's end, and the stride leaves room after it
+        // for the copy's reads past them
+        uint8_t* s0 = reinterpret_cast<uint8_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.slots))) +
+                      uint64_t(c) * a.slot_stride;
+        uint32_t x = 0, nd[2] = {0, 0};
+        if constexpr (NL == 32)
+            c64::encode_seg<R, W, BF>(jb.in, jb.n, c64::uni(jb.C), c, nch, a.l, jb.alphabet,
+                                      reinterpret_cast<const uint4*>(tab), s0, s0 + a.slot_stride, a.slot_bytes,
+                                      ring, sbuf, jb.d_status, &x, nd);
+        else
             c64::encode_chunk<R, W, NL, BF>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
-                                            reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes, sbuf,
-                                            nullptr, nullptr, jb.d_status, &x, &nd);
-            PlaceArgs pa;
-            pa.ticket = nullptr;
-            pa.lookback = reinterpret_cast<uint64_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.lookback)));
-            pa.out = jb.out;
-            pa.out_cap = jb.out_cap;
-            pa.total = &jb.total;
-            pa.total_out = jb.d_out_len;
-            uint32_t h[8];
-            job_header(a, jb, nch, h);
-            for (int q = 0; q < 8; ++q)
-                reinterpret_cast<uint32_t*>(pa.hdr)[q] = h[q];
-            // the digits end at the slot's end; the stride leaves room after
-            // it for the copy's reads past them
-            nd = c64::uni(nd);
-            c64::place_chunk<R, NL>(c, nch, x, nd, slot + a.slot_bytes - uint64_t(nd) * (R / 8), pa,
-                                    jb.d_status);
+                                            reinterpret_cast<const uint4*>(tab), s0, a.slot_bytes, ring, sbuf,
+                                            nullptr, nullptr, jb.d_status, &x, &nd[0]);
+        const PlaceArgs pa = job_place_args(a, jb, nch);
+        const uint32_t nd0 = c64::uni(nd[0]), nd1 = c64::uni(nd[1]);
+        if constexpr (NL == 32) {
+            // both lengths and group sums first: no chunk above them, in
+            // this group or a later one, waits on this wave's copies
+            const uint32_t x1 =
+                static_cast<uint32_t>(__shfl(static_cast<int>(x), static_cast<int>((threadIdx.x & 63) | 32)));
+            const bool two = c + 1 < nch;
+            c64::publish_chunk<R, 32>(c, nd0, pa);
+            if (two)
+                c64::publish_chunk<R, 32>(c + 1, nd1, pa);
+            bool t0 = false, t1 = false;
+            const uint64_t l0 = c64::chunk_local<R, 32>(c, nch, nd0, pa, t0);
+            const uint64_t l1 = two ? c64::chunk_local<R, 32>(c + 1, nch, nd1, pa, t1) : 0;
+            c64::place_chunk<R, 32>(c, nch, x, nd0, s0 + a.slot_bytes - uint64_t(nd0) * (R / 8), pa, jb.d_status,
+                                    true, l0, t0);
+            if (two)
+                c64::place_chunk<R, 32>(c + 1, nch, x1, nd1,
+                                        s0 + a.slot_stride + a.slot_bytes - uint64_t(nd1) * (R / 8), pa,
+                                        jb.d_status, true, l1, t1);
+        } else {
+            c64::place_chunk<R, NL>(c, nch, x, nd0, s0 + a.slot_bytes - uint64_t(nd0) * (R / 8), pa, jb.d_status);
         }
     }
 }
@@ -389,7 +387,7 @@ hipError_t persistent_decode_w(const BatchArgs& a, int W, int SW, Layout layout,
 template <int R, int W, int NL, bool BF>
 hipError_t persistent_encode(const BatchArgs& a, uint32_t grid, hipStream_t st)
 {
-    const uint32_t lds = a.tab_lds + a.G * c64::kEncWaveLds;
+    const uint32_t lds = a.G * c64::kEncWaveLds + a.tab_lds + 16;  // rings, blocks, table, item slot
     auto kern = k_batch_encode64<R, W, NL, BF>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess)

@@ -354,7 +354,7 @@ extern "C" int rans_decode_batch(const rans_job* jobs, uint32_t njobs, const ran
 extern "C" int rans_batch_set_config(const rans_batch_config* cfg)
 {
     if (!cfg || cfg->waves_per_group < 1 || cfg->waves_per_group > 16 || cfg->groups_per_cu < 1 ||
-        cfg->groups_per_cu > 8 || cfg->table_layout > 3)
+        cfg->groups_per_cu > 16 || cfg->table_layout > 3)
         return RANS_EINVAL;
     std::lock_guard<std::mutex> lk(g_cfg_mu);
     g_cfg = *cfg;

@@ -97,6 +97,47 @@ __device__ __forceinline__ uint32_t select_mask(uint64_t m, uint32_t a, uint32_t
     return r;
 }
 
+// Per lane, x > y as the wave's mask (returned), and *xs = x >> 16 where it
+// holds, x elsewhere.  The compare writes vcc, the one mask an SDWA select
+// reads, and the select takes x's upper half in place: one instruction
+// fewer than a shift and a select.
+__device__ __forceinline__ uint64_t gt_shift16(uint32_t x, uint32_t y, uint32_t* xs)
+{
+    uint64_t m;
+    uint32_t r;
+    asm("v_cmp_gt_u32_e32 vcc, %2, %3\n\t"
+        "s_mov_b64 %0, vcc\n\t"
+        "v_cndmask_b32_sdwa %1, %2, %2, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+        : "=s"(m), "=v"(r)
+        : "v"(x), "v"(y)
+        : "vcc");
+    *xs = r;
+    return m;
+}
+
+// A wave-uniform value in a vector register (a VOP3 operation reads at most
+// one scalar register on this chip; a loop-invariant copy frees the slot).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t s)
+{
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(s));
+    return r;
+}
+
+// A digit's ring store by the lanes of m: at LDS address a on those lanes,
+// at junk (a per-lane address nothing reads) on the others -- a select, not
+// an exec-mask branch, and a store the compiler counts when it waits for
+// the step's LDS reads.
+template <int B>
+__device__ __forceinline__ void ring_store(uint64_t m, uint32_t a, uint32_t junk, uint32_t v)
+{
+    const uint32_t o = select_mask(m, junk, a);
+    if constexpr (B == 2)
+        *(__attribute__((address_space(3))) uint16_t*)(o) = static_cast<uint16_t>(v);
+    else
+        *(__attribute__((address_space(3))) uint8_t*)(o) = static_cast<uint8_t>(v);
+}
+
 // The same address as a pointer into global memory.  Accesses through it are
 // global_* instructions, which count in vmcnt only and complete in issue
 // order, so the compiler waits for exactly the load it needs.  Through a
@@ -572,13 +613,16 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
         atomicMin(status, RANS_ECORRUPT);
 }
 
-// Four dwords as the compiler's vector type (for the non-temporal builtins).
-
-// Per-wave LDS of the encoder: a 1 KiB symbol block, a 4 KiB digit ring,
-// then 128 bytes where lanes with nothing to emit write.
+// Per-wave LDS of the encoder: a 4 KiB digit ring at an LDS address that is
+// a multiple of 4 KiB (a digit's ring address is its position's bits or-ed
+// into the ring's), and a symbol area: a 1 KiB symbol block, then 128
+// bytes where lanes with no digit to store write.  A kernel lays out the
+// rings of its waves first, from LDS address 0, then their symbol areas.
 constexpr uint32_t kEncRing = 4096;
+constexpr uint32_t kEncSymBlock = 1024;
+constexpr uint32_t kEncSymArea = kEncSymBlock + 128;
 constexpr uint32_t kEncWaveLds = kEncWaveLdsBytes;
-static_assert(kEncWaveLds == 1024 + kEncRing + 128, "encoder LDS layout");
+static_assert(kEncWaveLds == kEncRing + kEncSymArea, "encoder LDS layout");
 // Digits leave the ring in windows of kEncWindow bytes, aligned to
 // multiples of it in the slot (slot sizes are multiples of it), one 16-byte
 // store per lane.  Window stores per flush: after a flush fewer than
@@ -644,47 +688,54 @@ __device__ __forceinline__ uint32_t c_update(uint32_t x, uint32_t q, uint32_t z,
 // the step's block holds the first digit of every emitting lane, then the
 // second digit of every lane that emits two; depth-first keeps a lane's two
 // digits together.  Either way a lane's more significant digit is read first.
-template <int R, bool BF = false>
+template <int R, bool BF = false, bool FULL = false>
 __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& bad, const uint4& e,
-                                         bool act, uint8_t* dring, uint32_t lane)
+                                         bool act, uint32_t ringv, uint32_t junkv)
 {
     constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
     // idle lanes keep their state through selects, not branches (an
-    // exec-mask branch per step splits the unrolled loop into blocks)
-    bad |= act ? e.w : 0u;
-    const bool e1 = act && x > e.y;
-    // every lane writes (lanes with nothing to emit into the area after the
-    // ring), the address picked by a select on the ballot mask: no exec-mask
-    // changes on the step
+    // exec-mask branch per step splits the unrolled loop into blocks);
+    // FULL: every lane is active
+    bad |= FULL || act ? e.w : 0u;
+    // the emitting lanes store, each at its digit's ring position (ringv, the
+    // ring's LDS address in a vector register, is a multiple of the ring's
+    // size: the position's bits are or-ed in)
     if (R == 16) {
-        const uint64_t m = ballot(e1);
+        uint64_t m;
+        uint32_t xs;
+        if (FULL) {
+            m = gt_shift16(x, e.y, &xs);
+        } else {
+            const bool e1 = act && x > e.y;
+            m = ballot(e1);
+            xs = e1 ? x >> 16 : x;
+        }
         wpos -= __popcll(m);
-        const uint32_t o = select_mask(m, kEncRing + 2 * lane, ((wpos + mbcnt(m, 0)) << 1) & (2 * RD - 1));
-        *reinterpret_cast<uint16_t*>(dring + o) = static_cast<uint16_t>(x);
-        x = e1 ? x >> 16 : x;
+        ring_store<2>(m, (((mbcnt(m, 0) + wpos) << 1) & (2 * RD - 1)) | ringv, junkv, x);
+        x = xs;
     } else {
-        const bool e2 = act && (x >> 8) > e.y;
+        const bool e1 = (FULL || act) && x > e.y;
+        const bool e2 = (FULL || act) && (x >> 8) > e.y;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
         wpos -= __popcll(m1) + __popcll(m2);
         uint32_t i1, i2;
         if (BF) {
-            i1 = wpos + mbcnt(m1, 0);
-            i2 = (wpos + __popcll(m1)) + mbcnt(m2, 0);
+            i1 = mbcnt(m1, 0) + wpos;
+            i2 = mbcnt(m2, 0) + (wpos + __popcll(m1));
         } else {
-            i1 = wpos + (mbcnt(m1, 0) + mbcnt(m2, 0));
+            i1 = mbcnt(m1, mbcnt(m2, 0)) + wpos;
             i2 = i1 + 1;
         }
-        const uint32_t o1 = select_mask(m1, kEncRing + lane, i1 & (RD - 1));
-        const uint32_t o2 = select_mask(m2, kEncRing + 64 + lane, i2 & (RD - 1));
-        dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
-        dring[o2] = static_cast<uint8_t>(x);
+        ring_store<1>(m1, (i1 & (RD - 1)) | ringv, junkv, e2 ? x >> 8 : x);
+        ring_store<1>(m2, (i2 & (RD - 1)) | ringv, junkv, x);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
     // one multiply-high (the entry's m, inc and shift); the 24-bit multiply
     // reads M - f (bit 23 is set only on entries that are errors)
     const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
-    x = act ? c_update(x, q, e.z, e.w) : x;
+    const uint32_t xn = c_update(x, q, e.z, e.w);
+    x = FULL || act ? xn : x;
 }
 
 // Encoder step with escape coding (16-bit symbols, depth-first).  The value
@@ -697,7 +748,7 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
 // escape's entry, with bit 31 of z set, when v must escape.
 template <int R>
 __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32_t& bad, const uint4& e,
-                                             uint32_t v, bool act, uint8_t* dring, uint32_t lane)
+                                             uint32_t v, bool act, uint32_t ringv, uint32_t junkv)
 {
     constexpr uint32_t RD = kEncRing / (R / 8);  // ring size in digits
     const bool esc = act && (e.z >> 31) != 0;
@@ -706,11 +757,9 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
     const uint64_t m1 = ballot(e1), me = ballot(esc);
     if (R == 16) {
         wpos -= __popcll(m1) + __popcll(me);
-        const uint32_t i1 = wpos + (mbcnt(m1, 0) + mbcnt(me, 0));
-        const uint32_t o1 = select_mask(m1, kEncRing + 2 * lane, (i1 << 1) & (2 * RD - 1));
-        const uint32_t o2 = select_mask(me, kEncRing + 2 * lane, ((i1 + (e1 ? 1u : 0u)) << 1) & (2 * RD - 1));
-        *reinterpret_cast<uint16_t*>(dring + o1) = static_cast<uint16_t>(x);
-        *reinterpret_cast<uint16_t*>(dring + o2) = static_cast<uint16_t>(v);
+        const uint32_t i1 = mbcnt(m1, mbcnt(me, wpos));
+        ring_store<2>(m1, ((i1 << 1) & (2 * RD - 1)) | ringv, junkv, x);
+        ring_store<2>(me, (((i1 + (e1 ? 1u : 0u)) << 1) & (2 * RD - 1)) | ringv, junkv, v);
         x = e1 ? x >> 16 : x;
     } else {
         const bool e2 = act && (x >> 8) > e.y;
@@ -718,14 +767,10 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
         wpos -= __popcll(m1) + __popcll(m2) + 2 * __popcll(me);
         const uint32_t i1 = wpos + (mbcnt(m1, 0) + mbcnt(m2, 0) + 2 * mbcnt(me, 0));
         const uint32_t ir = i1 + (e1 ? 1u : 0u) + (e2 ? 1u : 0u);  // raw bytes after the renormalisation bytes
-        const uint32_t o1 = select_mask(m1, kEncRing + lane, i1 & (RD - 1));
-        const uint32_t o2 = select_mask(m2, kEncRing + 64 + lane, (i1 + 1) & (RD - 1));
-        const uint32_t o3 = select_mask(me, kEncRing + lane, ir & (RD - 1));
-        const uint32_t o4 = select_mask(me, kEncRing + 64 + lane, (ir + 1) & (RD - 1));
-        dring[o1] = static_cast<uint8_t>(e2 ? x >> 8 : x);
-        dring[o2] = static_cast<uint8_t>(x);
-        dring[o3] = static_cast<uint8_t>(v >> 8);
-        dring[o4] = static_cast<uint8_t>(v);
+        ring_store<1>(m1, (i1 & (RD - 1)) | ringv, junkv, e2 ? x >> 8 : x);
+        ring_store<1>(m2, ((i1 + 1) & (RD - 1)) | ringv, junkv, x);
+        ring_store<1>(me, (ir & (RD - 1)) | ringv, junkv, v >> 8);
+        ring_store<1>(me, ((ir + 1) & (RD - 1)) | ringv, junkv, v);
         x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
@@ -738,7 +783,8 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
 // states to states_out and the digit count to *ndig_out (or to the
 // caller's x_out / nd_out).  l_enc: LDS encoder entries staged by stage_enc
 // (alphabet + 1 entries; 256 with 8-bit symbols, which index it unclamped);
-// wave_lds: this wave's kEncWaveLds bytes.  Digits reach the slot from the
+// ring: this wave's kEncRing-byte digit ring (at an LDS address that is a
+// multiple of kEncRing); sbuf: its kEncSymArea-byte symbol area.  Digits reach the slot from the
 // LDS ring a window at a time, one 16-byte store per lane: after every block
 // of symbols, the windows the stream has grown past, padded to kFlushStores
 // stores with stores to the kSlotPad bytes after the slot.  A fixed
@@ -751,7 +797,7 @@ template <int R, int W, int NL, bool BF = false, bool ESC = false>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
                                              const uint4* l_enc, uint8_t* slot, uint64_t slot_bytes,
-                                             uint8_t* wave_lds, uint32_t* states_out, uint32_t* ndig_out,
+                                             uint8_t* ring, uint8_t* sbuf, uint32_t* states_out, uint32_t* ndig_out,
                                              int32_t* status, uint32_t* x_out = nullptr,
                                              uint32_t* nd_out = nullptr)
 {
@@ -761,8 +807,9 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
     constexpr uint32_t DB = R / 8, WD = kEncWindow / DB;  // bytes per digit, digits per window
     const uint32_t lane = threadIdx.x & 63;
     const bool live = NL == 64 || lane < NL;
-    uint8_t* sbuf = wave_lds;
-    uint8_t* dring = wave_lds + 1024;
+    const uint8_t* dring = ring;
+    const uint32_t ringv = in_vgpr(lds_addr(ring));
+    const uint32_t junkv = lds_addr(sbuf) + kEncSymBlock + 2 * lane;
     const uint64_t first = chunk * C;
     const uint32_t nsym = uni(static_cast<uint32_t>(n - first < C ? n - first : C));
     const InT* in = static_cast<const InT*>(syms_base) + first;
@@ -798,9 +845,9 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         const bool act = live && i < nsym;
         const uint32_t s = act ? static_cast<uint32_t>(gmem(in)[i]) : 0u;
         if (ESC)
-            enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], s, act, dring, lane);
+            enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], s, act, ringv, junkv);
         else
-            enc_step<R, BF>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], act, dring, lane);
+            enc_step<R, BF>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], act, ringv, junkv);
     }
     flush();  // the tail is shorter than a block: at most 2 windows
 
@@ -845,9 +892,9 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
                     if (q - PF >= 0)
                         ent[q - PF] = entry(q - PF);
                     if (ESC)
-                        enc_step_esc<R>(x, wpos, bad, ent[q], sy[q], live, dring, lane);
+                        enc_step_esc<R>(x, wpos, bad, ent[q], sy[q], live, ringv, junkv);
                     else
-                        enc_step<R, BF>(x, wpos, bad, ent[q], live, dring, lane);
+                        enc_step<R, BF, NL == 64>(x, wpos, bad, ent[q], live, ringv, junkv);
                 }
             }
             flush();

@@ -12,11 +12,18 @@ namespace {
 template <int R, int W, int NL, bool BF, bool ESC>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
+    // LDS: the waves' digit rings from address 0 (the kernel has no static
+    // LDS, so each ring's address is a multiple of its size), their symbol
+    // areas, then the encoder entries
     extern __shared__ __align__(16) uint8_t lds[];
-    const uint32_t tab = enc_lds_bytes(a.enc_bytes, W);
-    c64::stage_enc(lds, a.enc, a.enc_bytes, a.l + R - a.k, ESC ? a.alphabet - 1 : ~0u, tab / 16);
-    __syncthreads();
+    const uint32_t nw = c64::uni(blockDim.x >> 6);
     const uint32_t wave = c64::uni(threadIdx.x >> 6);
+    uint8_t* ring = lds + wave * c64::kEncRing;
+    uint8_t* sbuf = lds + nw * c64::kEncRing + wave * c64::kEncSymArea;
+    uint8_t* tab = lds + nw * c64::kEncWaveLds;
+    c64::stage_enc(tab, a.enc, a.enc_bytes, a.l + R - a.k, ESC ? a.alphabet - 1 : ~0u,
+                   enc_lds_bytes(a.enc_bytes, W) / 16);
+    __syncthreads();
     uint32_t t = 0;
     if ((threadIdx.x & 63) == 0)
         t = atomicAdd(p.ticket, 1u);
@@ -29,8 +36,8 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
         uint8_t* s1 = s0 + a.slot_stride;
         uint32_t x = 0, nd[2];
         c64::encode_seg<R, W, BF>(a.syms, a.n, a.C, chunk, a.n_chunks, a.l, a.alphabet,
-                                  reinterpret_cast<const uint4*>(lds), s0, s1, a.slot_bytes,
-                                  lds + tab + wave * c64::kEncWaveLds, a.status, &x, nd);
+                                  reinterpret_cast<const uint4*>(tab), s0, s1, a.slot_bytes, ring, sbuf,
+                                  a.status, &x, nd);
         // the lower chunk first: the upper one's look-back waits on it
         const uint32_t nd0 = c64::uni(nd[0]), nd1 = c64::uni(nd[1]);
         const uint32_t x1 = static_cast<uint32_t>(__shfl(static_cast<int>(x), static_cast<int>((threadIdx.x & 63) | 32)));
@@ -54,8 +61,8 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
     uint8_t* slot = a.slots + uint64_t(chunk) * a.slot_stride;
     uint32_t x = 0, nd = 0;
     c64::encode_chunk<R, W, NL, BF, ESC>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
-                                reinterpret_cast<const uint4*>(lds), slot, a.slot_bytes,
-                                lds + tab + wave * c64::kEncWaveLds, nullptr, nullptr, a.status,
+                                reinterpret_cast<const uint4*>(tab), slot, a.slot_bytes, ring, sbuf,
+                                nullptr, nullptr, a.status,
                                 &x, &nd);
     // the digits end at slot + slot_bytes; the slot padding after it absorbs
     // the copy's reads past them

@@ -12,9 +12,9 @@
 namespace rans {
 namespace c64 {
 
-// Per-wave LDS of the two-segment encoder: a 1 KiB symbol block (512 bytes
-// per segment), two 2 KiB digit rings, 128 bytes for the writes of lanes with
-// nothing to emit -- the one-chunk encoder's kEncWaveLds bytes.
+// Per-wave LDS of the two-segment encoder: the one-chunk encoder's 4 KiB
+// ring split into two 2 KiB digit rings (each at an LDS address that is a
+// multiple of 2 KiB), and its symbol area (a 512-byte block per segment).
 constexpr uint32_t kSegRing = 2048;
 // Digits leave a ring in 512-byte windows (16 bytes per lane of the
 // segment), aligned to multiples of 512 in the slot.  After a flush fewer
@@ -23,40 +23,47 @@ constexpr uint32_t kSegRing = 2048;
 // the ring holds the less than 1.5 KiB pending.
 constexpr uint32_t kSegWindow = 512;
 constexpr uint32_t kSegFlushStores = 2;
-static_assert(2 * kSegRing + 1024 + 128 == kEncWaveLds && kSlotAlign % kSegWindow == 0 &&
+static_assert(2 * kSegRing == kEncRing && kSlotAlign % kSegWindow == 0 &&
                   kSegRing % kSegWindow == 0 && kSlotPad >= kSegWindow,
               "two-segment encoder geometry");
 
 // One encoder step of both segments.  wpos: each segment's lowest digit
 // written so far (it grows downwards); amask: the lanes that code a symbol on
 // this step (wave-uniform; every lane when FULL); vhi: all ones in the upper
-// segment's lanes; segoff: the lane's ring (0 or kSegRing).  As enc_step,
-// with the prefix count taken over the whole wave and the upper segment's
-// lanes moved to their own position by a per-lane offset (the count also
-// covers the lower segment's emitting lanes, which the offset takes back
-// out).  Idle lanes keep their state through selects on amask: the ballots
-// are masked with it, so no per-lane predicate is formed and no exec-mask
-// branch splits the unrolled block.
+// segment's lanes; segbase: the LDS address of the lane's segment ring (a
+// multiple of kSegRing: a digit's ring address is its position's bits or-ed
+// in).  As enc_step, with the prefix count taken over the whole wave and
+// the upper segment's lanes moved to their own position by a per-lane
+// offset (the count also covers the lower segment's emitting lanes, which
+// the offset takes back out).  Idle lanes keep their state through selects
+// on amask: the ballots are masked with it, so no per-lane predicate is
+// formed and no exec-mask branch splits the unrolled block.
 template <int R, bool BF, bool FULL>
 __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32_t& bad, const uint4& e,
-                                             uint64_t amask, uint8_t* dring, uint32_t lane, uint32_t vhi,
-                                             uint32_t segoff)
+                                             uint64_t amask, uint32_t vhi, uint32_t segbase, uint32_t junkv)
 {
     constexpr uint32_t RB = kSegRing;
     const uint64_t am = FULL ? ~0ull : amask;
     bad |= FULL ? e.w : select_mask(am, 0u, e.w);
     if (R == 16) {
-        const uint64_t m = ballot(x > e.y) & am;
+        uint64_t m;
+        uint32_t xs;
+        if (FULL) {
+            m = gt_shift16(x, e.y, &xs);
+        } else {
+            m = ballot(x > e.y) & am;
+            xs = select_mask(m, x, x >> 16);
+        }
         const uint32_t lo = __popc(static_cast<uint32_t>(m)), hi = __popc(static_cast<uint32_t>(m >> 32));
         wpos[0] -= lo;
         wpos[1] -= hi;
-        const uint32_t acc = wpos[0] + and_sv(wpos[1] - wpos[0] - lo, vhi);
-        const uint32_t o = select_mask(m, 2 * kSegRing + 2 * lane, ((mbcnt(m, acc) << 1) & (RB - 1)) | segoff);
-        *reinterpret_cast<uint16_t*>(dring + o) = static_cast<uint16_t>(x);
-        x = select_mask(m, x, x >> 16);
+        const uint32_t pos = mbcnt(m, and_sv(wpos[1] - wpos[0] - lo, vhi)) + wpos[0];
+        ring_store<2>(m, ((pos << 1) & (RB - 1)) | segbase, junkv, x);
+        x = xs;
     } else {
         // a lane that emits two digits also emits one: m2 is within m1
-        const uint64_t m1 = ballot(x > e.y) & am, m2 = ballot((x >> 8) > e.y) & am;
+        const bool e1 = x > e.y, e2 = (x >> 8) > e.y;
+        const uint64_t m1 = FULL ? ballot(e1) : ballot(e1) & am, m2 = FULL ? ballot(e2) : ballot(e2) & am;
         const uint32_t lo1 = __popc(static_cast<uint32_t>(m1)), hi1 = __popc(static_cast<uint32_t>(m1 >> 32));
         const uint32_t lo2 = __popc(static_cast<uint32_t>(m2)), hi2 = __popc(static_cast<uint32_t>(m2 >> 32));
         wpos[0] -= lo1 + lo2;
@@ -64,17 +71,16 @@ __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32
         uint32_t i1, i2;
         if (BF) {
             // first digits of a segment, then its second digits
-            i1 = mbcnt(m1, wpos[0] + and_sv(wpos[1] - wpos[0] - lo1, vhi));
-            i2 = mbcnt(m2, (wpos[0] + lo1) + and_sv((wpos[1] + hi1) - (wpos[0] + lo1) - lo2, vhi));
+            i1 = mbcnt(m1, and_sv(wpos[1] - wpos[0] - lo1, vhi)) + wpos[0];
+            i2 = mbcnt(m2, and_sv((wpos[1] + hi1) - (wpos[0] + lo1) - lo2, vhi)) + (wpos[0] + lo1);
         } else {
-            i1 = mbcnt(m1, wpos[0] + and_sv(wpos[1] - wpos[0] - lo1 - lo2, vhi)) + mbcnt(m2, 0);
+            i1 = mbcnt(m1, mbcnt(m2, and_sv(wpos[1] - wpos[0] - lo1 - lo2, vhi))) + wpos[0];
             i2 = i1 + 1;
         }
-        const uint32_t o1 = select_mask(m1, 2 * kSegRing + lane, (i1 & (RB - 1)) | segoff);
-        const uint32_t o2 = select_mask(m2, 2 * kSegRing + 64 + lane, (i2 & (RB - 1)) | segoff);
-        dring[o1] = static_cast<uint8_t>(select_mask(m2, x, x >> 8));
-        dring[o2] = static_cast<uint8_t>(x);
-        x = select_mask(m2, select_mask(m1, x, x >> 8), x >> 16);
+        const uint32_t d1 = FULL ? (e2 ? x >> 8 : x) : select_mask(m2, x, x >> 8);
+        ring_store<1>(m1, (i1 & (RB - 1)) | segbase, junkv, d1);
+        ring_store<1>(m2, (i2 & (RB - 1)) | segbase, junkv, x);
+        x = FULL ? (e2 ? x >> 16 : (e1 ? x >> 8 : x)) : select_mask(m2, select_mask(m1, x, x >> 8), x >> 16);
     }
     const uint32_t q = __umulhi(e.x, x + (e.w >> 24)) >> ((e.z >> 16) & 31u);
     // computed on every lane and selected: C's result through a branch on a
@@ -91,13 +97,13 @@ __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32
 // chunk0's coders, 32-63 the next chunk's) and nd[s] is segment s's digit
 // count; slot1 is not touched when there is no second chunk.  l_enc: staged
 // encoder entries as for encode_chunk (alphabet + 1
-// entries; 256 with 8-bit symbols); wave_lds: kEncWaveLds bytes.  Arguments
-// wave-uniform.
+// entries; 256 with 8-bit symbols); ring, sbuf: this wave's digit ring and
+// symbol block, as for encode_chunk.  Arguments wave-uniform.
 template <int R, int W, bool BF>
 __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk0,
                                            uint32_t n_chunks, uint32_t l, uint32_t alphabet,
                                            const uint4* l_enc, uint8_t* slot0,
-                                           uint8_t* slot1, uint64_t slot_bytes, uint8_t* wave_lds,
+                                           uint8_t* slot1, uint64_t slot_bytes, uint8_t* ring, uint8_t* sbuf,
                                            int32_t* status, uint32_t* x_out, uint32_t* nd)
 {
     constexpr uint32_t NL = 32;
@@ -106,8 +112,9 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
     constexpr uint32_t DB = R / 8, WD = kSegWindow / DB;
     const uint32_t lane = threadIdx.x & 63, seg = lane >> 5, jl = lane & 31;
     const uint32_t vhi = seg ? 0xFFFFFFFFu : 0u, segoff = seg * kSegRing;
-    uint8_t* sbuf = wave_lds;
-    uint8_t* dring = wave_lds + 1024;
+    const uint8_t* dring = ring;
+    const uint32_t segbase = lds_addr(ring) + segoff;
+    const uint32_t junkv = lds_addr(sbuf) + kEncSymBlock + 2 * lane;
     const bool has1 = chunk0 + 1 < n_chunks;
     uint32_t nsym[2], steps[2], nblk[2];
     const InT* in[2];
@@ -200,7 +207,7 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
         for (int q = int(SPB) - 1; q >= 0; --q) {
             if (q - PF >= 0)
                 ent[q - PF] = entry(q - PF);
-            enc_step_seg<R, BF, decltype(full)::value>(x, wpos, bad, ent[q], amask, dring, lane, vhi, segoff);
+            enc_step_seg<R, BF, decltype(full)::value>(x, wpos, bad, ent[q], amask, vhi, segbase, junkv);
         }
     };
     int64_t b = int64_t(nb) - 1;
@@ -228,8 +235,8 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
                 const uint32_t i = t * NL + jl;
                 const bool act = i < mynsym;
                 const uint32_t s = act ? static_cast<uint32_t>(gmem(myin)[i]) : 0u;
-                enc_step_seg<R, BF, false>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], ballot(act), dring,
-                                           lane, vhi, segoff);
+                enc_step_seg<R, BF, false>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], ballot(act), vhi,
+                                           segbase, junkv);
             }
         }
         flush();

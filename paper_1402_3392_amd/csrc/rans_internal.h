@@ -200,8 +200,8 @@ uint32_t decode_seg_lds_per_wave(Layout layout, uint32_t N);
 hipError_t launch_decode64_lut(const DecodeArgs& a, int R, Layout layout, hipStream_t stream);
 // LDS bytes of a staged lookup table of `alphabet` entries of lw bytes.
 inline uint32_t lut_lds_bytes(uint32_t alphabet, int lw) { return (alphabet * uint32_t(lw) + 15) & ~15u; }
-// LDS per wave of the one-wave-per-chunk encoder: 1 KiB symbol block, 4 KiB
-// digit ring, 128 bytes for the writes of lanes with nothing to emit.
+// LDS per wave of the encoders: a 4 KiB digit ring, a 1 KiB symbol block and
+// 128 bytes for the stores of lanes with nothing to emit.
 constexpr uint32_t kEncWaveLdsBytes = 5248;
 // Encoder digit slots: sizes are multiples of kSlotAlign (the encoder
 // writes whole windows of that size, aligned to multiples of it), and

@@ -239,7 +239,7 @@ def test_batch_config_validation(lr):
     with pytest.raises(lr.RansError):
         lr.rans_batch_set_config(0, 1, 0, 1)
     with pytest.raises(lr.RansError):
-        lr.rans_batch_set_config(16, 9, 0, 1)
+        lr.rans_batch_set_config(16, 17, 0, 1)
     lr.rans_batch_set_config(8, 2, 2, 1)
     assert lr.rans_batch_get_config() == {"waves_per_group": 8, "groups_per_cu": 2,
                                           "table_layout": 2, "use_graph": 1}
