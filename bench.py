@@ -104,6 +104,9 @@ def parse():
                     help="autotuner cache file (results measured on MI355X; '' disables it)")
     ap.add_argument("--headline-only", action="store_true",
                     help="headline: only the sweep line (no 4096-stream, serving, round-trip extras)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="headline: only the timed batched steps and their roofline (no per-group "
+                         "times, plain launches or extras; the profiling passes run this)")
     return ap.parse_args()
 
 
@@ -783,7 +786,8 @@ def run_headline(args):
     for _ in range(args.warmup):
         sw.step()
     torch.cuda.synchronize()
-    sw.check()
+    if args.warmup:
+        sw.check()  # the decoded lengths are in place only after a step
     log(f"timing {args.steps} steps")
     lr.rans_timing_reset()
     lr.rans_timing_enable(True)
@@ -817,6 +821,16 @@ def run_headline(args):
 
     dom, other = ("encode", "decode") if kt["encode"][1] >= kt["decode"][1] else ("decode", "encode")
     knames = {"decode": "k_batch_decode64", "encode": "k_batch_encode64"}
+    if args.batched_only:
+        res = base_result("rANS decode/encode GB/s on 1 MI355X, batched", round(value, 2), "GB/s", args,
+                          {"workload": "radix/precision sweep, 84 points of 64 MiB, batched by (k,r,l,w,N)",
+                           "points": 84, "launches_per_step": 2 * nlaunch, "symbol_bytes_per_step": sw.total,
+                           "parallelism": "none"})
+        res["ms_per_step"] = round(1e3 * elapsed / args.steps, 3)
+        res["roofline"] = roof(dom, knames[dom])
+        res[f"roofline_{other}"] = roof(other, knames[other])
+        print(json.dumps(res), flush=True)
+        return
     log("per-group times")
     rows = sw.group_times(max(3, args.steps))
     log("plain launches per point at their best chunk size")
