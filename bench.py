@@ -104,6 +104,9 @@ def parse():
                     help="autotuner cache file (results measured on MI355X; '' disables it)")
     ap.add_argument("--headline-only", action="store_true",
                     help="headline: only the sweep line (no 4096-stream, serving, round-trip extras)")
+    ap.add_argument("--groups", default="",
+                    help="headline: only these sweep groups (comma-separated indices in (k, r, l, w, N) "
+                         "order; for profiling one kernel instance)")
     ap.add_argument("--batched-only", action="store_true",
                     help="headline: only the timed batched steps and their roofline (no per-group "
                          "times, plain launches or extras; the profiling passes run this)")
@@ -621,14 +624,19 @@ class SweepGroups:
         groups = {}
         for p in pts:
             groups.setdefault((p["k"], p["r"], p["l"], p["w"], p["N"]), []).append(p)
+        keys = sorted(groups)
+        if getattr(args, "groups", ""):
+            keys = [keys[int(i)] for i in args.groups.split(",")]
         data = {}
-        for p in pts:
-            key = (p["alphabet"], p["dist"])
-            if key not in data:
-                data[key] = datagen.sweep_data(p["alphabet"], p["dist"])[0]
+        for key in keys:
+            for p in groups[key]:
+                dk = (p["alphabet"], p["dist"])
+                if dk not in data:
+                    data[dk] = datagen.sweep_data(p["alphabet"], p["dist"])[0]
         self.groups = []
         self.points = []  # (point, symbols, quantised frequencies, C) for the CPU baseline
-        for (k, r, l, w, N), gp in sorted(groups.items()):
+        for (k, r, l, w, N) in keys:
+            gp = groups[(k, r, l, w, N)]
             syms = [data[(p["alphabet"], p["dist"])] for p in gp]
             sizes = [int(x.nbytes) for x in syms]
             tables = [lr.rans_tables_build(datagen.counts(x, p["alphabet"]), k) for p, x in zip(gp, syms)]
@@ -811,7 +819,7 @@ def run_headline(args):
         avg_us = 1e3 * ms / max(cnt, 1)
         alg_launch = sw.alg / nlaunch
         ach = args.steps * sw.alg / (ms / 1e3) / 1e9
-        tr = traffic_for(kname, "sweep84")
+        tr = None if args.groups else traffic_for(kname, "sweep84")
         return {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
                 "traffic": None if tr is None else int(tr / nlaunch),
@@ -823,9 +831,10 @@ def run_headline(args):
     knames = {"decode": "k_batch_decode64", "encode": "k_batch_encode64"}
     if args.batched_only:
         res = base_result("rANS decode/encode GB/s on 1 MI355X, batched", round(value, 2), "GB/s", args,
-                          {"workload": "radix/precision sweep, 84 points of 64 MiB, batched by (k,r,l,w,N)",
-                           "points": 84, "launches_per_step": 2 * nlaunch, "symbol_bytes_per_step": sw.total,
-                           "parallelism": "none"})
+                          {"workload": f"radix/precision sweep, {len(sw.points)} points of 64 MiB, batched by "
+                                       f"(k,r,l,w,N)" + (f" (groups {args.groups} only)" if args.groups else ""),
+                           "points": len(sw.points), "launches_per_step": 2 * nlaunch,
+                           "symbol_bytes_per_step": sw.total, "parallelism": "none"})
         res["ms_per_step"] = round(1e3 * elapsed / args.steps, 3)
         res["roofline"] = roof(dom, knames[dom])
         res[f"roofline_{other}"] = roof(other, knames[other])
@@ -847,7 +856,7 @@ def run_headline(args):
                                    "each with its own table, batched by (k,r,l,w,N): 12 persistent "
                                    "launches per direction, chunk size and launch shape autotuned per "
                                    "batch; one step = batched encode + batched decode of every point",
-                       "points": 84, "launches_per_step": 2 * nlaunch,
+                       "points": len(sw.points), "launches_per_step": 2 * nlaunch,
                        "symbol_bytes_per_step": sw.total, "parallelism": "none"})
     res["ms_per_step"] = round(1e3 * elapsed / args.steps, 3)
     res["batched_decode_gbps"] = round(sw.total / bat_dec / 1e9, 1)
