@@ -688,8 +688,8 @@ class SweepGroups:
         self.lr.rans_decode_batch(g["dec_jobs"], len(g["points"]), g["params"])
 
     def step(self):
+        # (the planning kernel of every launch sets each job's status word)
         for g in self.groups:
-            g["st"].zero_()
             self.encode(g)
             self.decode(g)
 
