@@ -1231,7 +1231,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one MI355X only: the coder's work is independent per "
-              "chunk and this build runs no multi-GPU path (--gpus 1).", file=sys.stderr)
+              "chunk and the library has no multi-GPU path (--gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     if args.source_hash:
