@@ -1175,8 +1175,12 @@ __device__ __forceinline__ void place_chunk(uint32_t chunk, uint32_t nch, uint32
             __builtin_nontemporal_store(t, gmem(reinterpret_cast<v4u*>(D + q)));
         };
         // KU rounds of loads in flight before their stores: one round at a
-        // time would wait a full memory latency per KiB
-        constexpr uint32_t KU = 8;
+        // time would wait a full memory latency per KiB.  Two rounds keep
+        // the copy's registers (four 16-byte loads per lane) under what the
+        // coding loop holds, so the copy does not set the kernel's register
+        // count: about 80, six waves per SIMD, where eight rounds took the
+        // encoders to 117-127 registers and four waves per SIMD.
+        constexpr uint32_t KU = 2;
         uint32_t q0 = lane;
         for (; q0 + 64 * (KU - 1) < pieces; q0 += 64 * KU) {
             uint4 lo[KU], hi[KU];
