@@ -717,18 +717,28 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         const bool e1 = (FULL || act) && x > e.y;
         const bool e2 = (FULL || act) && (x >> 8) > e.y;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
-        wpos -= __popcll(m1) + __popcll(m2);
-        uint32_t i1, i2;
-        if (BF) {
-            i1 = mbcnt(m1, 0) + wpos;
-            i2 = mbcnt(m2, 0) + (wpos + __popcll(m1));
+        if (FULL && m2 == 0) {
+            // no lane emits two digits (only a symbol with f < M / 256 can
+            // need two): one prefix count, one store, one shift; both digit
+            // orders agree.  A wave-uniform branch: in the two-chunk encoder
+            // it cost registers and gained little, so only this one has it.
+            wpos -= __popcll(m1);
+            ring_store<1>(m1, ((mbcnt(m1, 0) + wpos) & (RD - 1)) | ringv, junkv, x);
+            x = e1 ? x >> 8 : x;
         } else {
-            i1 = mbcnt(m1, mbcnt(m2, 0)) + wpos;
-            i2 = i1 + 1;
+            wpos -= __popcll(m1) + __popcll(m2);
+            uint32_t i1, i2;
+            if (BF) {
+                i1 = mbcnt(m1, 0) + wpos;
+                i2 = mbcnt(m2, 0) + (wpos + __popcll(m1));
+            } else {
+                i1 = mbcnt(m1, mbcnt(m2, 0)) + wpos;
+                i2 = i1 + 1;
+            }
+            ring_store<1>(m1, (i1 & (RD - 1)) | ringv, junkv, e2 ? x >> 8 : x);
+            ring_store<1>(m2, (i2 & (RD - 1)) | ringv, junkv, x);
+            x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
         }
-        ring_store<1>(m1, (i1 & (RD - 1)) | ringv, junkv, e2 ? x >> 8 : x);
-        ring_store<1>(m2, (i2 & (RD - 1)) | ringv, junkv, x);
-        x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
     // one multiply-high (the entry's m, inc and shift); the 24-bit multiply
