@@ -322,3 +322,32 @@ def test_digit_orders_equal_hand_derived_streams(lr, name):
         assert [int(v) for v in got[off + 4 * N:end]] == digits, order
         assert got.size == (end + 15) // 16 * 16 and not got[end:].any(), order
         assert (gpu_decode(lr, table, got, msg.size, 1) == msg).all(), order
+
+
+@pytest.mark.parametrize("order", ["df", "bf"])
+def test_byte_digit_steps_with_and_without_second_digits(lr, order):
+    """Byte digits (b = 2^8, L = 2^23) with 64 coders per chunk.  Most of each
+    chunk holds symbols with f >= M / 256, so no lane can need a second digit
+    in a step (the renormalised state stays below b L); short bursts of one
+    symbol with f < M / 256 give steps in which some lanes emit two.  The
+    encoder takes a shorter path for steps without second digits; either way
+    the container must equal the oracle's in both digit orders, and decode."""
+    k, r, l, N, C = 12, 8, 23, 64, 16384
+    rng = np.random.Generator(np.random.PCG64(4242))
+    n = 8 * C + 777
+    syms = rng.integers(0, 16, n, dtype=np.uint8)
+    for c0 in range(0, n, C):
+        burst = c0 + 4096 + np.arange(0, 1024, 32)
+        syms[burst[burst < n]] = 200
+    counts = datagen.counts(syms, 256)
+    f_or = oracle.quantize(counts, k)
+    assert 0 < f_or[200] < (1 << k) // 256 <= int(f_or[:16].min())
+    table = lr.rans_tables_build(counts, k)
+    print(f"[parity-digits] order={order} n={n}", flush=True)
+    ref = oracle.encode(f_or, syms, k, r, l, N, C, threads=4, order=order)
+    other = oracle.encode(f_or, syms, k, r, l, N, C, threads=4, order="bf" if order == "df" else "df")
+    assert (ref[32:] != other[32:]).any()  # the orders differ: some steps do emit second digits
+    got = gpu_encode(lr, table, (k, r, l, 1, N, C, order), syms)
+    assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
+    dec = gpu_decode(lr, table, ref, n, 1)
+    assert (dec == syms).all(), first_diff(dec, syms)
