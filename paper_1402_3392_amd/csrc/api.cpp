@@ -272,6 +272,7 @@ int rans::prepare_encode(const rans_table* table, const rans_params* params, con
     ea->alphabet = t.alphabet;
     ea->bf = p.digit_order;
     ea->esc = p.escape;
+    ea->one = R == 8 && !p.escape && t.one_digit ? 1u : 0u;
     ea->enc = pfx ? reinterpret_cast<const uint4*>(t.pfx_enc) : t.enc;
     ea->enc_bytes = static_cast<uint32_t>(pfx ? t.pfx_enc_bytes : t.enc_bytes);
     ea->slot_bytes = sb;

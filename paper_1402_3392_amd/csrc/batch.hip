@@ -304,14 +304,26 @@ __global__ void __launch_bounds__(1024) k_batch_encode64(const BatchArgs a)
         uint8_t* s0 = reinterpret_cast<uint8_t*>(c64::uni64(reinterpret_cast<uintptr_t>(jb.slots))) +
                       uint64_t(c) * a.slot_stride;
         uint32_t x = 0, nd[2] = {0, 0};
-        if constexpr (NL == 32)
-            c64::encode_seg<R, W, BF>(jb.in, jb.n, c64::uni(jb.C), c, nch, a.l, jb.alphabet,
-                                      reinterpret_cast<const uint4*>(tab), s0, s0 + a.slot_stride, a.slot_bytes,
-                                      ring, sbuf, jb.d_status, &x, nd);
-        else
-            c64::encode_chunk<R, W, NL, BF>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
-                                            reinterpret_cast<const uint4*>(tab), s0, a.slot_bytes, ring, sbuf,
-                                            nullptr, nullptr, jb.d_status, &x, &nd[0]);
+        auto code = [&](auto one) {
+            constexpr bool ONE = decltype(one)::value;
+            if constexpr (NL == 32)
+                c64::encode_seg<R, W, BF, ONE>(jb.in, jb.n, c64::uni(jb.C), c, nch, a.l, jb.alphabet,
+                                               reinterpret_cast<const uint4*>(tab), s0, s0 + a.slot_stride,
+                                               a.slot_bytes, ring, sbuf, jb.d_status, &x, nd);
+            else
+                c64::encode_chunk<R, W, NL, BF, false, ONE>(jb.in, jb.n, c64::uni(jb.C), c, a.k, a.l, jb.alphabet,
+                                                            reinterpret_cast<const uint4*>(tab), s0, a.slot_bytes,
+                                                            ring, sbuf, nullptr, nullptr, jb.d_status, &x, &nd[0]);
+        };
+        // byte digits and a one-digit table: the single-digit step
+        if constexpr (R == 8) {
+            if (c64::uni(jb.one))
+                code(std::true_type{});
+            else
+                code(std::false_type{});
+        } else {
+            code(std::false_type{});
+        }
         const PlaceArgs pa = job_place_args(a, jb, nch);
         const uint32_t nd0 = c64::uni(nd[0]), nd1 = c64::uni(nd[1]);
         if constexpr (NL == 32) {

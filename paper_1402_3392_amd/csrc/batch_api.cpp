@@ -126,6 +126,7 @@ int plan_batch(const rans_job* jobs, uint32_t njobs, const rans_params* params, 
         b.d_out_len = jb.d_out_len;
         b.d_status = jb.d_status;
         b.alphabet = t->alphabet;
+        b.one = p.radix_bits == 8 && t->one_digit ? 1u : 0u;
         b.enc = t->enc;
         b.enc_bytes = static_cast<uint32_t>(t->enc_bytes);
         if (!decode) {

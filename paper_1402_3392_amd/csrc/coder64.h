@@ -688,7 +688,10 @@ __device__ __forceinline__ uint32_t c_update(uint32_t x, uint32_t q, uint32_t z,
 // the step's block holds the first digit of every emitting lane, then the
 // second digit of every lane that emits two; depth-first keeps a lane's two
 // digits together.  Either way a lane's more significant digit is read first.
-template <int R, bool BF = false, bool FULL = false>
+// ONE (byte digits): the table is a one-digit table (every f is 0 or at least
+// M / 256), so no lane emits a second digit and the step has one compare,
+// one ballot, one prefix count and one store.
+template <int R, bool BF = false, bool FULL = false, bool ONE = false>
 __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& bad, const uint4& e,
                                          bool act, uint32_t ringv, uint32_t junkv)
 {
@@ -713,32 +716,28 @@ __device__ __forceinline__ void enc_step(uint32_t& x, uint32_t& wpos, uint32_t& 
         wpos -= __popcll(m);
         ring_store<2>(m, (((mbcnt(m, 0) + wpos) << 1) & (2 * RD - 1)) | ringv, junkv, x);
         x = xs;
+    } else if (ONE) {
+        const bool e1 = (FULL || act) && x > e.y;
+        const uint64_t m1 = ballot(e1);
+        wpos -= __popcll(m1);
+        ring_store<1>(m1, ((mbcnt(m1, 0) + wpos) & (RD - 1)) | ringv, junkv, x);
+        x = e1 ? x >> 8 : x;
     } else {
         const bool e1 = (FULL || act) && x > e.y;
         const bool e2 = (FULL || act) && (x >> 8) > e.y;
         const uint64_t m1 = ballot(e1), m2 = ballot(e2);
-        if (FULL && m2 == 0) {
-            // no lane emits two digits (only a symbol with f < M / 256 can
-            // need two): one prefix count, one store, one shift; both digit
-            // orders agree.  A wave-uniform branch: in the two-chunk encoder
-            // it cost registers and gained little, so only this one has it.
-            wpos -= __popcll(m1);
-            ring_store<1>(m1, ((mbcnt(m1, 0) + wpos) & (RD - 1)) | ringv, junkv, x);
-            x = e1 ? x >> 8 : x;
+        wpos -= __popcll(m1) + __popcll(m2);
+        uint32_t i1, i2;
+        if (BF) {
+            i1 = mbcnt(m1, 0) + wpos;
+            i2 = mbcnt(m2, 0) + (wpos + __popcll(m1));
         } else {
-            wpos -= __popcll(m1) + __popcll(m2);
-            uint32_t i1, i2;
-            if (BF) {
-                i1 = mbcnt(m1, 0) + wpos;
-                i2 = mbcnt(m2, 0) + (wpos + __popcll(m1));
-            } else {
-                i1 = mbcnt(m1, mbcnt(m2, 0)) + wpos;
-                i2 = i1 + 1;
-            }
-            ring_store<1>(m1, (i1 & (RD - 1)) | ringv, junkv, e2 ? x >> 8 : x);
-            ring_store<1>(m2, (i2 & (RD - 1)) | ringv, junkv, x);
-            x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
+            i1 = mbcnt(m1, mbcnt(m2, 0)) + wpos;
+            i2 = i1 + 1;
         }
+        ring_store<1>(m1, (i1 & (RD - 1)) | ringv, junkv, e2 ? x >> 8 : x);
+        ring_store<1>(m2, (i2 & (RD - 1)) | ringv, junkv, x);
+        x = e2 ? x >> 16 : (e1 ? x >> 8 : x);
     }
     // C(s, x) = M q + (x - q f) + cum = x + q (M - f) + cum, q = x / f by
     // one multiply-high (the entry's m, inc and shift); the 24-bit multiply
@@ -802,8 +801,8 @@ __device__ __forceinline__ void enc_step_esc(uint32_t& x, uint32_t& wpos, uint32
 // symbols of the next block leave the recent stores in flight.  BF: as in
 // enc_step.  ESC: escape coding, as in enc_step_esc; l_enc staged with the
 // escape (a 1 KiB block of 16-bit symbols still emits at most 2 KiB: 4
-// bytes per symbol).
-template <int R, int W, int NL, bool BF = false, bool ESC = false>
+// bytes per symbol).  ONE: as in enc_step (a one-digit table, byte digits).
+template <int R, int W, int NL, bool BF = false, bool ESC = false, bool ONE = false>
 __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk,
                                              uint32_t k, uint32_t l, uint32_t alphabet,
                                              const uint4* l_enc, uint8_t* slot, uint64_t slot_bytes,
@@ -857,7 +856,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
         if (ESC)
             enc_step_esc<R>(x, wpos, bad, l_enc[min(s, alphabet)], s, act, ringv, junkv);
         else
-            enc_step<R, BF>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], act, ringv, junkv);
+            enc_step<R, BF, false, ONE>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], act, ringv, junkv);
     }
     flush();  // the tail is shorter than a block: at most 2 windows
 
@@ -904,7 +903,7 @@ __device__ __forceinline__ void encode_chunk(const void* syms_base, uint64_t n, 
                     if (ESC)
                         enc_step_esc<R>(x, wpos, bad, ent[q], sy[q], live, ringv, junkv);
                     else
-                        enc_step<R, BF, NL == 64>(x, wpos, bad, ent[q], live, ringv, junkv);
+                        enc_step<R, BF, NL == 64, ONE>(x, wpos, bad, ent[q], live, ringv, junkv);
                 }
             }
             flush();

@@ -9,7 +9,7 @@ namespace {
 
 // Chunk indices come from a ticket in start order so that every look-back
 // only waits on chunks that are already running.
-template <int R, int W, int NL, bool BF, bool ESC>
+template <int R, int W, int NL, bool BF, bool ESC, bool ONE>
 __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, const PlaceArgs p)
 {
     // LDS: the waves' digit rings from address 0 (the kernel has no static
@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
         uint8_t* s0 = a.slots + uint64_t(chunk) * a.slot_stride;
         uint8_t* s1 = s0 + a.slot_stride;
         uint32_t x = 0, nd[2];
-        c64::encode_seg<R, W, BF>(a.syms, a.n, a.C, chunk, a.n_chunks, a.l, a.alphabet,
+        c64::encode_seg<R, W, BF, ONE>(a.syms, a.n, a.C, chunk, a.n_chunks, a.l, a.alphabet,
                                   reinterpret_cast<const uint4*>(tab), s0, s1, a.slot_bytes, ring, sbuf,
                                   a.status, &x, nd);
         // the lower chunk first: the upper one's look-back waits on it
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
         return;
     uint8_t* slot = a.slots + uint64_t(chunk) * a.slot_stride;
     uint32_t x = 0, nd = 0;
-    c64::encode_chunk<R, W, NL, BF, ESC>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
+    c64::encode_chunk<R, W, NL, BF, ESC, ONE>(a.syms, a.n, a.C, chunk, a.k, a.l, a.alphabet,
                                 reinterpret_cast<const uint4*>(tab), slot, a.slot_bytes, ring, sbuf,
                                 nullptr, nullptr, a.status,
                                 &x, &nd);
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(1024) k_encode64_place(const EncodeArgs a, con
                             slot + a.slot_bytes - uint64_t(c64::uni(nd)) * (R / 8), p, a.status);
 }
 
-template <int R, int W, int NL, bool BF, bool ESC = false>
+template <int R, int W, int NL, bool BF, bool ESC = false, bool ONE = false>
 hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
 {
     const uint32_t per = NL == 32 && !ESC ? 2 : 1;  // chunks per wave
@@ -78,7 +78,7 @@ hipError_t run_place(const EncodeArgs& a, const PlaceArgs& p, hipStream_t st)
     const uint32_t wpb = waves < 16 ? waves : 16;
     const uint32_t blocks = (waves + wpb - 1) / wpb;
     const uint32_t lds = enc_lds_bytes(a.enc_bytes, W) + wpb * c64::kEncWaveLds;
-    auto kern = k_encode64_place<R, W, NL, BF, ESC>;
+    auto kern = k_encode64_place<R, W, NL, BF, ESC, ONE>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess)
@@ -95,6 +95,11 @@ hipError_t run_n(const EncodeArgs& a, const PlaceArgs& p, int R, int W, hipStrea
     // 16-bit digits: one digit per step at most (b >= M), both orders coincide
     if (R == 16)
         return W == 1 ? run_place<16, 1, NL, false>(a, p, st) : run_place<16, 2, NL, false>(a, p, st);
+    // byte digits with a one-digit table: the single-digit step (both
+    // orders write the same bytes then)
+    if (a.one)
+        return W == 1 ? run_place<8, 1, NL, false, false, true>(a, p, st)
+                      : run_place<8, 2, NL, false, false, true>(a, p, st);
     if (a.bf)
         return W == 1 ? run_place<8, 1, NL, true>(a, p, st) : run_place<8, 2, NL, true>(a, p, st);
     return W == 1 ? run_place<8, 1, NL, false>(a, p, st) : run_place<8, 2, NL, false>(a, p, st);

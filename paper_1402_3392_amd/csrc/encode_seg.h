@@ -37,8 +37,9 @@ static_assert(2 * kSegRing == kEncRing && kSlotAlign % kSegWindow == 0 &&
 // offset (the count also covers the lower segment's emitting lanes, which
 // the offset takes back out).  Idle lanes keep their state through selects
 // on amask: the ballots are masked with it, so no per-lane predicate is
-// formed and no exec-mask branch splits the unrolled block.
-template <int R, bool BF, bool FULL>
+// formed and no exec-mask branch splits the unrolled block.  ONE: as in
+// enc_step (a one-digit table: no lane emits a second digit).
+template <int R, bool BF, bool FULL, bool ONE = false>
 __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32_t& bad, const uint4& e,
                                              uint64_t amask, uint32_t vhi, uint32_t segbase, uint32_t junkv)
 {
@@ -60,6 +61,15 @@ __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32
         const uint32_t pos = mbcnt(m, and_sv(wpos[1] - wpos[0] - lo, vhi)) + wpos[0];
         ring_store<2>(m, ((pos << 1) & (RB - 1)) | segbase, junkv, x);
         x = xs;
+    } else if (ONE) {
+        const bool e1 = x > e.y;
+        const uint64_t m1 = FULL ? ballot(e1) : ballot(e1) & am;
+        const uint32_t lo = __popc(static_cast<uint32_t>(m1)), hi = __popc(static_cast<uint32_t>(m1 >> 32));
+        wpos[0] -= lo;
+        wpos[1] -= hi;
+        const uint32_t i1 = mbcnt(m1, and_sv(wpos[1] - wpos[0] - lo, vhi)) + wpos[0];
+        ring_store<1>(m1, (i1 & (RB - 1)) | segbase, junkv, x);
+        x = FULL ? (e1 ? x >> 8 : x) : select_mask(m1, x, x >> 8);
     } else {
         // a lane that emits two digits also emits one: m2 is within m1
         const bool e1 = x > e.y, e2 = (x >> 8) > e.y;
@@ -98,8 +108,9 @@ __device__ __forceinline__ void enc_step_seg(uint32_t& x, uint32_t* wpos, uint32
 // count; slot1 is not touched when there is no second chunk.  l_enc: staged
 // encoder entries as for encode_chunk (alphabet + 1
 // entries; 256 with 8-bit symbols); ring, sbuf: this wave's digit ring and
-// symbol block, as for encode_chunk.  Arguments wave-uniform.
-template <int R, int W, bool BF>
+// symbol block, as for encode_chunk.  Arguments wave-uniform.  ONE: as in
+// enc_step_seg.
+template <int R, int W, bool BF, bool ONE = false>
 __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, uint32_t C, uint64_t chunk0,
                                            uint32_t n_chunks, uint32_t l, uint32_t alphabet,
                                            const uint4* l_enc, uint8_t* slot0,
@@ -207,7 +218,7 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
         for (int q = int(SPB) - 1; q >= 0; --q) {
             if (q - PF >= 0)
                 ent[q - PF] = entry(q - PF);
-            enc_step_seg<R, BF, decltype(full)::value>(x, wpos, bad, ent[q], amask, vhi, segbase, junkv);
+            enc_step_seg<R, BF, decltype(full)::value, ONE>(x, wpos, bad, ent[q], amask, vhi, segbase, junkv);
         }
     };
     int64_t b = int64_t(nb) - 1;
@@ -235,8 +246,8 @@ __device__ __forceinline__ void encode_seg(const void* syms_base, uint64_t n, ui
                 const uint32_t i = t * NL + jl;
                 const bool act = i < mynsym;
                 const uint32_t s = act ? static_cast<uint32_t>(gmem(myin)[i]) : 0u;
-                enc_step_seg<R, BF, false>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], ballot(act), vhi,
-                                           segbase, junkv);
+                enc_step_seg<R, BF, false, ONE>(x, wpos, bad, l_enc[W == 1 ? s : min(s, alphabet)], ballot(act),
+                                                vhi, segbase, junkv);
             }
         }
         flush();

@@ -43,6 +43,10 @@ struct DevTable {
     uint16_t* pfx_dec;
     uint32_t pfx_maxlen;
     uint64_t pfx_enc_bytes, pfx_dec_bytes;
+    // every f is 0 or at least M / 256: with byte digits (b = 2^8) no state
+    // moves two digits in one renormalisation (Algorithm 1's loop runs at
+    // most once), so coders may take the single-digit step
+    uint32_t one_digit;
 };
 
 // Encoder entry, one per symbol (uint4):
@@ -85,6 +89,7 @@ struct EncodeArgs {
     uint32_t alphabet;
     uint32_t bf;          // breadth-first digit order (Section 5)
     uint32_t esc;         // escape coding with raw digits (16-bit symbols)
+    uint32_t one;         // byte digits, a one-digit table, no escapes: single-digit steps
     const uint4* enc;     // alphabet + 1 entries
     uint32_t enc_bytes;   // multiple of 16
     uint8_t* slots;       // n_chunks slots, slot_stride apart
@@ -152,6 +157,7 @@ struct BatchJob {
     const void* tab_ent;
     const uint4* enc;      // encoder entries (alphabet + 1)
     uint32_t sym_bytes, ent_bytes, enc_bytes, alphabet;
+    uint32_t one;          // encode with byte digits and a one-digit table: single-digit steps
     // plan
     uint64_t n;            // symbols
     uint64_t total;        // encode: container length

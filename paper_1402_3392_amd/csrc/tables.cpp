@@ -188,6 +188,13 @@ extern "C" int rans_tables_build(const uint64_t* counts, uint32_t alphabet, uint
     DevTable d{};
     d.alphabet = alphabet;
     d.k = k;
+    // with b = 2^8 a state needs a second digit in one step only for a
+    // symbol with 0 < f < M / 256: after one digit it is below L, and L is
+    // at most the symbol's bound f b L / M exactly when f >= M / 256
+    d.one_digit = 1;
+    for (uint32_t s = 0; s < alphabet; ++s)
+        if (f[s] != 0 && f[s] < (M >> 8))
+            d.one_digit = 0;
     d.sym_w = sym_w;
     d.dec_bytes = pad16(uint64_t(M) * 4);
     d.sym_bytes = pad16(uint64_t(M) * sym_w);
