@@ -533,6 +533,7 @@ static int prepare_decode(const rans_table* table, const void* d_in, uint64_t in
     da->alphabet = t.alphabet;
     da->bf = h->p.digit_order;
     da->esc = h->p.escape;
+    da->one = h->p.radix_bits == 8 && !h->p.escape && !h->pfx && t.one_digit ? 1u : 0u;
     da->lut = d_lut;
     da->lut_w = lut_w;
     fill_decode_tables(t, *layout, da);

@@ -237,16 +237,29 @@ __global__ void __launch_bounds__(1024) k_batch_decode64(const BatchArgs a)
         const uint32_t c = c64::uni(((item - jb.item_base) * a.G + wave) * SEG);
         if (c < nch) {
             const uint32_t sym_bytes = c64::uni(jb.sym_bytes);
-            if constexpr (SEG == 1)
-                c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n,
-                                                            jb.out, a.k, a.l, tab,
-                                                            reinterpret_cast<const uint32_t*>(tab + sym_bytes),
-                                                            wave_lds, jb.d_status);
-            else
-                c64::decode_seg<R, W, SW, LAYOUT, NL, BF>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out,
-                                                          a.k, a.l, tab,
-                                                          reinterpret_cast<const uint32_t*>(tab + sym_bytes),
-                                                          wave_lds, jb.d_status);
+            auto code = [&](auto one) {
+                constexpr bool ONE = decltype(one)::value;
+                if constexpr (SEG == 1)
+                    c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, 0, false, false, ONE>(
+                        jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n, jb.out, a.k, a.l, tab,
+                        reinterpret_cast<const uint32_t*>(tab + sym_bytes), wave_lds, jb.d_status);
+                else
+                    c64::decode_seg<R, W, SW, LAYOUT, NL, BF, ONE>(jb.in, jb.in_len, nch, c, c64::uni(jb.C), jb.n,
+                                                                   jb.out, a.k, a.l, tab,
+                                                                   reinterpret_cast<const uint32_t*>(tab + sym_bytes),
+                                                                   wave_lds, jb.d_status);
+            };
+            // byte digits and a one-digit table: the single-byte refill
+            // (8-bit symbols only: a second inlined decoder cost the 16-bit
+            // symbol kernels 3%, and their tables rarely qualify)
+            if constexpr (R == 8 && W == 1) {
+                if (c64::uni(jb.one))
+                    code(std::true_type{});
+                else
+                    code(std::false_type{});
+            } else {
+                code(std::false_type{});
+            }
         }
     }
 }

@@ -221,7 +221,7 @@ __device__ __forceinline__ void stage2(uint8_t* lds, const void* a, uint32_t aby
 // entries symbol | length << 12); the end check compares the bits each lane
 // consumed with its count.
 template <int R, int W, int SW, int LAYOUT, int NL, bool BF = false, int LW = 0, bool ESC = false,
-          bool PFX = false>
+          bool PFX = false, bool ONE = false>
 __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                              uint64_t chunk, uint32_t C, uint64_t n, void* out_base,
                                              uint32_t k_, uint32_t l, const void* l_sym_v,
@@ -397,6 +397,13 @@ __device__ __forceinline__ void decode_chunk(const uint8_t* in, uint64_t in_len,
                 const uint16_t* rp = reinterpret_cast<const uint16_t*>(ring) + (pos & DMASK);
                 const uint32_t v = rp[mbcnt(m1, 0)];
                 x = select_mask(m1, x, (x << 16) | v);
+                pos += __popcll(m1);
+            }
+        } else if (ONE) {
+            // a one-digit table: no state falls below L / 256, one byte per
+            // refilling lane (both digit orders read the same bytes then)
+            if (dense || m1) {
+                x = select_mask(m1, x, (x << 8) | ring[(pos & DMASK) + mbcnt(m1, 0)]);
                 pos += __popcll(m1);
             }
         } else {

@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(1024) k_decode64(const DecodeArgs a)
 
 // Symbol output, rANS without escapes: 64 / NL chunks per wave (no lane
 // idles with N = 32), the decoder in decode_seg.h.
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, bool ONE>
 __global__ void __launch_bounds__(1024) k_decode64_seg(const DecodeArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -74,13 +74,13 @@ __global__ void __launch_bounds__(1024) k_decode64_seg(const DecodeArgs a)
         return;  // no barrier follows
     uint8_t* wave_lds = lds + wave * c64::seg_wave_lds_bytes(LAYOUT, NL);
     if constexpr (SEG == 1)
-        c64::decode_chunk<R, W, SW, LAYOUT, NL, BF>(a.in, a.in_len, a.n_chunks, chunk0, a.C, a.n, a.out, a.k,
-                                                    a.l, tab, reinterpret_cast<const uint32_t*>(tab + sym_bytes),
-                                                    wave_lds, a.status);
+        c64::decode_chunk<R, W, SW, LAYOUT, NL, BF, 0, false, false, ONE>(
+            a.in, a.in_len, a.n_chunks, chunk0, a.C, a.n, a.out, a.k, a.l, tab,
+            reinterpret_cast<const uint32_t*>(tab + sym_bytes), wave_lds, a.status);
     else
-        c64::decode_seg<R, W, SW, LAYOUT, NL, BF>(a.in, a.in_len, a.n_chunks, chunk0, a.C, a.n, a.out, a.k, a.l,
-                                                  tab, reinterpret_cast<const uint32_t*>(tab + sym_bytes), wave_lds,
-                                                  a.status);
+        c64::decode_seg<R, W, SW, LAYOUT, NL, BF, ONE>(a.in, a.in_len, a.n_chunks, chunk0, a.C, a.n, a.out, a.k,
+                                                       a.l, tab, reinterpret_cast<const uint32_t*>(tab + sym_bytes),
+                                                       wave_lds, a.status);
 }
 
 // Waves per block: 16 when the tables leave room for them, fewer otherwise.
@@ -101,7 +101,10 @@ hipError_t run(const DecodeArgs& a, hipStream_t st)
     const uint32_t blocks = (waves + wpb - 1) / wpb;
     const uint32_t lds = tabs + wpb * per;
     if constexpr (SEGK) {
-        auto kern = k_decode64_seg<R, W, SW, LAYOUT, NL, BF>;
+        // byte digits with a one-digit table: the single-byte refill (for
+        // either digit order: no lane reads a second byte)
+        auto kern = R == 8 && a.one ? k_decode64_seg<R, W, SW, LAYOUT, NL, BF, true>
+                                    : k_decode64_seg<R, W, SW, LAYOUT, NL, BF, false>;
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess)

@@ -96,7 +96,7 @@ __device__ __forceinline__ void wait_vm_atmost(uint32_t n)
 // container `in`; arguments as decode_chunk's (every one wave-uniform).
 // wave_lds: seg_wave_lds_bytes(LAYOUT, NL) bytes.  When it returns, every
 // memory operation it issued has completed.
-template <int R, int W, int SW, int LAYOUT, int NL, bool BF>
+template <int R, int W, int SW, int LAYOUT, int NL, bool BF, bool ONE = false>
 __device__ __forceinline__ void decode_seg(const uint8_t* in, uint64_t in_len, uint32_t n_chunks,
                                            uint64_t chunk0, uint32_t C, uint64_t n, void* out_base,
                                            uint32_t k_, uint32_t l, const void* l_sym_v,
@@ -283,6 +283,18 @@ __device__ __forceinline__ void decode_seg(const uint8_t* in, uint64_t in_len, u
                 const uint16_t* rp = reinterpret_cast<const uint16_t*>(wave_lds + OB) + (pos[0] & DMASK);
                 const uint32_t v = rp[mbcnt(m1, pos_off(lo1))];
                 x = select_mask(m1, x, (x << 16) | v);
+                if (SEG == 1) {
+                    pos[0] += lo1 + hi1;
+                } else {
+                    pos[0] += lo1;
+                    pos[SEG - 1] += hi1;
+                }
+            }
+        } else if (ONE) {
+            // a one-digit table: one byte per refilling lane
+            if (dense || m1) {
+                const uint8_t* r = wave_lds + OB + (pos[0] & DMASK);
+                x = select_mask(m1, x, (x << 8) | r[mbcnt(m1, pos_off(lo1))]);
                 if (SEG == 1) {
                     pos[0] += lo1 + hi1;
                 } else {

@@ -70,6 +70,7 @@ struct DecodeArgs {
     uint32_t bf;         // breadth-first digit order (Section 5)
     uint32_t esc;        // escape coding with raw digits (16-bit symbols)
     uint32_t pfx;        // prefix-code family (k = its longest code length)
+    uint32_t one;        // byte digits and a one-digit table: single-digit refills
     const void* lut;     // fused consumer: alphabet entries of lut_w bytes (device)
     uint32_t lut_w;      // 0 (symbol output), 2 or 4
     const void* tab0;    // kPacked: dec; kTwoLevel: sym

@@ -351,3 +351,41 @@ def test_byte_digit_steps_with_and_without_second_digits(lr, order):
     assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
     dec = gpu_decode(lr, table, ref, n, 1)
     assert (dec == syms).all(), first_diff(dec, syms)
+
+
+@pytest.mark.parametrize("N", [32, 64])
+@pytest.mark.parametrize("order", ["df", "bf"])
+def test_byte_digits_one_digit_table(lr, N, order):
+    """A table whose every nonzero f is at least M / 256 never needs two byte
+    digits in one step (b = 2^8), and the coders then take their single-digit
+    encode and refill paths: containers equal the oracle's in both digit
+    orders (which coincide here), and decode, through the single-buffer and
+    the batched kernels."""
+    from test_gpu_batch import run_decode_batch, run_encode_batch
+    k, r, l, C = 12, 8, 23, 8192
+    rng = np.random.Generator(np.random.PCG64(5150 + N))
+    syms = rng.integers(0, 16, 5 * C + 333, dtype=np.uint8)
+    counts = datagen.counts(syms, 256)
+    f_or = oracle.quantize(counts, k)
+    assert int(f_or[f_or > 0].min()) >= (1 << k) // 256
+    table = lr.rans_tables_build(counts, k)
+    print(f"[parity-one-digit] N={N} order={order}", flush=True)
+    ref = oracle.encode(f_or, syms, k, r, l, N, C, threads=4, order=order)
+    other = oracle.encode(f_or, syms, k, r, l, N, C, threads=4, order="bf" if order == "df" else "df")
+    assert (ref[32:] == other[32:]).all()  # one digit per step: the orders agree
+    got = gpu_encode(lr, table, (k, r, l, 1, N, C, order), syms)
+    assert got.size == ref.size and (got == ref).all(), first_diff(got, ref)
+    dec = gpu_decode(lr, table, ref, syms.size, 1)
+    assert (dec == syms).all(), first_diff(dec, syms)
+    data = [(syms, None), (syms[: 2 * C + 77].copy(), None)]
+    tables, outs, st, _ = run_encode_batch(lr, data, k, r, l, C, N=N, order=order)
+    assert (st == 0).all(), st
+    refs = [ref, oracle.encode(oracle.quantize(datagen.counts(data[1][0], 256), k),
+                               data[1][0], k, r, l, N, C, threads=4, order=order)]
+    for i in range(2):
+        assert outs[i].size == refs[i].size and (outs[i] == refs[i]).all(), (i, first_diff(outs[i], refs[i]))
+    sizes = [s.size for s, _ in data]
+    dec2, st2, n2 = run_decode_batch(lr, tables, refs, sizes, k, r, l, N=N, order=order)
+    assert (st2 == 0).all(), st2
+    for i, (s, _) in enumerate(data):
+        assert n2[i] == s.size and (dec2[i] == s).all(), i
